@@ -1,0 +1,153 @@
+/*
+ * pepsnet -- Block Belief Propagation (BlockBP) on kagome PEPS, MI355X (gfx950).
+ *
+ * C ABI of the HIP library libpepsnet.so.  The library computes the BlockBP
+ * message update of Eq. blockBP:DefiningEquation: a block of the double-layer
+ * (ket x bra) PEPS is contracted with its incoming MPS messages by the
+ * boundary-MPS method (Sec. "The boundary-MPS method") and compressed by QR
+ * and truncated SVD into outgoing bond-chi MPS messages; sweeps repeat this
+ * for every message (Alg. BlockBP_singleBlock for the infinite lattice, the
+ * defining equation on finite lattices) and local expectations <S_i . S_j>
+ * of the Heisenberg Hamiltonian (Eq. res:afm-h:hamiltonian) are computed from
+ * the converged messages.
+ *
+ * Conventions (part of the ABI):
+ *   - complex numbers are interleaved double pairs (re, im), C order;
+ *   - a site's ket tensor is t[p][l0][l1][l2][l3], physical dimension d, the
+ *     virtual legs ordered by bond angle counter-clockwise from +x
+ *     (DL: 0,60,180,240 deg; DR: 0,120,180,300 deg; U: 60,120,240,300 deg);
+ *     legs leaving a finite patch have dimension 1;
+ *   - tensor order: finite patch -- one tensor per site, sites ordered by
+ *     cell (row j outer, column i inner) then U, DL, DR inside a cell;
+ *     infinite lattice -- three tensors U, DL, DR (the 3-site unit cell);
+ *   - double legs fuse I = ket * D + bra; messages are MPS sites
+ *     A[l][I][r], legs in the receiving face's counter-clockwise order.
+ * Errors: every call returns BBP_OK (0), a positive warning (outputs valid)
+ * or a negative error; pepsnet_last_error() gives the thread-local text.
+ * Handles are not thread-safe; a handle owns all of its device memory.
+ */
+#ifndef PEPSNET_H
+#define PEPSNET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PEPSNET_ABI_VERSION 1
+
+typedef struct pepsnet_s* pepsnet_t;
+
+enum {
+  BBP_OK = 0,
+  BBP_NOT_CONVERGED = 1, /* warning: max_sweeps reached, outputs valid */
+  BBP_EINVAL = -1,       /* bad argument; nothing changed */
+  BBP_ENOMEM = -2,       /* device allocation failed */
+  BBP_EDEVICE = -3,      /* HIP runtime error */
+  BBP_ENUMERIC = -4,     /* NaN/Inf or zero trace in a result */
+  BBP_EGEOM = -5         /* geometry, tiling or sweep order could not be built */
+};
+
+typedef enum { BBP_KAGOME_OPEN = 1, BBP_KAGOME_INF_HEX = 2 } bbp_lattice;
+/* arithmetic of the contraction GEMMs (merge, double-layer absorption and
+ * the randomized sketches); QR, SVD and normalisation are always FP64 */
+typedef enum { BBP_FP64 = 0, BBP_FP32 = 1, BBP_BF16X3 = 2 } bbp_precision;
+/* truncated split: T1 exact SVD; T2 randomized range finder (Halko,
+ * Martinsson & Tropp 2011, Alg. 4.4) with a SplitMix64 sign sketch */
+typedef enum { BBP_SVD_FULL = 0, BBP_SVD_RAND = 1 } bbp_trunc;
+
+typedef struct {
+  int32_t abi_version;  /* PEPSNET_ABI_VERSION */
+  int32_t lattice;      /* bbp_lattice */
+  int32_t Lx, Ly;       /* BBP_KAGOME_OPEN: patch size in unit cells */
+  int32_t bLx, bLy;     /* BBP_KAGOME_OPEN: parallelogram block size in cells */
+  int32_t hex_N;        /* BBP_KAGOME_INF_HEX: face length N (>= 2), N_T = 3(3N^2-3N+1) */
+  int32_t d, D;         /* physical (2) and virtual bond dimension */
+  int32_t chi;          /* message bond dimension */
+  int32_t chi_env;      /* boundary-chain truncation; must equal chi */
+  int32_t precision;    /* bbp_precision */
+  int32_t trunc;        /* bbp_trunc */
+  int32_t rsvd_q;       /* T2 power iterations */
+  int32_t rsvd_p;       /* T2 oversampling */
+  uint64_t seed;        /* T2 sketch seed */
+  void* stream;         /* borrowed hipStream_t; NULL: the library creates one */
+} pepsnet_desc;
+
+/* Build the geometry and plans, allocate device memory and copy the site
+ * tensors (host pointer, complex128, see tensor order above; `sites_len` in
+ * doubles) to the device.  Messages start as vec(I_D)/sqrt(D) on every leg. */
+int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t sites_len,
+                       pepsnet_t* out);
+
+/* Replace the site tensors (same shapes); messages are kept (warm start)
+ * unless reset_messages != 0. */
+int32_t pepsnet_set_sites(pepsnet_t h, const double* sites, int64_t sites_len,
+                          int32_t reset_messages);
+
+/* Run Jacobi sweeps: every message is recomputed from the previous sweep's
+ * messages.  Stops after max_sweeps or when the largest Frobenius distance
+ * between a message and its previous value (both unit norm, real positive
+ * trace) is <= tol.  Returns BBP_NOT_CONVERGED if tol was not reached. */
+int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
+                      double* max_err);
+
+/* Two-site reduced density matrices and <S_i . S_j> for the default bonds:
+ * the six unique bonds of the central unit cell (infinite lattice: U-DL,
+ * U-DR, DL-DR, DR-DL(a1), U-DL(a2), U-DR(a2-a1)) or every bond of a finite
+ * patch (ordered by first site then slot).  rho_out: n_bonds x 4 x 4 complex
+ * (row (p_i p_j), column (p_i' p_j'), NULL to skip); ss_out: n_bonds doubles;
+ * energy: energy per site ((1/3) sum of the six unique bonds; infinite
+ * lattice only, else the mean bond energy).  n_bonds_out receives the count. */
+int32_t blockbp_expect(pepsnet_t h, double* rho_out, double* ss_out, double* energy,
+                       int32_t* n_bonds_out);
+
+/* Number of default bonds and their site pairs (2 ints per bond). */
+int32_t pepsnet_bonds(pepsnet_t h, int32_t* pairs, int32_t cap, int32_t* n);
+
+/* Copy the current messages to host (complex128, each message's sites in
+ * order, every site zero-padded to its static shape).  With buf NULL only
+ * *len (doubles) is set. */
+int32_t pepsnet_get_messages(pepsnet_t h, double* buf, int64_t cap, int64_t* len);
+int32_t pepsnet_set_messages(pepsnet_t h, const double* buf, int64_t len);
+
+/* Static shape of message slot m site j: (bond left, double-leg dim, bond right). */
+int32_t pepsnet_message_shape(pepsnet_t h, int32_t m, int32_t j, int32_t* l, int32_t* P,
+                              int32_t* r, int32_t* n_sites);
+int32_t pepsnet_num_messages(pepsnet_t h);
+
+/* Stream that the handle launches on (hipStream_t). */
+void* pepsnet_stream(pepsnet_t h);
+
+/* Time the last sweep's kernels with HIP events on the handle's stream:
+ * average milliseconds per sweep over the sweeps run since the last reset. */
+int32_t pepsnet_timing(pepsnet_t h, int32_t reset, double* ms_per_sweep, int64_t* sweeps);
+
+/* Use a captured HIP graph for sweeps (1) or direct launches (0). */
+int32_t pepsnet_use_graph(pepsnet_t h, int32_t on);
+
+/* Algorithmic flop count of one sweep's contraction GEMMs (8 real flops per
+ * complex multiply-add) and of all its GEMMs, and the number of launches. */
+int32_t pepsnet_sweep_stats(pepsnet_t h, double* contraction_flops, double* gemm_flops,
+                            int64_t* launches);
+
+void pepsnet_destroy(pepsnet_t h);
+const char* pepsnet_last_error(void);
+
+/* Host-only geometry queries (no device use), for checking the sweep orders
+ * against an independent implementation.
+ *   what = 0: faces of block `a`: [n_faces, {keytype, key, n_legs, (site, slot)...}...]
+ *   what = 1: sweep of block `a` toward face `b` with open sites:
+ *             [n_steps, {site, pos, r, s, in_slots[r], out_slots[s], open, absorb}...,
+ *              n_final, (site, slot)...]
+ *   what = 2: summary [n_sites, n_blocks, n_msgs, n_bonds]
+ * buf receives up to cap int32 values; *len gets the needed length. */
+int32_t pepsnet_describe(const pepsnet_desc* desc, int32_t what, int32_t a, int32_t b,
+                         int32_t n_open, const int32_t* open_sites, int32_t* buf, int64_t cap,
+                         int64_t* len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEPSNET_H */

@@ -12,7 +12,10 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__``).
 * Initial messages: normalised identity vec(I_D)/sqrt(D) on every leg (a
   positive semi-definite start, Sec. "Introduction to Belief-Propagation").
 * Messages are stored right-canonical with unit norm, legs in the receiving
-  face's counter-clockwise order, and with real positive trace as operators
+  face's counter-clockwise order, every bond zero-padded to the static
+  dimension min(chi, product of double-leg dimensions on either side) (the
+  represented tensor is unchanged; fixed shapes also fix the T2 sketch
+  layout), and with real positive trace as operators
   (ket legs rows, bra legs columns).  The update fixes a message only up to a
   complex phase; a positive semi-definite message has positive trace, and
   without this convention a round-off phase is multiplied by the number of
@@ -60,8 +63,8 @@ class BlockBP:
         for key in prob.msg_keys:
             skey = self._store_key(key)
             legs = self._recv_legs(skey)
-            self.msgs[skey] = [identity_vec(self._dim(s, l)).reshape(1, -1, 1)
-                               for (s, l) in legs]
+            ident = [identity_vec(self._dim(s, l)).reshape(1, -1, 1) for (s, l) in legs]
+            self.msgs[skey] = self._pad_to_caps(ident, legs)
 
     # ---------------------------------------------------------- bookkeeping
     def _dim(self, s, l):
@@ -76,6 +79,30 @@ class BlockBP:
             return P.faces[0][skey]["legs"]
         a, b = skey
         return P.faces[b][P.face_index(b, ("block", a))]["legs"]
+
+    def _caps(self, legs):
+        """Static bond dimensions of a message on ``legs``: bond j is
+        min(chi, prod of double-leg dims left of it, prod right of it)."""
+        pd = [self._dim(s, l) ** 2 for (s, l) in legs]
+        caps = [1]
+        for j in range(1, len(pd)):
+            caps.append(min(self.chi, int(np.prod(pd[:j])), int(np.prod(pd[j:]))))
+        caps.append(1)
+        return caps
+
+    def _pad_to_caps(self, A, legs):
+        """Zero-pad every bond of a message to its static dimension (the
+        represented tensor is unchanged)."""
+        caps = self._caps(legs)
+        out = []
+        for j, x in enumerate(A):
+            l, P, r = x.shape
+            if l > caps[j] or r > caps[j + 1]:
+                raise ValueError("message bond above its static dimension")
+            y = np.zeros((caps[j], P, caps[j + 1]), complex)
+            y[:l, :, :r] = x
+            out.append(y)
+        return out
 
     def _incoming(self, b, face):
         P = self.prob
@@ -121,7 +148,9 @@ class BlockBP:
         ch.legdim = dims
         return ch
 
-    def run_sweep(self, b, face, open_sites=(), override=None, tags=(0, 0, 0)):
+    def run_sweep(self, b, face, open_sites=(), override=None, tags=(0, 0, 0), last_tag=0):
+        """Sketch keys of T2 splits: SplitMix64 stream keys over the tags
+        (purpose, index, sub-sweep, step, split, last_tag)."""
         steps, final = self.schedule(b, face, open_sites)
         ch = self.initial_chain(b, face, override)
         P = self.prob
@@ -129,7 +158,7 @@ class BlockBP:
             t = self.tensors[P.net.sites[st["site"]]["tensor"]]
 
             def keyfn(m, n=n):
-                return _rng.stream_key(self.seed, list(tags) + [n, m])
+                return _rng.stream_key(self.seed, list(tags) + [n, m, last_tag])
 
             bb.swallow(ch, st, t, self.chi_env, self.trunc, self.q, self.p, keyfn)
         return ch, final
@@ -138,8 +167,10 @@ class BlockBP:
         """New message for ``key`` (unit norm, right-canonical, storage order)."""
         P = self.prob
         a, fa, recv = P.update_target(key)
-        tags = (PURPOSE_MSG, self.msg_index(key), self.sweeps_done)
-        ch, final = self.run_sweep(a, fa, tags=tags)
+        # sketch keys are the same at every sweep, so the truncated update is
+        # one fixed map whose fixed point BlockBP can reach
+        tags = (PURPOSE_MSG, self.msg_index(key), 0)
+        ch, final = self.run_sweep(a, fa, tags=tags, last_tag=0)
         if final == list(recv):
             A = ch.A
         elif final == list(recv)[::-1]:
@@ -152,10 +183,11 @@ class BlockBP:
         A = out.A
         if max(x.shape[2] for x in A) > self.chi:
             A = bb.compress(A, self.chi)
+        legs = self._recv_legs(self._store_key(key))
+        A = self._pad_to_caps(A, legs)
         # unit norm alone leaves the message's global phase free; round-off
         # in it is amplified by the sweep, so fix the trace real positive
-        return bb.fix_phase(A, [self._dim(s, l) for (s, l) in
-                                self._recv_legs(self._store_key(key))])
+        return bb.fix_phase(A, [self._dim(s, l) for (s, l) in legs])
 
     def sweep(self):
         new = {}

@@ -17,8 +17,13 @@ by SVD and the new bond is truncated to at most chi.  Supporting readings:
 * A chain site is a tensor A[l, P, r]; its leg P fuses (ket, bra, carried...)
   row-major, with ket/bra of dimension D_leg each (double leg, I = k*D + b)
   and each carried factor d*d (physical pair p*d + p' of an open site).
+* Canonical gauge: QR factors carry a real non-negative R diagonal and the
+  left factor of every split has, in each column, its largest-modulus entry
+  real positive.  No represented tensor changes; the gauge makes every bond
+  basis unique, which the randomized sketch (applied on a bond index) needs.
 * Truncation keeps exactly min(chi, rank) values -- with rank = min(rows,
-  cols) -- and no relative cutoff.  ``trunc="T1"``: full SVD.
+  cols) -- and no relative cutoff.  Splits whose kept and dropped singular
+  values are degenerate are recorded in ``DEGENERATE`` (ambiguous cut).  ``trunc="T1"``: full SVD.
   ``trunc="T2"``: randomized range finder with q power iterations and p
   oversampling (Halko, Martinsson & Tropp 2011, Alg. 4.4) followed by an exact
   SVD of the projected matrix; the sketch comes from ``oracle.rng``.  T2 falls
@@ -44,16 +49,66 @@ class Chain:
         return len(self.A)
 
 
+# Splits whose kept and discarded singular values are degenerate to within
+# DEGENERATE_TOL * sigma_1 (the truncation is then ambiguous); tests read and
+# reset this list to exclude such results from parity checks.
+DEGENERATE = []
+DEGENERATE_TOL = 1e-8
+# Splits whose kept singular values contain a degenerate non-zero pair: the
+# new bond's basis is then a free rotation, which a later randomized sketch
+# (applied on that bond) sees; T2 results after such a split are not unique.
+GAUGE_AMBIGUOUS = []
+
+
+def _record(S, keep, rows, cols):
+    if len(S) == 0 or S[0] == 0:
+        return
+    if keep < len(S) and S[keep - 1] - S[keep] < DEGENERATE_TOL * S[0] \
+            and S[keep - 1] > DEGENERATE_TOL * S[0]:
+        DEGENERATE.append((rows, cols, keep))
+    kept = S[:keep]
+    big = kept > DEGENERATE_TOL * S[0]
+    gaps = kept[:-1][big[1:]] - kept[1:][big[1:]]
+    if np.any(gaps < DEGENERATE_TOL * S[0]):
+        GAUGE_AMBIGUOUS.append((rows, cols, keep))
+
+
 def _qr(M):
     Q, R = np.linalg.qr(M, mode="reduced")
     return Q, R
+
+
+def qr_pos(M):
+    """Reduced QR with the diagonal of R real and non-negative: a unique
+    factorisation for full column rank (canonical gauge of the new bond)."""
+    Q, R = np.linalg.qr(M, mode="reduced")
+    d = np.diag(R)
+    ph = np.ones(len(d), complex)
+    nz = np.abs(d) > 0
+    ph[nz] = d[nz] / np.abs(d[nz])
+    return Q * ph[None, :], R * ph.conj()[:, None]
+
+
+def fix_columns(L, R):
+    """Canonical gauge of a split bond: each column of L gets its entry of
+    largest modulus (first one on ties) real and positive; R's rows follow."""
+    L = L.copy()
+    R = R.copy()
+    for j in range(L.shape[1]):
+        i = int(np.argmax(L[:, j].real ** 2 + L[:, j].imag ** 2))
+        a = abs(L[i, j])
+        if a > 0:
+            ph = L[i, j] / a
+            L[:, j] *= np.conj(ph)
+            R[j, :] *= ph
+    return L, R
 
 
 def move_right(ch, j):
     """Left-canonicalise site j and push the remainder into site j+1."""
     A = ch.A[j]
     l, P, r = A.shape
-    Q, R = _qr(A.reshape(l * P, r))
+    Q, R = qr_pos(A.reshape(l * P, r))
     ch.A[j] = Q.reshape(l, P, Q.shape[1])
     ch.A[j + 1] = np.tensordot(R, ch.A[j + 1], axes=([1], [0]))
 
@@ -63,7 +118,7 @@ def move_left(ch, j):
     A = ch.A[j]
     l, P, r = A.shape
     # A = L Q with Q having orthonormal rows: QR of A^H
-    Q, R = _qr(A.reshape(l, P * r).conj().T)
+    Q, R = qr_pos(A.reshape(l, P * r).conj().T)
     k = Q.shape[1]
     ch.A[j] = Q.conj().T.reshape(k, P, r)
     ch.A[j - 1] = np.tensordot(ch.A[j - 1], R.conj().T, axes=([2], [0]))
@@ -87,7 +142,8 @@ def truncated_split(M, chi, trunc="T1", q=2, p=8, key=None):
     keep = full if chi <= 0 else min(chi, full)
     if trunc == "T1" or chi <= 0 or chi + p >= full:
         U, S, Vh = np.linalg.svd(M, full_matrices=False)
-        return U[:, :keep], S[:keep, None] * Vh[:keep]
+        _record(S, keep, rows, cols)
+        return fix_columns(U[:, :keep], S[:keep, None] * Vh[:keep])
     k = chi + p
     Om = _rng.sign_matrix(key, cols, k)
     Y = M @ Om
@@ -99,7 +155,8 @@ def truncated_split(M, chi, trunc="T1", q=2, p=8, key=None):
     Q, _ = _qr(Y)
     B = Q.conj().T @ M
     Ub, S, Vh = np.linalg.svd(B, full_matrices=False)
-    return Q @ Ub[:, :keep], S[:keep, None] * Vh[:keep]
+    _record(S, keep, rows, cols)
+    return fix_columns(Q @ Ub[:, :keep], S[:keep, None] * Vh[:keep])
 
 
 def _unfuse_dims(ch, j):

@@ -1,0 +1,213 @@
+"""ctypes binding of libpepsnet.so (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts numpy
+arrays to the C ABI of ``include/pepsnet.h`` and back.  Loading fails loudly
+if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+BBP_KAGOME_OPEN, BBP_KAGOME_INF_HEX = 1, 2
+BBP_FP64, BBP_FP32, BBP_BF16X3 = 0, 1, 2
+BBP_SVD_FULL, BBP_SVD_RAND = 0, 1
+ABI_VERSION = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class PepsnetError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pepsnet error {code}: {msg}")
+        self.code = code
+
+
+class Desc(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("lattice", C.c_int32),
+                ("Lx", C.c_int32), ("Ly", C.c_int32), ("bLx", C.c_int32), ("bLy", C.c_int32),
+                ("hex_N", C.c_int32), ("d", C.c_int32), ("D", C.c_int32),
+                ("chi", C.c_int32), ("chi_env", C.c_int32), ("precision", C.c_int32),
+                ("trunc", C.c_int32), ("rsvd_q", C.c_int32), ("rsvd_p", C.c_int32),
+                ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+def library_path():
+    return os.path.join(_HERE, "libpepsnet.so")
+
+
+def load_library():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2603_13304_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    i32, i64, dbl, vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    P = C.POINTER
+    sig = {
+        "pepsnet_create": (i32, [P(Desc), P(dbl), i64, P(vp)]),
+        "pepsnet_set_sites": (i32, [vp, P(dbl), i64, i32]),
+        "blockbp_sweep": (i32, [vp, i32, dbl, P(i32), P(dbl)]),
+        "blockbp_expect": (i32, [vp, P(dbl), P(dbl), P(dbl), P(i32)]),
+        "pepsnet_bonds": (i32, [vp, P(i32), i32, P(i32)]),
+        "pepsnet_get_messages": (i32, [vp, P(dbl), i64, P(i64)]),
+        "pepsnet_set_messages": (i32, [vp, P(dbl), i64]),
+        "pepsnet_message_shape": (i32, [vp, i32, i32, P(i32), P(i32), P(i32), P(i32)]),
+        "pepsnet_num_messages": (i32, [vp]),
+        "pepsnet_stream": (vp, [vp]),
+        "pepsnet_timing": (i32, [vp, i32, P(dbl), P(i64)]),
+        "pepsnet_use_graph": (i32, [vp, i32]),
+        "pepsnet_sweep_stats": (i32, [vp, P(dbl), P(dbl), P(i64)]),
+        "pepsnet_destroy": (None, [vp]),
+        "pepsnet_last_error": (C.c_char_p, []),
+        "pepsnet_describe": (i32, [P(Desc), i32, i32, i32, i32, P(i32), P(i32), i64, P(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise PepsnetError(rc, _LIB.pepsnet_last_error().decode())
+    return rc
+
+
+def make_desc(lattice, D, chi, Lx=0, Ly=0, bLx=0, bLy=0, hex_N=0, chi_env=None,
+              precision=BBP_FP64, trunc=BBP_SVD_FULL, q=2, p=8, seed=0, stream=None, d=2):
+    return Desc(ABI_VERSION, lattice, Lx, Ly, bLx, bLy, hex_N, d, D, chi,
+                chi if chi_env is None else chi_env, precision, trunc, q, p, seed,
+                stream if stream is None else C.c_void_p(stream))
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _flatten_sites(tensors):
+    return np.ascontiguousarray(np.concatenate(
+        [np.ascontiguousarray(t, dtype=np.complex128).reshape(-1) for t in tensors])).view(np.float64)
+
+
+def describe(desc, what, a=0, b=0, open_sites=()):
+    lib = load_library()
+    op = np.asarray(open_sites, dtype=np.int32)
+    n = C.c_int64(0)
+    _check(lib.pepsnet_describe(C.byref(desc), what, a, b, len(op),
+                                op.ctypes.data_as(C.POINTER(C.c_int32)), None, 0, C.byref(n)))
+    buf = np.zeros(max(n.value, 1), np.int32)
+    _check(lib.pepsnet_describe(C.byref(desc), what, a, b, len(op),
+                                op.ctypes.data_as(C.POINTER(C.c_int32)),
+                                buf.ctypes.data_as(C.POINTER(C.c_int32)), n.value, C.byref(n)))
+    return buf[:n.value]
+
+
+class PepsNet:
+    """Handle over ``pepsnet_t``: pepsnet_create / blockbp_sweep /
+    blockbp_expect with numpy in and out."""
+
+    def __init__(self, desc, tensors):
+        self.lib = load_library()
+        self.desc = desc
+        self._sites = _flatten_sites(tensors)
+        h = C.c_void_p()
+        _check(self.lib.pepsnet_create(C.byref(desc), _dptr(self._sites), self._sites.size,
+                                       C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pepsnet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_sites(self, tensors, reset_messages=False):
+        s = _flatten_sites(tensors)
+        _check(self.lib.pepsnet_set_sites(self.h, _dptr(s), s.size, int(reset_messages)))
+
+    def blockbp_sweep(self, max_sweeps, tol=0.0):
+        done, err = C.c_int32(0), C.c_double(0.0)
+        rc = _check(self.lib.blockbp_sweep(self.h, max_sweeps, tol, C.byref(done), C.byref(err)))
+        return done.value, err.value, rc
+
+    def blockbp_expect(self):
+        n = C.c_int32(0)
+        _check(self.lib.pepsnet_bonds(self.h, None, 0, C.byref(n)))
+        nb = n.value
+        rho = np.zeros(nb * 32, np.float64)
+        ss = np.zeros(nb, np.float64)
+        e = C.c_double(0.0)
+        _check(self.lib.blockbp_expect(self.h, _dptr(rho), _dptr(ss), C.byref(e), C.byref(n)))
+        return rho.view(np.complex128).reshape(nb, 4, 4), ss, e.value
+
+    def bonds(self):
+        n = C.c_int32(0)
+        _check(self.lib.pepsnet_bonds(self.h, None, 0, C.byref(n)))
+        buf = np.zeros(2 * n.value, np.int32)
+        _check(self.lib.pepsnet_bonds(self.h, buf.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      buf.size, C.byref(n)))
+        return [tuple(x) for x in buf.reshape(-1, 2)]
+
+    def num_messages(self):
+        return self.lib.pepsnet_num_messages(self.h)
+
+    def message_shapes(self, m):
+        l, P, r, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        _check(self.lib.pepsnet_message_shape(self.h, m, -1, None, None, None, C.byref(n)))
+        out = []
+        for j in range(n.value):
+            _check(self.lib.pepsnet_message_shape(self.h, m, j, C.byref(l), C.byref(P),
+                                                  C.byref(r), C.byref(n)))
+            out.append((l.value, P.value, r.value))
+        return out
+
+    def get_messages(self):
+        """List (per message slot) of lists of site arrays [l, P, r]."""
+        n = C.c_int64(0)
+        _check(self.lib.pepsnet_get_messages(self.h, None, 0, C.byref(n)))
+        buf = np.zeros(n.value, np.float64)
+        _check(self.lib.pepsnet_get_messages(self.h, _dptr(buf), buf.size, C.byref(n)))
+        z = buf.view(np.complex128)
+        out, o = [], 0
+        for m in range(self.num_messages()):
+            sites = []
+            for (l, P, r) in self.message_shapes(m):
+                sites.append(z[o:o + l * P * r].reshape(l, P, r).copy())
+                o += l * P * r
+            out.append(sites)
+        return out
+
+    def set_messages(self, msgs):
+        flat = np.concatenate([np.ascontiguousarray(x, np.complex128).reshape(-1)
+                               for sites in msgs for x in sites]).view(np.float64)
+        _check(self.lib.pepsnet_set_messages(self.h, _dptr(flat), flat.size))
+
+    def stream(self):
+        return self.lib.pepsnet_stream(self.h)
+
+    def timing(self, reset=False):
+        ms, n = C.c_double(0.0), C.c_int64(0)
+        _check(self.lib.pepsnet_timing(self.h, int(reset), C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def use_graph(self, on=True):
+        _check(self.lib.pepsnet_use_graph(self.h, int(on)))
+
+    def sweep_stats(self):
+        cf, gf, nl = C.c_double(0.0), C.c_double(0.0), C.c_int64(0)
+        _check(self.lib.pepsnet_sweep_stats(self.h, C.byref(cf), C.byref(gf), C.byref(nl)))
+        return cf.value, gf.value, nl.value

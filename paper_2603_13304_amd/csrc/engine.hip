@@ -1,0 +1,771 @@
+// Executor and C ABI of the BlockBP engine (see include/pepsnet.h).
+//
+// A compiled plan (plan.hpp) is resolved into batched descriptor tables on
+// the device: ops of all lanes are sorted by their wave key, every wave's
+// ops are bucketed by kernel, and each bucket becomes one launch whose grid
+// spans all its items.  A sweep is therefore a fixed list of launches that
+// can be replayed directly or captured once into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pepsnet.h"
+#include "geometry.hpp"
+#include "kernels.hip"
+#include "plan.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define PN_HIP(call)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(BBP_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+using namespace pn;
+
+struct LaunchRec {
+  int type = 0;
+  int prec = 0;
+  size_t desc_off = 0;   // byte offset into the descriptor blob
+  int count = 0;
+  dim3 grid;
+  size_t lds = 0;
+  double gemm_flops = 0.0, contraction_flops = 0.0;
+};
+
+struct Compiled {
+  std::vector<LaunchRec> launches;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  double gemm_flops = 0.0, contraction_flops = 0.0;
+};
+
+}  // namespace
+
+struct pepsnet_s {
+  Problem P;
+  PlanOptions opt;
+  std::unique_ptr<Compiler> comp;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  cplx* arena = nullptr;
+  int64_t arena_len = 0;
+  double* scal = nullptr;
+  std::vector<int64_t> region_base;
+  char* desc_dev = nullptr;
+  std::vector<char> desc_host;
+  Compiled prep, sweep[2], expect[2];
+  std::vector<std::vector<int>> carry_order[2];
+  std::vector<int64_t> rho_off[2];
+  std::vector<std::pair<int, int>> bonds;
+  RhoDesc* rho_descs[2] = {nullptr, nullptr};
+  cplx* rho_mat = nullptr;
+  double* ss_dev = nullptr;
+  int parity = 0;
+  int64_t sweeps_total = 0;
+  bool use_graph = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double timed_ms = 0.0;
+  int64_t timed_sweeps = 0;
+  int64_t site_len = 0;
+  double* pinned = nullptr;   // host pinned: [0] sweep counter, [1..] distances
+};
+
+namespace {
+
+cplx* resolve(pepsnet_s* h, const Ref& r) {
+  if (!r.valid()) return nullptr;
+  return h->arena + h->region_base[r.region] + r.off;
+}
+
+template <class T>
+size_t push_descs(std::vector<char>* blob, const std::vector<T>& v) {
+  size_t off = (blob->size() + 255) / 256 * 256;
+  blob->resize(off + v.size() * sizeof(T));
+  std::memcpy(blob->data() + off, v.data(), v.size() * sizeof(T));
+  return off;
+}
+
+void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, Op>>>& lanes,
+                 Compiled* out) {
+  // (wave key, lane, op index)
+  std::vector<std::tuple<WaveKey, int, int>> all;
+  for (size_t L = 0; L < lanes.size(); ++L)
+    for (size_t k = 0; k < lanes[L].size(); ++k) all.emplace_back(lanes[L][k].first, int(L), int(k));
+  std::stable_sort(all.begin(), all.end(), [](const auto& a, const auto& b) {
+    return std::get<0>(a) < std::get<0>(b);
+  });
+  size_t i = 0;
+  while (i < all.size()) {
+    size_t j = i;
+    while (j < all.size() && !(std::get<0>(all[i]) < std::get<0>(all[j])) &&
+           !(std::get<0>(all[j]) < std::get<0>(all[i])))
+      ++j;
+    std::map<std::pair<int, int>, std::vector<const Op*>> buckets;
+    for (size_t t = i; t < j; ++t) {
+      const Op& op = lanes[std::get<1>(all[t])][std::get<2>(all[t])].second;
+      int prec = op.type == OPK_GEMM ? int(op.i[8]) : 0;
+      buckets[{op.type, prec}].push_back(&op);
+    }
+    for (auto& bk : buckets) {
+      LaunchRec rec;
+      rec.type = bk.first.first;
+      rec.prec = bk.first.second;
+      rec.count = int(bk.second.size());
+      const auto& ops = bk.second;
+      switch (rec.type) {
+        case OPK_GEMM: {
+          std::vector<GemmDesc> v;
+          int64_t mM = 1, mN = 1;
+          for (const Op* op : ops) {
+            GemmDesc g;
+            g.A = resolve(h, op->a); g.B = resolve(h, op->b); g.C = resolve(h, op->c);
+            g.M = int(op->i[0]); g.N = int(op->i[1]); g.K = int(op->i[2]);
+            g.lda = int(op->i[3]); g.ldb = int(op->i[4]); g.ldc = int(op->i[5]);
+            g.opA = int(op->i[6]); g.opB = int(op->i[7]);
+            g.alpha = cplx{op->x[0], op->x[1]};
+            g.beta = cplx{op->x[2], op->x[3]};
+            mM = std::max<int64_t>(mM, g.M);
+            mN = std::max<int64_t>(mN, g.N);
+            double f = 8.0 * double(g.M) * double(g.N) * double(g.K);
+            rec.gemm_flops += f;
+            if (op->i[9]) rec.contraction_flops += f;
+            v.push_back(g);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned((mN + 63) / 64), unsigned((mM + 63) / 64), unsigned(v.size()));
+          break;
+        }
+        case OPK_PERM: {
+          std::vector<PermDesc> v;
+          int64_t mt = 1;
+          for (const Op* op : ops) {
+            PermDesc p;
+            std::memset(&p, 0, sizeof p);
+            p.src = resolve(h, op->a); p.dst = resolve(h, op->b);
+            p.rank = int(op->i[0]); p.conj = int(op->i[1]);
+            p.total = 1;
+            for (int k = 0; k < p.rank; ++k) {
+              p.dims[k] = int(op->i[2 + k]);
+              p.stride[k] = op->i[18 + k];
+              p.total *= p.dims[k];
+            }
+            mt = std::max(mt, p.total);
+            v.push_back(p);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(std::min<int64_t>(4096, (mt + 255) / 256)), unsigned(v.size()));
+          break;
+        }
+        case OPK_QR: {
+          std::vector<QrDesc> v;
+          for (const Op* op : ops) {
+            QrDesc q;
+            q.A = resolve(h, op->a); q.work = resolve(h, op->b);
+            q.Q = resolve(h, op->c); q.R = resolve(h, op->d);
+            q.m = int(op->i[0]); q.n = int(op->i[1]); q.lda = int(op->i[2]); q.conjT = int(op->i[3]);
+            v.push_back(q);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(v.size()));
+          break;
+        }
+        case OPK_JACOBI: {
+          std::vector<JacobiDesc> v;
+          int klds = 0;
+          for (const Op* op : ops) {
+            JacobiDesc jd;
+            jd.R = resolve(h, op->a); jd.work = resolve(h, op->b); jd.V = resolve(h, op->c);
+            jd.sigma = reinterpret_cast<double*>(resolve(h, op->d));
+            jd.k = int(op->i[0]);
+            if (jd.k <= JAC_LDS_MAX) klds = std::max(klds, jd.k);
+            v.push_back(jd);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(v.size()));
+          rec.lds = size_t(2) * klds * klds * sizeof(cplx);
+          break;
+        }
+        case OPK_OMEGA: {
+          std::vector<OmegaDesc> v;
+          int64_t mt = 1;
+          for (const Op* op : ops) {
+            OmegaDesc o;
+            o.out = resolve(h, op->a);
+            o.n = int(op->i[0]); o.k = int(op->i[1]);
+            o.prefix = op->key;
+            o.last_tag = op->i[2] ? h->scal + Compiler::kSweepSlot : nullptr;
+            mt = std::max<int64_t>(mt, int64_t(o.n) * o.k);
+            v.push_back(o);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(std::min<int64_t>(1024, (mt + 255) / 256)), unsigned(v.size()));
+          break;
+        }
+        case OPK_NORM: {
+          std::vector<NormDesc> v;
+          for (const Op* op : ops) {
+            NormDesc nd;
+            nd.x = resolve(h, op->a);
+            nd.len = op->i[0];
+            nd.logscale = op->s0.off >= 0 ? h->scal + op->s0.off : nullptr;
+            nd.norm_out = op->s1.off >= 0 ? h->scal + op->s1.off : nullptr;
+            v.push_back(nd);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(v.size()));
+          break;
+        }
+        case OPK_PAD: {
+          std::vector<PadDesc> v;
+          int64_t mt = 1;
+          for (const Op* op : ops) {
+            PadDesc p;
+            p.src = resolve(h, op->a); p.dst = resolve(h, op->b);
+            p.l1 = int(op->i[0]); p.P = int(op->i[1]); p.r1 = int(op->i[2]);
+            p.l2 = int(op->i[3]); p.r2 = int(op->i[4]);
+            p.off_l = int(op->i[5]); p.off_r = int(op->i[6]); p.mode = int(op->i[7]);
+            p.sign = op->x[0];
+            mt = std::max<int64_t>(mt, int64_t(p.l2) * p.P * p.r2);
+            v.push_back(p);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(std::min<int64_t>(4096, (mt + 255) / 256)), unsigned(v.size()));
+          break;
+        }
+        case OPK_COLPHASE: {
+          std::vector<ColPhaseDesc> v;
+          for (const Op* op : ops) {
+            ColPhaseDesc c;
+            c.L = resolve(h, op->a); c.R = resolve(h, op->b);
+            c.m = int(op->i[0]); c.keep = int(op->i[1]); c.n = int(op->i[2]);
+            v.push_back(c);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(v.size()));
+          break;
+        }
+        case OPK_PHASE: {
+          std::vector<PhaseDesc> v;
+          for (const Op* op : ops) {
+            PhaseDesc p;
+            std::memset(&p, 0, sizeof p);
+            p.nsites = int(op->i[0]);
+            for (int s = 0; s < p.nsites; ++s) {
+              p.sites[s] = resolve(h, op->refs[s]);
+              p.l[s] = int(op->i[1 + 4 * s]);
+              p.P[s] = int(op->i[2 + 4 * s]);
+              p.r[s] = int(op->i[3 + 4 * s]);
+              p.D[s] = int(op->i[4 + 4 * s]);
+            }
+            v.push_back(p);
+          }
+          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.grid = dim3(unsigned(v.size()));
+          break;
+        }
+      }
+      out->gemm_flops += rec.gemm_flops;
+      out->contraction_flops += rec.contraction_flops;
+      out->launches.push_back(rec);
+    }
+    i = j;
+  }
+}
+
+hipError_t launch(pepsnet_s* h, const LaunchRec& r) {
+  const void* d = h->desc_dev + r.desc_off;
+  dim3 blk(256);
+  switch (r.type) {
+    case OPK_GEMM:
+      if (r.prec == PREC_FP64)
+        hipLaunchKernelGGL(k_gemm<PREC_FP64>, r.grid, blk, 0, h->stream, (const GemmDesc*)d);
+      else if (r.prec == PREC_FP32)
+        hipLaunchKernelGGL(k_gemm<PREC_FP32>, r.grid, blk, 0, h->stream, (const GemmDesc*)d);
+      else
+        hipLaunchKernelGGL(k_gemm<PREC_BF16X3>, r.grid, blk, 0, h->stream, (const GemmDesc*)d);
+      break;
+    case OPK_PERM:
+      hipLaunchKernelGGL(k_permute, r.grid, blk, 0, h->stream, (const PermDesc*)d);
+      break;
+    case OPK_QR:
+      hipLaunchKernelGGL(k_qr, r.grid, blk, 0, h->stream, (const QrDesc*)d);
+      break;
+    case OPK_JACOBI:
+      hipLaunchKernelGGL(k_jacobi, r.grid, blk, r.lds, h->stream, (const JacobiDesc*)d);
+      break;
+    case OPK_OMEGA:
+      hipLaunchKernelGGL(k_omega, r.grid, blk, 0, h->stream, (const OmegaDesc*)d);
+      break;
+    case OPK_NORM:
+      hipLaunchKernelGGL(k_normalize, r.grid, blk, 0, h->stream, (const NormDesc*)d);
+      break;
+    case OPK_PAD:
+      hipLaunchKernelGGL(k_pad, r.grid, blk, 0, h->stream, (const PadDesc*)d);
+      break;
+    case OPK_PHASE:
+      hipLaunchKernelGGL(k_phase, r.grid, blk, 0, h->stream, (const PhaseDesc*)d);
+      break;
+    case OPK_COLPHASE:
+      hipLaunchKernelGGL(k_colphase, r.grid, blk, 0, h->stream, (const ColPhaseDesc*)d);
+      break;
+  }
+  return hipGetLastError();
+}
+
+int32_t run_compiled(pepsnet_s* h, Compiled* c, bool allow_graph) {
+  if (allow_graph && h->use_graph) {
+    if (!c->exec) {
+      PN_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      for (const LaunchRec& r : c->launches) {
+        hipError_t e = launch(h, r);
+        if (e != hipSuccess) {
+          hipGraph_t g;
+          hipStreamEndCapture(h->stream, &g);
+          return fail(BBP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+        }
+      }
+      PN_HIP(hipStreamEndCapture(h->stream, &c->graph));
+      PN_HIP(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+    }
+    PN_HIP(hipGraphLaunch(c->exec, h->stream));
+    return BBP_OK;
+  }
+  for (const LaunchRec& r : c->launches) {
+    hipError_t e = launch(h, r);
+    if (e != hipSuccess) return fail(BBP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+  }
+  return BBP_OK;
+}
+
+std::string build_problem(const pepsnet_desc* d, Problem* P) {
+  if (d->lattice == BBP_KAGOME_OPEN) return build_finite(P, d->Lx, d->Ly, d->bLx, d->bLy);
+  if (d->lattice == BBP_KAGOME_INF_HEX) return build_hex(P, d->hex_N);
+  return "unknown lattice";
+}
+
+int32_t check_desc(const pepsnet_desc* d) {
+  if (!d) return fail(BBP_EINVAL, "null descriptor");
+  if (d->abi_version != PEPSNET_ABI_VERSION) return fail(BBP_EINVAL, "ABI version mismatch");
+  if (d->d != 2) return fail(BBP_EINVAL, "physical dimension must be 2 (spin 1/2)");
+  if (d->D < 1 || d->D > 16) return fail(BBP_EINVAL, "D must be in [1, 16]");
+  if (d->chi < 1 || d->chi > 256) return fail(BBP_EINVAL, "chi must be in [1, 256]");
+  if (d->chi_env != d->chi) return fail(BBP_EINVAL, "chi_env must equal chi");
+  if (d->precision < 0 || d->precision > 2) return fail(BBP_EINVAL, "bad precision");
+  if (d->trunc < 0 || d->trunc > 1) return fail(BBP_EINVAL, "bad truncation mode");
+  if (d->rsvd_q < 0 || d->rsvd_q > 8 || d->rsvd_p < 0 || d->rsvd_p > 64)
+    return fail(BBP_EINVAL, "bad randomized SVD parameters");
+  return BBP_OK;
+}
+
+int32_t upload_sites(pepsnet_s* h, const double* sites, int64_t len) {
+  if (!sites || len != 2 * h->comp->site_region_size)
+    return fail(BBP_EINVAL, "site tensor buffer has the wrong length (expected " +
+                                std::to_string(2 * h->comp->site_region_size) + " doubles)");
+  for (int64_t i = 0; i < len; ++i)
+    if (!std::isfinite(sites[i])) return fail(BBP_ENUMERIC, "non-finite site tensor entry");
+  PN_HIP(hipMemcpyAsync(h->arena + h->region_base[RG_SITE], sites, len * sizeof(double),
+                        hipMemcpyHostToDevice, h->stream));
+  int32_t rc = run_compiled(h, &h->prep, false);
+  if (rc) return rc;
+  PN_HIP(hipStreamSynchronize(h->stream));
+  return BBP_OK;
+}
+
+int32_t reset_messages(pepsnet_s* h) {
+  const MsgLayout& M = h->comp->msg;
+  std::vector<double> buf(2 * M.size, 0.0);
+  for (size_t m = 0; m < M.off.size(); ++m)
+    for (size_t j = 0; j < M.off[m].size(); ++j) {
+      int D = M.D[m][j], P = M.P[m][j], r = M.br[m][j];
+      double v = 1.0 / std::sqrt(double(D));
+      for (int k = 0; k < D; ++k) buf[2 * (M.off[m][j] + int64_t(k * D + k) * r)] = v;
+      (void)P;
+    }
+  h->parity = 0;
+  PN_HIP(hipMemcpyAsync(h->arena + h->region_base[RG_MSG0], buf.data(), buf.size() * sizeof(double),
+                        hipMemcpyHostToDevice, h->stream));
+  PN_HIP(hipStreamSynchronize(h->stream));
+  return BBP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pepsnet_last_error(void) { return g_last_error.c_str(); }
+
+int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t sites_len,
+                       pepsnet_t* out) {
+  if (!out) return fail(BBP_EINVAL, "null output handle");
+  *out = nullptr;
+  int32_t rc = check_desc(desc);
+  if (rc) return rc;
+  std::unique_ptr<pepsnet_s> h(new pepsnet_s());
+  std::string e = build_problem(desc, &h->P);
+  if (!e.empty()) return fail(BBP_EGEOM, e);
+  h->opt.chi = desc->chi;
+  h->opt.chi_env = desc->chi_env;
+  h->opt.trunc = desc->trunc;
+  h->opt.q = desc->rsvd_q;
+  h->opt.p = desc->rsvd_p;
+  h->opt.precision = desc->precision;
+  h->opt.seed = desc->seed;
+  h->opt.d = desc->d;
+  h->opt.D = desc->D;
+  h->comp.reset(new Compiler(h->P, h->opt));
+  if (!h->comp->error.empty()) return fail(BBP_EGEOM, h->comp->error);
+  Plan sp[2], ep[2];
+  for (int par = 0; par < 2; ++par)
+    if (!h->comp->build_sweep(par, &sp[par])) return fail(BBP_EGEOM, h->comp->error);
+  h->bonds = h->P.kind == 1 ? h->P.central_bonds() : h->P.bonds();
+  for (int par = 0; par < 2; ++par)
+    if (!h->comp->build_expect(par, h->bonds, &ep[par], &h->carry_order[par], &h->rho_off[par]))
+      return fail(BBP_EGEOM, h->comp->error);
+  // arena layout
+  Compiler& C = *h->comp;
+  int nl = int(C.lane_size.size());
+  std::vector<int64_t> sizes(RG_LANE0 + nl, 0);
+  sizes[RG_SITE] = C.site_region_size;
+  sizes[RG_SMAT] = C.smat_size;
+  sizes[RG_MSG0] = C.msg.size;
+  sizes[RG_MSG1] = C.msg.size;
+  sizes[RG_CONST] = 8;
+  sizes[RG_RHO] = std::max<int64_t>(C.rho_size, 8);
+  for (int L = 0; L < nl; ++L) sizes[RG_LANE0 + L] = C.lane_size[L];
+  h->region_base.assign(sizes.size(), 0);
+  int64_t tot = 0;
+  for (size_t r = 0; r < sizes.size(); ++r) {
+    h->region_base[r] = tot;
+    tot += (sizes[r] + 31) / 32 * 32;
+  }
+  h->arena_len = tot;
+  if (desc->stream) {
+    h->stream = (hipStream_t)desc->stream;
+  } else {
+    PN_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    h->own_stream = true;
+  }
+  if (hipMalloc(&h->arena, size_t(tot) * sizeof(cplx)) != hipSuccess)
+    return fail(BBP_ENOMEM, "device allocation of " + std::to_string(tot * 16) + " bytes failed");
+  if (hipMalloc(&h->scal, size_t(C.n_scalars) * sizeof(double)) != hipSuccess)
+    return fail(BBP_ENOMEM, "scalar allocation failed");
+  PN_HIP(hipMemsetAsync(h->arena, 0, size_t(tot) * sizeof(cplx), h->stream));
+  PN_HIP(hipMemsetAsync(h->scal, 0, size_t(C.n_scalars) * sizeof(double), h->stream));
+  cplx one = {1.0, 0.0};
+  PN_HIP(hipMemcpyAsync(h->arena + h->region_base[RG_CONST], &one, sizeof one,
+                        hipMemcpyHostToDevice, h->stream));
+  // compile and upload descriptors
+  {
+    std::vector<std::vector<std::pair<WaveKey, Op>>> prep(1);
+    for (size_t k = 0; k < C.prep_ops.size(); ++k) {
+      WaveKey wk;
+      wk.k = {0};
+      prep[0].push_back({wk, C.prep_ops[k]});
+    }
+    // prep ops are independent: one wave
+    compile_ops(h.get(), prep, &h->prep);
+  }
+  for (int par = 0; par < 2; ++par) {
+    std::vector<std::vector<std::pair<WaveKey, Op>>> lanes;
+    for (auto& L : sp[par].lanes) lanes.push_back(L.ops);
+    compile_ops(h.get(), lanes, &h->sweep[par]);
+    lanes.clear();
+    for (auto& L : ep[par].lanes) lanes.push_back(L.ops);
+    compile_ops(h.get(), lanes, &h->expect[par]);
+  }
+  int nb = int(h->bonds.size());
+  if (hipMalloc(&h->rho_mat, size_t(std::max(nb, 1)) * 16 * sizeof(cplx)) != hipSuccess ||
+      hipMalloc(&h->ss_dev, size_t(std::max(nb, 1)) * sizeof(double)) != hipSuccess)
+    return fail(BBP_ENOMEM, "expectation buffers");
+  for (int par = 0; par < 2; ++par) {
+    std::vector<RhoDesc> rd(nb);
+    for (int b = 0; b < nb; ++b) {
+      const std::vector<int>& ord = h->carry_order[par][b];
+      if (ord.size() != 2) return fail(BBP_EGEOM, "expectation carries two open sites");
+      rd[b].R = h->arena + h->region_base[RG_RHO] + h->rho_off[par][b];
+      rd[b].rho = h->rho_mat + 16 * b;
+      rd[b].ss = h->ss_dev + b;
+      rd[b].first_is_i = ord[0] == h->bonds[b].first ? 1 : 0;
+    }
+    size_t off = push_descs(&h->desc_host, rd);
+    h->rho_descs[par] = reinterpret_cast<RhoDesc*>(off);  // fixed up below
+  }
+  if (hipMalloc(&h->desc_dev, std::max<size_t>(h->desc_host.size(), 256)) != hipSuccess)
+    return fail(BBP_ENOMEM, "descriptor allocation failed");
+  PN_HIP(hipMemcpyAsync(h->desc_dev, h->desc_host.data(), h->desc_host.size(),
+                        hipMemcpyHostToDevice, h->stream));
+  for (int par = 0; par < 2; ++par)
+    h->rho_descs[par] = reinterpret_cast<RhoDesc*>(h->desc_dev + size_t(h->rho_descs[par]));
+  if (hipHostMalloc(&h->pinned, size_t(C.msg.off.size() + 8) * sizeof(double), 0) != hipSuccess)
+    return fail(BBP_ENOMEM, "pinned host buffer");
+  PN_HIP(hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(2 * JAC_LDS_MAX * JAC_LDS_MAX * sizeof(cplx))));
+  PN_HIP(hipEventCreate(&h->ev0));
+  PN_HIP(hipEventCreate(&h->ev1));
+  PN_HIP(hipStreamSynchronize(h->stream));
+  h->site_len = 2 * C.site_region_size;
+  rc = upload_sites(h.get(), sites, sites_len);
+  if (rc) return rc;
+  rc = reset_messages(h.get());
+  if (rc) return rc;
+  *out = h.release();
+  return BBP_OK;
+}
+
+int32_t pepsnet_set_sites(pepsnet_t h, const double* sites, int64_t len, int32_t reset) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  int32_t rc = upload_sites(h, sites, len);
+  if (rc) return rc;
+  if (reset) return reset_messages(h);
+  return BBP_OK;
+}
+
+int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
+                      double* max_err) {
+  if (!h || max_sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
+  const int nm = int(h->P.msg_keys.size());
+  std::vector<double> errs(nm);
+  double err = INFINITY;
+  int s = 0;
+  for (; s < max_sweeps;) {
+    h->pinned[0] = double(h->sweeps_total);
+    PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
+    PN_HIP(hipEventRecord(h->ev0, h->stream));
+    int32_t rc = run_compiled(h, &h->sweep[h->parity], true);
+    if (rc) return rc;
+    PN_HIP(hipEventRecord(h->ev1, h->stream));
+    PN_HIP(hipMemcpyAsync(h->pinned + 1, h->scal + h->comp->err_slot(0), nm * sizeof(double),
+                          hipMemcpyDeviceToHost, h->stream));
+    PN_HIP(hipStreamSynchronize(h->stream));
+    for (int m = 0; m < nm; ++m) errs[m] = h->pinned[1 + m];
+    float ms = 0.0f;
+    PN_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->timed_ms += ms;
+    h->timed_sweeps += 1;
+    h->parity ^= 1;
+    h->sweeps_total += 1;
+    ++s;
+    err = 0.0;
+    for (double x : errs) {
+      if (!std::isfinite(x)) {
+        if (sweeps_done) *sweeps_done = s;
+        return fail(BBP_ENUMERIC, "non-finite message after a sweep");
+      }
+      err = std::max(err, x);
+    }
+    if (err <= tol) break;
+  }
+  if (sweeps_done) *sweeps_done = s;
+  if (max_err) *max_err = err;
+  return err <= tol ? BBP_OK : BBP_NOT_CONVERGED;
+}
+
+int32_t blockbp_expect(pepsnet_t h, double* rho_out, double* ss_out, double* energy,
+                       int32_t* n_bonds_out) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  int nb = int(h->bonds.size());
+  int32_t rc = run_compiled(h, &h->expect[h->parity], false);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rho_ss, dim3((nb + 63) / 64), dim3(64), 0, h->stream, h->rho_descs[h->parity], nb);
+  PN_HIP(hipGetLastError());
+  std::vector<double> ss(nb);
+  PN_HIP(hipMemcpyAsync(ss.data(), h->ss_dev, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  if (rho_out)
+    PN_HIP(hipMemcpyAsync(rho_out, h->rho_mat, size_t(nb) * 16 * sizeof(cplx), hipMemcpyDeviceToHost,
+                          h->stream));
+  PN_HIP(hipStreamSynchronize(h->stream));
+  double e = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    if (!std::isfinite(ss[b])) return fail(BBP_ENUMERIC, "non-finite expectation value");
+    if (ss_out) ss_out[b] = ss[b];
+    e += ss[b];
+  }
+  if (energy) *energy = h->P.kind == 1 ? e / 3.0 : e / std::max(nb, 1);
+  if (n_bonds_out) *n_bonds_out = nb;
+  return BBP_OK;
+}
+
+int32_t pepsnet_bonds(pepsnet_t h, int32_t* pairs, int32_t cap, int32_t* n) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  int nb = int(h->bonds.size());
+  if (n) *n = nb;
+  if (pairs)
+    for (int b = 0; b < nb && 2 * b + 1 < cap; ++b) {
+      pairs[2 * b] = h->bonds[b].first;
+      pairs[2 * b + 1] = h->bonds[b].second;
+    }
+  return BBP_OK;
+}
+
+int32_t pepsnet_num_messages(pepsnet_t h) { return h ? int32_t(h->P.msg_keys.size()) : 0; }
+
+int32_t pepsnet_message_shape(pepsnet_t h, int32_t m, int32_t j, int32_t* l, int32_t* P,
+                              int32_t* r, int32_t* n_sites) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  const MsgLayout& M = h->comp->msg;
+  if (m < 0 || m >= int(M.off.size())) return fail(BBP_EINVAL, "bad message index");
+  if (n_sites) *n_sites = int(M.off[m].size());
+  if (j < 0 || j >= int(M.off[m].size())) return BBP_OK;
+  if (l) *l = M.bl[m][j];
+  if (P) *P = M.P[m][j];
+  if (r) *r = M.br[m][j];
+  return BBP_OK;
+}
+
+int32_t pepsnet_get_messages(pepsnet_t h, double* buf, int64_t cap, int64_t* len) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  const MsgLayout& M = h->comp->msg;
+  int64_t need = 0;
+  for (size_t m = 0; m < M.off.size(); ++m)
+    for (size_t j = 0; j < M.off[m].size(); ++j) need += 2LL * M.bl[m][j] * M.P[m][j] * M.br[m][j];
+  if (len) *len = need;
+  if (!buf) return BBP_OK;
+  if (cap < need) return fail(BBP_EINVAL, "buffer too small");
+  std::vector<cplx> all(M.size);
+  PN_HIP(hipMemcpyAsync(all.data(), h->arena + h->region_base[h->parity ? RG_MSG1 : RG_MSG0],
+                        M.size * sizeof(cplx), hipMemcpyDeviceToHost, h->stream));
+  PN_HIP(hipStreamSynchronize(h->stream));
+  int64_t o = 0;
+  for (size_t m = 0; m < M.off.size(); ++m)
+    for (size_t j = 0; j < M.off[m].size(); ++j) {
+      int64_t n = int64_t(M.bl[m][j]) * M.P[m][j] * M.br[m][j];
+      std::memcpy(buf + o, all.data() + M.off[m][j], n * sizeof(cplx));
+      o += 2 * n;
+    }
+  return BBP_OK;
+}
+
+int32_t pepsnet_set_messages(pepsnet_t h, const double* buf, int64_t len) {
+  if (!h || !buf) return fail(BBP_EINVAL, "null argument");
+  const MsgLayout& M = h->comp->msg;
+  int64_t need = 0;
+  for (size_t m = 0; m < M.off.size(); ++m)
+    for (size_t j = 0; j < M.off[m].size(); ++j) need += 2LL * M.bl[m][j] * M.P[m][j] * M.br[m][j];
+  if (len != need) return fail(BBP_EINVAL, "message buffer has the wrong length");
+  std::vector<cplx> all(M.size, cplx{0.0, 0.0});
+  int64_t o = 0;
+  for (size_t m = 0; m < M.off.size(); ++m)
+    for (size_t j = 0; j < M.off[m].size(); ++j) {
+      int64_t n = int64_t(M.bl[m][j]) * M.P[m][j] * M.br[m][j];
+      std::memcpy(all.data() + M.off[m][j], buf + o, n * sizeof(cplx));
+      o += 2 * n;
+    }
+  PN_HIP(hipMemcpyAsync(h->arena + h->region_base[h->parity ? RG_MSG1 : RG_MSG0], all.data(),
+                        M.size * sizeof(cplx), hipMemcpyHostToDevice, h->stream));
+  PN_HIP(hipStreamSynchronize(h->stream));
+  return BBP_OK;
+}
+
+void* pepsnet_stream(pepsnet_t h) { return h ? (void*)h->stream : nullptr; }
+
+int32_t pepsnet_timing(pepsnet_t h, int32_t reset, double* ms, int64_t* sweeps) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (ms) *ms = h->timed_sweeps ? h->timed_ms / double(h->timed_sweeps) : 0.0;
+  if (sweeps) *sweeps = h->timed_sweeps;
+  if (reset) { h->timed_ms = 0.0; h->timed_sweeps = 0; }
+  return BBP_OK;
+}
+
+int32_t pepsnet_use_graph(pepsnet_t h, int32_t on) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  h->use_graph = on != 0;
+  return BBP_OK;
+}
+
+int32_t pepsnet_sweep_stats(pepsnet_t h, double* cflops, double* gflops, int64_t* launches) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (cflops) *cflops = h->sweep[0].contraction_flops;
+  if (gflops) *gflops = h->sweep[0].gemm_flops;
+  if (launches) *launches = int64_t(h->sweep[0].launches.size());
+  return BBP_OK;
+}
+
+void pepsnet_destroy(pepsnet_t h) {
+  if (!h) return;
+  if (h->stream) hipStreamSynchronize(h->stream);
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep}) {
+    if (c->exec) hipGraphExecDestroy(c->exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+  }
+  if (h->arena) hipFree(h->arena);
+  if (h->scal) hipFree(h->scal);
+  if (h->desc_dev) hipFree(h->desc_dev);
+  if (h->rho_mat) hipFree(h->rho_mat);
+  if (h->ss_dev) hipFree(h->ss_dev);
+  if (h->pinned) hipHostFree(h->pinned);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int32_t pepsnet_describe(const pepsnet_desc* desc, int32_t what, int32_t a, int32_t b,
+                         int32_t n_open, const int32_t* open_sites, int32_t* buf, int64_t cap,
+                         int64_t* len) {
+  if (!desc) return fail(BBP_EINVAL, "null descriptor");
+  Problem P;
+  std::string e = build_problem(desc, &P);
+  if (!e.empty()) return fail(BBP_EGEOM, e);
+  std::vector<int32_t> out;
+  if (what == 0) {
+    if (a < 0 || a >= int(P.blocks.size())) return fail(BBP_EINVAL, "bad block");
+    out.push_back(int32_t(P.faces[a].size()));
+    for (auto& f : P.faces[a]) {
+      out.push_back(f.keytype);
+      out.push_back(f.key);
+      out.push_back(int32_t(f.legs.size()));
+      for (auto& sl : f.legs) { out.push_back(sl.first); out.push_back(sl.second); }
+    }
+  } else if (what == 1) {
+    if (a < 0 || a >= int(P.blocks.size())) return fail(BBP_EINVAL, "bad block");
+    std::vector<int> opens;
+    for (int k = 0; k < n_open; ++k) opens.push_back(open_sites[k]);
+    Schedule sc;
+    e = sweep_schedule(P, a, b, opens, &sc);
+    if (!e.empty()) return fail(BBP_EGEOM, e);
+    out.push_back(int32_t(sc.steps.size()));
+    for (auto& st : sc.steps) {
+      out.push_back(st.site);
+      out.push_back(st.pos);
+      out.push_back(int32_t(st.in_slots.size()));
+      out.push_back(int32_t(st.out_slots.size()));
+      for (int x : st.in_slots) out.push_back(x);
+      for (int x : st.out_slots) out.push_back(x);
+      out.push_back(st.open ? 1 : 0);
+      out.push_back(st.absorb);
+    }
+    out.push_back(int32_t(sc.final_legs.size()));
+    for (auto& sl : sc.final_legs) { out.push_back(sl.first); out.push_back(sl.second); }
+  } else if (what == 2) {
+    out = {int32_t(P.sites.size()), int32_t(P.blocks.size()), int32_t(P.msg_keys.size()),
+           int32_t(P.kind == 1 ? 6 : P.bonds().size())};
+  } else {
+    return fail(BBP_EINVAL, "unknown query");
+  }
+  if (len) *len = int64_t(out.size());
+  if (buf) {
+    if (cap < int64_t(out.size())) return fail(BBP_EINVAL, "buffer too small");
+    std::memcpy(buf, out.data(), out.size() * sizeof(int32_t));
+  }
+  return BBP_OK;
+}
+
+}  // extern "C"

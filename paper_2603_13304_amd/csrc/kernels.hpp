@@ -1,0 +1,123 @@
+// Device-side operation descriptors shared by the plan compiler and the
+// HIP kernels.  Every kernel is batched: it receives an array of descriptors
+// (one per independent work item, e.g. one per message update running side
+// by side) and blockIdx.z / blockIdx.y selects the item.
+//
+// Complex numbers are stored as interleaved double pairs (re, im), C order.
+#pragma once
+#include <cstdint>
+
+namespace pn {
+
+struct cplx {
+  double re, im;
+};
+
+enum GemmOp { OP_N = 0, OP_T = 1, OP_C = 2 };        // op(X) = X, X^T, X^H
+enum Precision { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
+
+// C = alpha * op(A) * op(B) + beta * C, row-major, op(A) is M x K, op(B) K x N.
+struct GemmDesc {
+  const cplx* A;
+  const cplx* B;
+  cplx* C;
+  int M, N, K;
+  int lda, ldb, ldc;
+  int opA, opB;
+  cplx alpha, beta;
+};
+
+// dst[o] = src[sum_k idx_k(o) * stride[k]] for o over the row-major output
+// shape dims[0..rank).
+struct PermDesc {
+  const cplx* src;
+  cplx* dst;
+  int rank;
+  int conj;       // 1: complex-conjugate while copying
+  int64_t total;
+  int dims[16];
+  int64_t stride[16];
+};
+
+// Householder QR of the m x n matrix A (row-major, lda) or, with conjT, of
+// A^H where A is n x m.  Work is an m x n scratch; Q (m x k, ldq = k) and
+// R (k x n, ldr = n) with k = min(m, n) are written explicitly.
+struct QrDesc {
+  const cplx* A;
+  cplx* work;
+  cplx* Q;
+  cplx* R;
+  int m, n, lda, conjT;
+};
+
+// One-sided Jacobi on the columns of the k x k matrix R (row-major, ld k):
+// R J = W with orthogonal columns.  Writes J with columns sorted by
+// decreasing column norm into V (k x k) and the norms into sigma.
+struct JacobiDesc {
+  const cplx* R;
+  cplx* work;   // k x k scratch (used when the matrix does not fit in LDS)
+  cplx* V;      // k x k output
+  double* sigma;
+  int k;
+};
+
+// Random sign sketch: out[i, j] = (+-1 +- 1j)/sqrt(2) from SplitMix64 output
+// number i*k + j of the generator seeded with key (n x k, row-major).  The
+// key is out0(prefix ^ tag) where tag is read from *last_tag (the sweep
+// counter, kept on the device so captured launches stay valid).
+struct OmegaDesc {
+  cplx* out;
+  int n, k;
+  uint64_t prefix;
+  const double* last_tag;
+};
+
+// x /= ||x||_F, logscale += log10 ||x||_F
+struct NormDesc {
+  cplx* x;
+  int64_t len;
+  double* logscale;
+  double* norm_out;   // optional: stores ||x||
+};
+
+// Block copy between [l, P, r] tensors: dst[l, p, r] <- sign * src[l - off_l,
+// p, r - off_r] where the source index is in range.  mode 0 writes every
+// destination element (zero outside the block), mode 1 writes the block only,
+// mode 2 adds the block to the destination.  Also used to crop (r2 < r1).
+struct PadDesc {
+  const cplx* src;
+  cplx* dst;
+  int l1, P, r1, l2, r2, off_l, off_r;
+  int mode;
+  double sign;
+};
+
+// Message trace (ket = bra on every leg) and phase fix of site 0.
+struct PhaseDesc {
+  cplx* sites[16];
+  int l[16], P[16], r[16], D[16];
+  int nsites;
+};
+
+}  // namespace pn
+
+namespace pn {
+// Canonical gauge of a split bond: for each column j of L (m x keep, ld keep)
+// the entry of largest modulus (first on ties) becomes real positive; row j of
+// R (keep x n, ld n) takes the inverse phase.
+struct ColPhaseDesc {
+  cplx* L;
+  cplx* R;
+  int m, keep, n;
+};
+
+// rho and <S_i.S_j> from the carried expectation vectors: R[q_a * d^2 + q_b]
+// with q = p * d + p' for the two carried open sites in carry order (first
+// is site i when first_is_i).  rho is written as [(p_i p_j), (p_i' p_j')].
+struct RhoDesc {
+  const cplx* R;
+  cplx* rho;
+  double* ss;
+  int first_is_i;
+};
+}  // namespace pn

@@ -1,0 +1,864 @@
+// Plan compiler: turns the geometry's sweep orders into static device
+// operations (see plan.hpp).
+//
+// Boundary chain (Sec. "The boundary-MPS method"): a chain site is a tensor
+// A[l, P, r] whose leg P fuses (ket, bra, carried pairs...) row-major, ket and
+// bra of the leg's bond dimension D (double leg I = k*D + b), each carried
+// pair of an open site d*d (p*d + p').  Bond dimensions are static: a
+// factorisation of an m x n matrix keeps min(m, n) columns, a truncated
+// split keeps min(chi_env, m, n); stored messages are zero-padded to the MPS
+// caps min(chi, prod of leg dims on each side).
+//
+// Per swallowed site (ket tensor t[p, slots]) with in-legs at chain
+// positions pos..pos+r-1 and out-legs o_1..o_s:
+//   1. canonical moves: QR steps to the right / LQ steps to the left bring
+//      the orthogonality centre into the run (Sec. "Canonical MPS");
+//   2. merge the run: Theta[a, L_1 .. L_r, b] by r-1 GEMMs;
+//   3. absorb the ket (GEMM over the in-legs' ket indices) and the bra
+//      (GEMM over p and the in-legs' bra indices; p kept open for an open
+//      site), with three tensor transposes around the two GEMMs;
+//   4. split Theta'[a, O_1 .. O_s, b] left to right into s sites with
+//      truncated SVDs: T1 exact (Householder QR + one-sided Jacobi), or T2
+//      randomized range finder with q power iterations and p oversampling
+//      (Halko, Martinsson & Tropp 2011, Alg. 4.4) on a SplitMix64 sign
+//      sketch, then the same exact small SVD;
+//   5. normalise the centre and accumulate log10 of its norm (Sec.
+//      "Mantissa and Exponent").
+// A site with no out-leg leaves a bond matrix that is absorbed into the
+// chain neighbour.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+
+namespace pn {
+namespace {
+
+uint64_t mix_out0(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t key_prefix(uint64_t seed, const std::vector<uint64_t>& tags) {
+  uint64_t k = seed;
+  for (uint64_t t : tags) k = mix_out0(k ^ t);
+  return k;
+}
+
+int64_t prod(const std::vector<int>& v) {
+  int64_t p = 1;
+  for (int x : v) p *= x;
+  return p;
+}
+
+int ipow(int b, int e) {
+  int r = 1;
+  while (e-- > 0) r *= b;
+  return r;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- lane
+struct Compiler::Lane {
+  Compiler* C;
+  int id;
+  LaneOps* out;
+  int64_t chain_top = 0, scratch_top = 0, scratch_max = 0;
+  int stage = 0, step = 0, phase = 0, counter = 0;
+  std::string err;
+
+  Lane(Compiler* c, int lane, LaneOps* o) : C(c), id(lane), out(o) {}
+
+  int rg_chain() const { return RG_LANE0 + 2 * id; }
+  int rg_scratch() const { return RG_LANE0 + 2 * id + 1; }
+  Ref chain_alloc(int64_t n) {
+    Ref r{rg_chain(), chain_top};
+    chain_top += (n + 7) / 8 * 8;
+    return r;
+  }
+  Ref scratch(int64_t n) {
+    Ref r{rg_scratch(), scratch_top};
+    scratch_top += (n + 7) / 8 * 8;
+    scratch_max = std::max(scratch_max, scratch_top);
+    return r;
+  }
+  void reset_scratch() { scratch_top = 0; }
+  void at(int st, int sp, int ph) {
+    if (st != stage || sp != step || ph != phase) counter = 0;
+    stage = st; step = sp; phase = ph;
+  }
+  void push(const Op& op) {
+    WaveKey k;
+    k.k = {stage, step, phase, counter++};
+    out->ops.push_back({k, op});
+  }
+
+  // ------------------------------------------------------------ emitters
+  void gemm(Ref A, Ref B, Ref Cc, int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb,
+            int64_t ldc, int opA, int opB, int prec, int contraction = 0, double ar = 1.0,
+            double ai = 0.0, double br = 0.0, double bi = 0.0) {
+    Op op;
+    op.type = OPK_GEMM;
+    op.a = A; op.b = B; op.c = Cc;
+    op.i[0] = M; op.i[1] = N; op.i[2] = K;
+    op.i[3] = lda; op.i[4] = ldb; op.i[5] = ldc;
+    op.i[6] = opA; op.i[7] = opB; op.i[8] = prec; op.i[9] = contraction;
+    op.x[0] = ar; op.x[1] = ai; op.x[2] = br; op.x[3] = bi;
+    push(op);
+  }
+  // dst = transpose(src) with output axis k = input axis perm[k]
+  void perm(Ref src, Ref dst, const std::vector<int>& dims, const std::vector<int>& pm,
+            int conj = 0) {
+    int n = int(dims.size());
+    std::vector<int64_t> st(n, 1);
+    for (int k = n - 2; k >= 0; --k) st[k] = st[k + 1] * dims[k + 1];
+    std::vector<int> od;
+    std::vector<int64_t> os;
+    for (int k = 0; k < n; ++k) {
+      int ax = pm[k];
+      if (dims[ax] == 1) continue;
+      if (!od.empty() && os.back() == st[ax] * dims[ax]) {  // merge contiguous axes
+        od.back() *= dims[ax];
+        os.back() = st[ax];
+        continue;
+      }
+      od.push_back(dims[ax]);
+      os.push_back(st[ax]);
+    }
+    if (od.empty()) { od.push_back(1); os.push_back(1); }
+    if (od.size() > 16) { err = "tensor rank too large for the transpose kernel"; return; }
+    Op op;
+    op.type = OPK_PERM;
+    op.a = src; op.b = dst;
+    op.i[0] = int64_t(od.size());
+    op.i[1] = conj;
+    for (size_t k = 0; k < od.size(); ++k) { op.i[2 + k] = od[k]; op.i[18 + k] = os[k]; }
+    push(op);
+  }
+  void qr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R) {
+    if (std::min(m, n) > 256) { err = "QR width above 256"; return; }
+    Op op;
+    op.type = OPK_QR;
+    op.a = A; op.b = scratch(m * n); op.c = Q; op.d = R;
+    op.i[0] = m; op.i[1] = n; op.i[2] = lda; op.i[3] = conjT;
+    push(op);
+  }
+  void jacobi(Ref R, int64_t k, Ref V, Ref sig) {
+    if (k > 256) { err = "Jacobi size above 256"; return; }
+    Op op;
+    op.type = OPK_JACOBI;
+    op.a = R; op.b = scratch(k * k); op.c = V; op.d = sig;
+    op.i[0] = k;
+    push(op);
+  }
+  void omega(Ref dst, int64_t n, int64_t k, uint64_t prefix, bool sweep_tag) {
+    Op op;
+    op.type = OPK_OMEGA;
+    op.a = dst;
+    op.i[0] = n; op.i[1] = k; op.i[2] = sweep_tag ? 1 : 0;
+    op.key = prefix;
+    push(op);
+  }
+  void norm(Ref x, int64_t len, int64_t logslot, int64_t normslot) {
+    Op op;
+    op.type = OPK_NORM;
+    op.a = x;
+    op.i[0] = len;
+    op.s0.off = logslot;
+    op.s1.off = normslot;
+    push(op);
+  }
+  void pad(Ref src, Ref dst, int l1, int P, int r1, int l2, int r2, int offl, int offr,
+           int mode, double sign = 1.0) {
+    Op op;
+    op.type = OPK_PAD;
+    op.a = src; op.b = dst;
+    op.i[0] = l1; op.i[1] = P; op.i[2] = r1; op.i[3] = l2; op.i[4] = r2;
+    op.i[5] = offl; op.i[6] = offr; op.i[7] = mode;
+    op.x[0] = sign;
+    push(op);
+  }
+  void phase_fix(const std::vector<CSite>& sites) {
+    if (sites.size() > 16) { err = "message longer than 16 legs"; return; }
+    Op op;
+    op.type = OPK_PHASE;
+    op.i[0] = int64_t(sites.size());
+    for (size_t j = 0; j < sites.size(); ++j) {
+      op.refs.push_back(sites[j].buf);
+      op.i[1 + 4 * j] = sites[j].l;
+      op.i[2 + 4 * j] = sites[j].P;
+      op.i[3 + 4 * j] = sites[j].r;
+      op.i[4 + 4 * j] = sites[j].D;
+    }
+    push(op);
+  }
+
+  void colphase(Ref L, Ref R, int64_t m, int64_t keep, int64_t n) {
+    Op op;
+    op.type = OPK_COLPHASE;
+    op.a = L; op.b = R;
+    op.i[0] = m; op.i[1] = keep; op.i[2] = n;
+    push(op);
+  }
+
+  // ------------------------------------------------------ chain operations
+  // left-canonicalise site j, push R into j+1
+  void move_right(std::vector<CSite>& ch, int j) {
+    CSite& A = ch[j];
+    CSite& B = ch[j + 1];
+    int64_t m = int64_t(A.l) * A.P, n = A.r, k = std::min(m, n);
+    Ref Q = chain_alloc(m * k), R = scratch(k * n);
+    qr(A.buf, m, n, n, 0, Q, R);
+    Ref NB = chain_alloc(k * B.P * B.r);
+    gemm(R, B.buf, NB, k, int64_t(B.P) * B.r, n, n, int64_t(B.P) * B.r, int64_t(B.P) * B.r,
+         OP_N, OP_N, PREC_FP64);
+    A.buf = Q; A.r = int(k);
+    B.buf = NB; B.l = int(k);
+  }
+  // right-canonicalise site j, push L into j-1
+  void move_left(std::vector<CSite>& ch, int j) {
+    CSite& A = ch[j];
+    CSite& B = ch[j - 1];
+    int64_t m = int64_t(A.P) * A.r, n = A.l, k = std::min(m, n);
+    // A^H (m x n) = Q' R'  ->  A = R'^H Q'^H
+    Ref Qp = scratch(m * k), Rp = scratch(k * n);
+    qr(A.buf, m, n, m, 1, Qp, Rp);
+    Ref NA = chain_alloc(k * m);
+    perm(Qp, NA, {int(m), int(k)}, {1, 0}, 1);
+    Ref NB = chain_alloc(int64_t(B.l) * B.P * k);
+    gemm(B.buf, Rp, NB, int64_t(B.l) * B.P, k, n, n, n, k, OP_N, OP_C, PREC_FP64);
+    A.buf = NA; A.l = int(k);
+    B.buf = NB; B.r = int(k);
+  }
+  void move_center(std::vector<CSite>& ch, int& center, int lo, int hi) {
+    while (center < lo) { move_right(ch, center); ++center; }
+    while (center > hi) { move_left(ch, center); --center; }
+  }
+
+  // truncated split of the m x n matrix M: writes L (m x keep) and R (keep x n)
+  int split(Ref M, int64_t m, int64_t n, Ref Lout, Ref Rout, uint64_t prefix, bool sweep_tag,
+            int* keep_out) {
+    const PlanOptions& o = C->opt;
+    int64_t full = std::min(m, n);
+    int64_t keep = o.chi_env > 0 ? std::min<int64_t>(o.chi_env, full) : full;
+    *keep_out = int(keep);
+    bool t2 = o.trunc == 1 && o.chi_env > 0 && o.chi_env + o.p < full;
+    if (t2) {
+      int64_t k = o.chi_env + o.p;
+      Ref Om = scratch(n * k);
+      omega(Om, n, k, prefix, sweep_tag);
+      Ref Y = scratch(m * k);
+      gemm(M, Om, Y, m, k, n, n, k, k, OP_N, OP_N, o.precision, 1);
+      for (int it = 0; it < o.q; ++it) {
+        Ref Qy = scratch(m * k), Ry = scratch(k * k);
+        qr(Y, m, k, k, 0, Qy, Ry);
+        Ref Z = scratch(n * k);
+        gemm(M, Qy, Z, n, k, m, n, k, k, OP_C, OP_N, o.precision, 1);
+        Ref Qz = scratch(n * k), Rz = scratch(k * k);
+        qr(Z, n, k, k, 0, Qz, Rz);
+        Y = scratch(m * k);
+        gemm(M, Qz, Y, m, k, n, n, k, k, OP_N, OP_N, o.precision, 1);
+      }
+      Ref Q = scratch(m * k), Rq = scratch(k * k);
+      qr(Y, m, k, k, 0, Q, Rq);
+      Ref B = scratch(k * n);
+      gemm(Q, M, B, k, n, m, k, n, n, OP_C, OP_N, o.precision, 1);
+      Ref Q3 = scratch(n * k), R3 = scratch(k * k);
+      qr(B, n, k, n, 1, Q3, R3);
+      Ref V = scratch(k * k), sig = scratch(k);
+      jacobi(R3, k, V, sig);
+      gemm(Q, V, Lout, m, keep, k, k, k, keep, OP_N, OP_N, PREC_FP64);
+      gemm(V, B, Rout, keep, n, k, k, n, n, OP_C, OP_N, PREC_FP64);
+      colphase(Lout, Rout, m, keep, n);
+      return 0;
+    }
+    if (m <= n) {
+      Ref Q3 = scratch(n * m), R3 = scratch(m * m);
+      qr(M, n, m, n, 1, Q3, R3);
+      Ref V = scratch(m * m), sig = scratch(m);
+      jacobi(R3, m, V, sig);
+      pad(V, Lout, int(m), 1, int(m), int(m), int(keep), 0, 0, 0);
+      gemm(V, M, Rout, keep, n, m, m, n, n, OP_C, OP_N, PREC_FP64);
+      colphase(Lout, Rout, m, keep, n);
+    } else {
+      Ref Q = scratch(m * n), R = scratch(n * n);
+      qr(M, m, n, n, 0, Q, R);
+      Ref Q3 = scratch(n * n), R3 = scratch(n * n);
+      qr(R, n, n, n, 1, Q3, R3);
+      Ref V = scratch(n * n), sig = scratch(n);
+      jacobi(R3, n, V, sig);
+      gemm(Q, V, Lout, m, keep, n, n, n, keep, OP_N, OP_N, PREC_FP64);
+      gemm(V, R, Rout, keep, n, n, n, n, n, OP_C, OP_N, PREC_FP64);
+      colphase(Lout, Rout, m, keep, n);
+    }
+    return 0;
+  }
+
+  // swallow one site; stepno used for wave alignment and the sketch tags
+  void swallow(std::vector<CSite>& ch, int& center, const Step& st, int stepno,
+               const std::vector<uint64_t>& tag_head, bool sweep_tag) {
+    const Problem& P = C->prob;
+    const PlanOptions& o = C->opt;
+    const int pos = st.pos, r = int(st.in_slots.size()), s = int(st.out_slots.size());
+    const int t = P.sites[st.site].tensor;
+    const std::vector<int>& td = C->tensor_dims[t];
+    const int d = td[0];
+    reset_scratch();
+    at(stage, stepno, 0);
+    move_center(ch, center, pos, pos + r - 1);
+    // --- merge
+    at(stage, stepno, 1);
+    Ref th = ch[pos].buf;
+    int64_t a = ch[pos].l, rows = int64_t(ch[pos].l) * ch[pos].P;
+    int64_t b = ch[pos].r;
+    for (int j = 1; j < r; ++j) {
+      const CSite& A = ch[pos + j];
+      Ref dst = scratch(rows * A.P * A.r);
+      gemm(th, A.buf, dst, rows, int64_t(A.P) * A.r, b, b, int64_t(A.P) * A.r,
+           int64_t(A.P) * A.r, OP_N, OP_N, o.precision, 1);
+      th = dst;
+      rows *= A.P;
+      b = A.r;
+    }
+    // --- absorb: Theta dims [a, (k_j, b_j, Q_j)..., b]
+    at(stage, stepno, 2);
+    std::vector<int> Din(r), Qin(r), carry_ids;
+    for (int j = 0; j < r; ++j) {
+      Din[j] = ch[pos + j].D;
+      Qin[j] = ipow(d * d, int(ch[pos + j].carries.size()));
+      for (int c : ch[pos + j].carries) carry_ids.push_back(c);
+      if (Din[j] != td[1 + st.in_slots[j]]) { err = "leg dimension mismatch"; return; }
+    }
+    std::vector<int> Dout(s);
+    for (int j = 0; j < s; ++j) Dout[j] = td[1 + st.out_slots[j]];
+    if (st.open) carry_ids.push_back(st.site);
+    // theta axes: 0 = a, 1+3j = k_j, 2+3j = b_j, 3+3j = Q_j, 1+3r = b
+    std::vector<int> thd = {int(a)};
+    for (int j = 0; j < r; ++j) { thd.push_back(Din[j]); thd.push_back(Din[j]); thd.push_back(Qin[j]); }
+    thd.push_back(int(b));
+    std::vector<int> p1 = {0};
+    for (int j = 0; j < r; ++j) { p1.push_back(2 + 3 * j); p1.push_back(3 + 3 * j); }
+    p1.push_back(1 + 3 * r);
+    for (int j = 0; j < r; ++j) p1.push_back(1 + 3 * j);
+    int64_t Kin = prod(Din), Qtot_in = prod(Qin);
+    int64_t M1 = a * b * Kin * Qtot_in;     // rows (a, b_j, Q_j, b)
+    Ref X = scratch(M1 * Kin);
+    perm(th, X, thd, p1);
+    int64_t Kout = prod(Dout);
+    int64_t N1 = d * Kout;
+    Ref Y = scratch(M1 * N1);
+    auto sm = C->ensure_smat(t, st.in_slots, st.out_slots, st.open);
+    gemm(X, sm.first, Y, M1, N1, Kin, Kin, N1, N1, OP_N, OP_N, o.precision, 1);
+    // Y axes: 0 = a, 1+2j = b_j, 2+2j = Q_j, 1+2r = b, 2+2r = p, 3+2r+m = ko_m
+    std::vector<int> yd = {int(a)};
+    for (int j = 0; j < r; ++j) { yd.push_back(Din[j]); yd.push_back(Qin[j]); }
+    yd.push_back(int(b));
+    yd.push_back(d);
+    for (int m = 0; m < s; ++m) yd.push_back(Dout[m]);
+    std::vector<int> p2 = {0, 1 + 2 * r};
+    for (int j = 0; j < r; ++j) p2.push_back(2 + 2 * j);
+    if (st.open) p2.push_back(2 + 2 * r);
+    for (int m = 0; m < s; ++m) p2.push_back(3 + 2 * r + m);
+    if (!st.open) p2.push_back(2 + 2 * r);
+    for (int j = 0; j < r; ++j) p2.push_back(1 + 2 * j);
+    Ref Z = scratch(M1 * N1);
+    perm(Y, Z, yd, p2);
+    int64_t K2 = (st.open ? 1 : d) * Kin;
+    int64_t N2 = (st.open ? d : 1) * Kout;
+    int64_t M2 = M1 * N1 / K2;
+    Ref W = scratch(M2 * N2);
+    gemm(Z, sm.second, W, M2, N2, K2, K2, N2, N2, OP_N, OP_N, o.precision, 1);
+    // W axes (not open): 0 = a, 1 = b, 2+j = Q_j, 2+r+m = ko_m, 2+r+s+m = bo_m
+    // W axes (open):     0 = a, 1 = b, 2+j = Q_j, 2+r = p, 3+r+m = ko_m,
+    //                    3+r+s = p', 4+r+s+m = bo_m
+    std::vector<int> wd = {int(a), int(b)};
+    for (int j = 0; j < r; ++j) wd.push_back(Qin[j]);
+    if (st.open) wd.push_back(d);
+    for (int m = 0; m < s; ++m) wd.push_back(Dout[m]);
+    if (st.open) wd.push_back(d);
+    for (int m = 0; m < s; ++m) wd.push_back(Dout[m]);
+    const int ko0 = st.open ? 3 + r : 2 + r;
+    const int bo0 = st.open ? 4 + r + s : 2 + r + s;
+    std::vector<int> p3 = {0};
+    if (s > 0) { p3.push_back(ko0); p3.push_back(bo0); }
+    for (int j = 0; j < r; ++j) p3.push_back(2 + j);
+    if (st.open) { p3.push_back(2 + r); p3.push_back(3 + r + s); }
+    for (int m = 1; m < s; ++m) { p3.push_back(ko0 + m); p3.push_back(bo0 + m); }
+    p3.push_back(1);
+    int64_t Qtot = ipow(d * d, int(carry_ids.size()));
+    std::vector<int> phys(s);
+    for (int m = 0; m < s; ++m) phys[m] = Dout[m] * Dout[m];
+    if (s > 0) phys[0] *= int(Qtot);
+    const int64_t thp_len = M2 * N2;
+    if (s == 0) {
+      Ref Tp = scratch(thp_len);
+      perm(W, Tp, wd, p3);
+      // Theta'[a, Q, b] absorbed into a neighbour
+      if (st.absorb == 0) {
+        CSite& Nb = ch[pos + r];
+        Ref G = scratch(a * Qtot * Nb.P * Nb.r);
+        gemm(Tp, Nb.buf, G, a * Qtot, int64_t(Nb.P) * Nb.r, b, b, int64_t(Nb.P) * Nb.r,
+             int64_t(Nb.P) * Nb.r, OP_N, OP_N, PREC_FP64);
+        Ref NS = chain_alloc(a * Qtot * Nb.P * Nb.r);
+        perm(G, NS, {int(a), int(Qtot), Nb.P, Nb.r}, {0, 2, 1, 3});
+        Nb.buf = NS;
+        Nb.l = int(a);
+        Nb.P = int(Nb.P * Qtot);
+        for (int c : carry_ids) Nb.carries.push_back(c);
+        at(stage, stepno, 4);
+        norm(NS, int64_t(Nb.l) * Nb.P * Nb.r, C->logscale_slot(id), -1);
+        ch.erase(ch.begin() + pos, ch.begin() + pos + r);
+        center = pos;
+      } else {
+        CSite& Nb = ch[pos - 1];
+        Ref NS = chain_alloc(int64_t(Nb.l) * Nb.P * Qtot * b);
+        gemm(Nb.buf, Tp, NS, int64_t(Nb.l) * Nb.P, Qtot * b, a, a, Qtot * b, Qtot * b, OP_N,
+             OP_N, PREC_FP64);
+        Nb.buf = NS;
+        Nb.r = int(b);
+        Nb.P = int(Nb.P * Qtot);
+        for (int c : carry_ids) Nb.carries.push_back(c);
+        at(stage, stepno, 4);
+        norm(NS, int64_t(Nb.l) * Nb.P * Nb.r, C->logscale_slot(id), -1);
+        ch.erase(ch.begin() + pos, ch.begin() + pos + r);
+        center = pos - 1;
+      }
+      return;
+    }
+    Ref Tp = (s == 1) ? chain_alloc(thp_len) : scratch(thp_len);
+    perm(W, Tp, wd, p3);
+    // --- split left to right
+    at(stage, stepno, 3);
+    std::vector<CSite> news;
+    int64_t left = a;
+    Ref rest = Tp;
+    for (int m = 0; m < s - 1; ++m) {
+      int64_t rws = left * phys[m];
+      int64_t cols = b;
+      for (int u = m + 1; u < s; ++u) cols *= phys[u];
+      int64_t full = std::min(rws, cols);
+      int64_t keep = o.chi_env > 0 ? std::min<int64_t>(o.chi_env, full) : full;
+      Ref L = chain_alloc(rws * keep);
+      Ref R = (m == s - 2) ? chain_alloc(keep * cols) : scratch(keep * cols);
+      std::vector<uint64_t> tags = tag_head;
+      tags.push_back(uint64_t(stepno));
+      tags.push_back(uint64_t(m));
+      int kk = 0;
+      split(rest, rws, cols, L, R, key_prefix(o.seed, tags), sweep_tag, &kk);
+      CSite ns;
+      ns.buf = L; ns.l = int(left); ns.P = phys[m]; ns.r = kk; ns.D = Dout[m];
+      if (m == 0) ns.carries = carry_ids;
+      news.push_back(ns);
+      rest = R;
+      left = kk;
+    }
+    CSite last;
+    last.buf = rest; last.l = int(left); last.P = phys[s - 1]; last.r = int(b); last.D = Dout[s - 1];
+    if (s == 1) last.carries = carry_ids;
+    news.push_back(last);
+    at(stage, stepno, 4);
+    norm(last.buf, int64_t(last.l) * last.P * last.r, C->logscale_slot(id), -1);
+    ch.erase(ch.begin() + pos, ch.begin() + pos + r);
+    ch.insert(ch.begin() + pos, news.begin(), news.end());
+    center = pos + s - 1;
+  }
+
+  // chain from face legs of block b: faces after ``target`` counter-clockwise;
+  // ``override_face`` replaces one face's message by the given sites
+  std::vector<CSite> initial_chain(int blk, int target, int msg_region,
+                                   int override_face, const std::vector<CSite>* ovr) {
+    const Problem& P = C->prob;
+    const std::vector<Face>& F = P.faces[blk];
+    int nf = int(F.size());
+    std::vector<CSite> ch;
+    for (int k = 1; k < nf; ++k) {
+      int f = (target + k) % nf;
+      if (f == override_face && ovr) {
+        for (auto& x : *ovr) ch.push_back(x);
+        continue;
+      }
+      int slot = P.incoming_msg(blk, f);
+      for (size_t j = 0; j < F[f].legs.size(); ++j) {
+        const auto& sl = F[f].legs[j];
+        int D = C->tensor_dims[P.sites[sl.first].tensor][1 + sl.second];
+        CSite cs;
+        cs.D = D;
+        if (slot < 0) {
+          cs.buf = Ref{RG_CONST, 0};   // trivial message: [1] on a dimension-1 leg
+          cs.l = 1; cs.P = 1; cs.r = 1;
+          if (D != 1) { err = "trivial face with a non-trivial leg"; }
+        } else {
+          cs.buf = Ref{msg_region, C->msg.off[slot][j]};
+          cs.l = C->msg.bl[slot][j];
+          cs.P = C->msg.P[slot][j];
+          cs.r = C->msg.br[slot][j];
+        }
+        ch.push_back(cs);
+      }
+    }
+    return ch;
+  }
+
+  std::vector<CSite> run_sweep(int blk, int target, const std::vector<int>& open_sites,
+                               int msg_region, const std::vector<uint64_t>& tag_head,
+                               bool sweep_tag, int override_face,
+                               const std::vector<CSite>* ovr,
+                               std::vector<std::pair<int, int>>* final_legs, int* center_out) {
+    Schedule sc;
+    std::string e = sweep_schedule(C->prob, blk, target, open_sites, &sc);
+    if (!e.empty()) { err = e; return {}; }
+    std::vector<CSite> ch = initial_chain(blk, target, msg_region, override_face, ovr);
+    int center = 0;
+    for (size_t n = 0; n < sc.steps.size() && err.empty(); ++n)
+      swallow(ch, center, sc.steps[n], int(n), tag_head, sweep_tag);
+    *final_legs = sc.final_legs;
+    *center_out = center;
+    return ch;
+  }
+
+  void reverse_chain(std::vector<CSite>& ch, int& center) {
+    std::vector<CSite> rv;
+    for (int j = int(ch.size()) - 1; j >= 0; --j) {
+      CSite x = ch[j];
+      Ref nb = chain_alloc(int64_t(x.l) * x.P * x.r);
+      perm(x.buf, nb, {x.l, x.P, x.r}, {2, 1, 0});
+      x.buf = nb;
+      std::swap(x.l, x.r);
+      rv.push_back(x);
+    }
+    center = int(ch.size()) - 1 - center;
+    ch = rv;
+  }
+
+  void right_canonical(std::vector<CSite>& ch, int& center) {
+    move_center(ch, center, int(ch.size()) - 1, int(ch.size()) - 1);
+    move_center(ch, center, 0, 0);
+    norm(ch[0].buf, int64_t(ch[0].l) * ch[0].P * ch[0].r, C->logscale_slot(id), -1);
+  }
+};
+
+// ------------------------------------------------------------- compiler
+Compiler::Compiler(const Problem& P, const PlanOptions& o) : prob(P), opt(o) {
+  // tensor dims: legs to outside a finite patch have dimension 1
+  int nt = P.n_tensors();
+  tensor_dims.assign(nt, {});
+  tensor_off.assign(nt, 0);
+  for (size_t s = 0; s < P.sites.size(); ++s) {
+    int t = P.sites[s].tensor;
+    if (!tensor_dims[t].empty()) continue;
+    std::vector<int> dims = {opt.d};
+    for (int l = 0; l < P.sites[s].nslot; ++l)
+      dims.push_back(P.links[s][l].type == LINK_OUTSIDE ? 1 : opt.D);
+    tensor_dims[t] = dims;
+  }
+  int64_t off = 0;
+  for (int t = 0; t < nt; ++t) {
+    tensor_off[t] = off;
+    off += prod(tensor_dims[t]);
+  }
+  site_region_size = off;
+  // message layout: caps min(chi, prod of leg dims on each side)
+  int nm = int(P.msg_keys.size());
+  msg.off.resize(nm); msg.bl.resize(nm); msg.br.resize(nm); msg.P.resize(nm); msg.D.resize(nm);
+  int64_t moff = 0;
+  for (int m = 0; m < nm; ++m) {
+    const auto& legs = P.stored_legs(m);
+    int n = int(legs.size());
+    std::vector<int> pd(n), Ds(n);
+    for (int j = 0; j < n; ++j) {
+      Ds[j] = tensor_dims[P.sites[legs[j].first].tensor][1 + legs[j].second];
+      pd[j] = Ds[j] * Ds[j];
+    }
+    std::vector<int64_t> capb(n + 1, 1);
+    for (int j = 1; j < n; ++j) {
+      int64_t lp = 1, rp = 1;
+      for (int u = 0; u < j; ++u) lp = std::min<int64_t>(lp * pd[u], 1 << 30);
+      for (int u = j; u < n; ++u) rp = std::min<int64_t>(rp * pd[u], 1 << 30);
+      capb[j] = std::min<int64_t>(std::min<int64_t>(opt.chi, lp), rp);
+    }
+    for (int j = 0; j < n; ++j) {
+      msg.off[m].push_back(moff);
+      msg.bl[m].push_back(int(capb[j]));
+      msg.br[m].push_back(int(capb[j + 1]));
+      msg.P[m].push_back(pd[j]);
+      msg.D[m].push_back(Ds[j]);
+      moff += (capb[j] * pd[j] * capb[j + 1] + 7) / 8 * 8;
+    }
+  }
+  msg.size = moff;
+  n_scalars = 1024 + nm + 8;
+}
+
+std::pair<Ref, Ref> Compiler::ensure_smat(int tensor, const std::vector<int>& in_slots,
+                                          const std::vector<int>& out_slots, bool open) {
+  SiteMatKey k{tensor, in_slots, out_slots, open};
+  auto it = smat.find(k);
+  if (it != smat.end()) return it->second;
+  const std::vector<int>& td = tensor_dims[tensor];
+  int64_t len = prod(td);
+  Ref ket{RG_SMAT, smat_size};
+  smat_size += (len + 7) / 8 * 8;
+  Ref bra{RG_SMAT, smat_size};
+  smat_size += (len + 7) / 8 * 8;
+  smat[k] = {ket, bra};
+  // ket: [k_in..., p, k_out...]; bra: [p, b_in..., b_out...] or, for an open
+  // site, [b_in..., p', b_out...] (complex conjugated)
+  std::vector<int> pk, pb;
+  for (int l : in_slots) pk.push_back(1 + l);
+  pk.push_back(0);
+  for (int l : out_slots) pk.push_back(1 + l);
+  if (!open) pb.push_back(0);
+  for (int l : in_slots) pb.push_back(1 + l);
+  if (open) pb.push_back(0);
+  for (int l : out_slots) pb.push_back(1 + l);
+  Ref src{RG_SITE, tensor_off[tensor]};
+  auto mk = [&](Ref dst, const std::vector<int>& pm, int conj) {
+    Op op;
+    op.type = OPK_PERM;
+    op.a = src; op.b = dst;
+    int n = int(td.size());
+    std::vector<int64_t> stv(n, 1);
+    for (int q = n - 2; q >= 0; --q) stv[q] = stv[q + 1] * td[q + 1];
+    op.i[0] = n; op.i[1] = conj;
+    for (int q = 0; q < n; ++q) { op.i[2 + q] = td[pm[q]]; op.i[18 + q] = stv[pm[q]]; }
+    prep_ops.push_back(op);
+  };
+  mk(ket, pk, 0);
+  mk(bra, pb, 1);
+  return smat[k];
+}
+
+bool Compiler::build_sweep(int parity, Plan* out) {
+  const Problem& P = prob;
+  int nm = int(P.msg_keys.size());
+  int rin = parity ? RG_MSG1 : RG_MSG0;
+  int rout = parity ? RG_MSG0 : RG_MSG1;
+  out->lanes.assign(nm, {});
+  out->nlanes = nm;
+  if (int(lane_size.size()) < 2 * nm) lane_size.resize(2 * nm, 0);
+  for (int m = 0; m < nm; ++m) {
+    Lane L(this, m, &out->lanes[m]);
+    int blk, face;
+    std::vector<std::pair<int, int>> recv;
+    P.update_target(m, &blk, &face, &recv);
+    std::vector<std::pair<int, int>> fin;
+    int center = 0;
+    L.stage = 0;
+    // the sketch keys do not depend on the sweep: the truncated map is the
+    // same at every sweep, so BlockBP can reach its fixed point
+    std::vector<CSite> ch = L.run_sweep(blk, face, {}, rin, {1, uint64_t(m), 0}, false, -1, nullptr,
+                                        &fin, &center);
+    if (!L.err.empty()) { error = L.err; return false; }
+    // order the result like the receiving face
+    L.stage = 1;
+    L.reset_scratch();
+    L.at(1, 0, 0);
+    if (fin == recv) {
+    } else {
+      std::vector<std::pair<int, int>> rv(fin.rbegin(), fin.rend());
+      if (rv != recv) { error = "final chain does not match the receiving face"; return false; }
+      L.reverse_chain(ch, center);
+    }
+    L.at(1, 1, 0);
+    L.right_canonical(ch, center);
+    for (size_t j = 0; j < ch.size(); ++j) {
+      if (ch[j].r > msg.br[L.C->prob.stored_slot_of_update(m)][j] && opt.chi_env > 0) {
+        error = "bond above the message cap (chi_env > chi is not supported)";
+        return false;
+      }
+    }
+    int slot = P.stored_slot_of_update(m);
+    // pad into the stored message (caps), fix the phase, then the distance
+    L.at(1, 2, 0);
+    std::vector<CSite> stored;
+    for (size_t j = 0; j < ch.size(); ++j) {
+      if (ch[j].l > msg.bl[slot][j] || ch[j].r > msg.br[slot][j]) {
+        error = "message bond above its cap";
+        return false;
+      }
+      Ref dst{rout, msg.off[slot][j]};
+      L.pad(ch[j].buf, dst, ch[j].l, ch[j].P, ch[j].r, msg.bl[slot][j], msg.br[slot][j], 0, 0, 0);
+      CSite cs = ch[j];
+      cs.buf = dst; cs.l = msg.bl[slot][j]; cs.r = msg.br[slot][j];
+      stored.push_back(cs);
+    }
+    L.at(1, 3, 0);
+    L.phase_fix(stored);
+    // convergence distance ||new - old|| from the direct-sum MPS and a QR sweep
+    L.at(1, 4, 0);
+    int n = int(stored.size());
+    if (n == 1) {
+      Ref X = L.scratch(int64_t(stored[0].l) * stored[0].P * stored[0].r);
+      L.pad(stored[0].buf, X, 1, stored[0].P, 1, 1, 1, 0, 0, 0);
+      L.pad(Ref{rin, msg.off[slot][0]}, X, 1, stored[0].P, 1, 1, 1, 0, 0, 2, -1.0);
+      L.norm(X, stored[0].P, -1, err_slot(slot));
+    } else {
+      Ref Rm;
+      int64_t rl = 1;
+      for (int j = 0; j < n; ++j) {
+        int lN = msg.bl[slot][j], rN = msg.br[slot][j], Pj = msg.P[slot][j];
+        int l2 = (j == 0) ? 1 : 2 * lN, r2 = (j == n - 1) ? 1 : 2 * rN;
+        Ref X = L.scratch(int64_t(l2) * Pj * r2);
+        Ref newb = stored[j].buf, oldb{rin, msg.off[slot][j]};
+        L.pad(newb, X, lN, Pj, rN, l2, r2, 0, 0, 0);
+        L.pad(oldb, X, lN, Pj, rN, l2, r2, (j == 0) ? 0 : lN, (j == n - 1) ? 0 : rN, 1,
+              j == 0 ? -1.0 : 1.0);
+        Ref Mx;
+        int64_t ml;
+        if (j == 0) { Mx = X; ml = l2; }
+        else {
+          Mx = L.scratch(rl * Pj * r2);
+          L.gemm(Rm, X, Mx, rl, int64_t(Pj) * r2, l2, l2, int64_t(Pj) * r2, int64_t(Pj) * r2,
+                 OP_N, OP_N, PREC_FP64);
+          ml = rl;
+        }
+        if (j == n - 1) {
+          L.norm(Mx, ml * Pj * r2, -1, err_slot(slot));
+        } else {
+          int64_t mm = ml * Pj, nn = r2, k = std::min(mm, nn);
+          Ref Qx = L.scratch(mm * k);
+          Rm = L.scratch(k * nn);
+          L.qr(Mx, mm, nn, nn, 0, Qx, Rm);
+          rl = k;
+        }
+      }
+    }
+    if (!L.err.empty()) { error = L.err; return false; }
+    lane_size[2 * m] = std::max(lane_size[2 * m], L.chain_top);
+    lane_size[2 * m + 1] = std::max(lane_size[2 * m + 1], L.scratch_max);
+  }
+  return true;
+}
+
+bool Compiler::build_expect(int parity, const std::vector<std::pair<int, int>>& bonds,
+                            Plan* out, std::vector<std::vector<int>>* carry_order,
+                            std::vector<int64_t>* rho_off) {
+  const Problem& P = prob;
+  int rin = parity ? RG_MSG1 : RG_MSG0;
+  int nb = int(bonds.size());
+  out->lanes.assign(nb, {});
+  out->nlanes = nb;
+  if (int(lane_size.size()) < 2 * nb) lane_size.resize(2 * nb, 0);
+  carry_order->assign(nb, {});
+  rho_off->assign(nb, 0);
+  for (int bi = 0; bi < nb; ++bi) {
+    int i = bonds[bi].first, j = bonds[bi].second;
+    Lane L(this, bi, &out->lanes[bi]);
+    int a = P.block_of[i], b = P.block_of[j];
+    // closing face: first face carrying a real message, else the first face
+    auto expect_face = [&](int blk, int skip) {
+      const std::vector<Face>& F = P.faces[blk];
+      for (size_t n = 0; n < F.size(); ++n)
+        if (int(n) != skip && F[n].keytype != FACE_OUTSIDE) return int(n);
+      for (size_t n = 0; n < F.size(); ++n)
+        if (int(n) != skip) return int(n);
+      return 0;
+    };
+    std::vector<std::pair<int, int>> fin;
+    int center = 0, cblk, cface;
+    std::vector<CSite> ch;
+    L.stage = 0;
+    if (a == b) {
+      cblk = a;
+      cface = expect_face(a, -1);
+      ch = L.run_sweep(a, cface, {i, j}, rin, {2, uint64_t(bi), 0}, false, -1, nullptr, &fin,
+                       &center);
+    } else {
+      int fa = P.face_index(a, FACE_BLOCK, b), fb = P.face_index(b, FACE_BLOCK, a);
+      std::vector<CSite> c1 = L.run_sweep(a, fa, {i}, rin, {2, uint64_t(bi), 0}, false, -1,
+                                          nullptr, &fin, &center);
+      if (!L.err.empty()) { error = L.err; return false; }
+      std::vector<std::pair<int, int>> recv;
+      for (auto& sl : P.faces[b][fb].legs) {
+        const Link& k = P.links[sl.first][sl.second];
+        recv.push_back({k.s2, k.l2});
+      }
+      L.stage = 1;
+      L.reset_scratch();
+      L.at(1, 0, 0);
+      if (fin != recv) {
+        std::vector<std::pair<int, int>> rv(fin.rbegin(), fin.rend());
+        if (rv != recv) { error = "carried message does not match the receiving face"; return false; }
+        L.reverse_chain(c1, center);
+      }
+      L.right_canonical(c1, center);
+      cblk = b;
+      cface = expect_face(b, fb);
+      L.stage = 2;
+      ch = L.run_sweep(b, cface, {j}, rin, {2, uint64_t(bi), 1}, false, fb, &c1, &fin, &center);
+    }
+    if (!L.err.empty()) { error = L.err; return false; }
+    // close with the incoming message of the closing face
+    L.stage = 3;
+    L.reset_scratch();
+    L.at(3, 0, 0);
+    const std::vector<Face>& F = P.faces[cblk];
+    std::vector<std::pair<int, int>> legs = F[cface].legs;
+    bool rev;
+    if (fin == legs) rev = false;
+    else {
+      std::vector<std::pair<int, int>> rv(legs.rbegin(), legs.rend());
+      if (fin != rv) { error = "final chain does not match the closing face"; return false; }
+      rev = true;
+    }
+    int slot = P.incoming_msg(cblk, cface);
+    int nl = int(legs.size());
+    std::vector<CSite> msgs(nl);
+    for (int q = 0; q < nl; ++q) {
+      CSite cs;
+      int D = tensor_dims[P.sites[legs[q].first].tensor][1 + legs[q].second];
+      cs.D = D;
+      if (slot < 0) { cs.buf = Ref{RG_CONST, 0}; cs.l = cs.P = cs.r = 1; }
+      else {
+        cs.buf = Ref{rin, msg.off[slot][q]};
+        cs.l = msg.bl[slot][q]; cs.P = msg.P[slot][q]; cs.r = msg.br[slot][q];
+      }
+      msgs[q] = cs;
+    }
+    if (rev) {
+      int dummy = 0;
+      L.reverse_chain(msgs, dummy);
+    }
+    // L[c, d, X]: start from the scalar 1
+    Ref Lb{RG_CONST, 0};
+    int64_t Lc = 1, Ld = 1, LX = 1;
+    std::vector<int> order;
+    for (size_t q = 0; q < ch.size(); ++q) {
+      const CSite& A = ch[q];
+      const CSite& M = msgs[q];
+      int64_t Qd = ipow(opt.d * opt.d, int(A.carries.size()));
+      int64_t I = A.P / Qd;
+      if (I != M.P || A.l != Lc || M.l != Ld) { error = "closing shapes mismatch"; return false; }
+      // S1[(d X), (I q e)] = L^T[(d X), c] A[c, (I q e)]
+      Ref S1 = L.scratch(Ld * LX * A.P * A.r);
+      L.gemm(Lb, A.buf, S1, Ld * LX, int64_t(A.P) * A.r, Lc, Ld * LX, int64_t(A.P) * A.r,
+             int64_t(A.P) * A.r, OP_T, OP_N, PREC_FP64);
+      Ref S1p = L.scratch(Ld * LX * A.P * A.r);
+      L.perm(S1, S1p, {int(Ld), int(LX), int(I), int(Qd), A.r}, {1, 3, 4, 0, 2});
+      Ref S2 = L.scratch(LX * Qd * A.r * M.r);
+      L.gemm(S1p, M.buf, S2, LX * Qd * A.r, M.r, Ld * I, Ld * I, M.r, M.r, OP_N, OP_N,
+             PREC_FP64);
+      Ref Ln = L.scratch(LX * Qd * A.r * M.r);
+      L.perm(S2, Ln, {int(LX), int(Qd), A.r, M.r}, {2, 3, 0, 1});
+      Lb = Ln;
+      Lc = A.r; Ld = M.r; LX *= Qd;
+      for (int c : A.carries) order.push_back(c);
+    }
+    if (Lc != 1 || Ld != 1) { error = "closing contraction left open bonds"; return false; }
+    int64_t roff = rho_size;
+    rho_size += (LX + 7) / 8 * 8;
+    L.pad(Lb, Ref{RG_RHO, roff}, 1, int(LX), 1, 1, 1, 0, 0, 0);
+    (*carry_order)[bi] = order;
+    (*rho_off)[bi] = roff;
+    if (!L.err.empty()) { error = L.err; return false; }
+    lane_size[2 * bi] = std::max(lane_size[2 * bi], L.chain_top);
+    lane_size[2 * bi + 1] = std::max(lane_size[2 * bi + 1], L.scratch_max);
+  }
+  return true;
+}
+
+}  // namespace pn

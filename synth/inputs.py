@@ -222,3 +222,19 @@ def tree_peps(n_sites, D, seed, d=2, max_degree=4):
         deg[s] += 1
     ts = [cgauss(rng, (d,) + (D,) * deg[s]) for s in range(n_sites)]
     return edges, ts
+
+
+def random_messages(shapes, seed):
+    """Seeded generic messages for a handle's static message shapes: for each
+    message a list of (l, P, r) site shapes; every site i.i.d. complex
+    Gaussian.  Used as a non-degenerate starting point."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for sites in shapes:
+        A = [cgauss(rng, sh) for sh in sites]
+        nrm = 1.0
+        for x in A:
+            nrm *= np.linalg.norm(x)
+        A[0] = A[0] / max(nrm, 1e-300)
+        out.append(A)
+    return out

@@ -1,0 +1,119 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Tolerances: 1e-10 on messages and expectation
+values in FP64 (the oracle and the kernels differ only in rounding order),
+1e-5 for FP32 / split-BF16 contraction arithmetic."""
+import numpy as np
+import pytest
+
+from oracle import bubble as bb
+from synth import inputs as syn
+
+from gpu_cases import (message_diff, oracle_bond_energies, oracle_for, problem,
+                       set_random_messages)
+
+pytestmark = pytest.mark.gpu
+
+pn = pytest.importorskip("paper_2603_13304_amd")
+
+
+def _run(kind, ts, sweeps, randmsg=None, graph=False, **kw):
+    P, desc = problem(kind, **kw)
+    g = pn.PepsNet(desc, ts)
+    g.use_graph(graph)
+    O = oracle_for(P, ts, kw["chi"], kw.get("trunc", 0), kw.get("q", 2), kw.get("p", 8),
+                   kw.get("seed", 0))
+    if randmsg is not None:
+        set_random_messages(g, O, P, randmsg)
+    bb.DEGENERATE.clear()
+    bb.GAUGE_AMBIGUOUS.clear()
+    for it in range(sweeps):
+        done, err, _ = g.blockbp_sweep(1, 0.0)
+        eo = O.sweep()
+        assert done == 1
+        print(f"{kind} sweep {it}: gpu err {err:.15g} oracle {eo:.15g}", flush=True)
+        if not bb.DEGENERATE:
+            assert abs(err - eo) < 1e-10 * max(1.0, eo)
+    return P, g, O
+
+
+def _check_expect(P, g, O, tol, hermitian=True):
+    rho, ss, e = g.blockbp_expect()
+    bonds = g.bonds()
+    ref = oracle_bond_energies(O, bonds)
+    n_cmp = 0
+    for b, r in enumerate(ref):
+        if r is None:
+            continue
+        assert abs(ss[b] - r) < tol, (b, bonds[b], ss[b], r)
+        n_cmp += 1
+        if hermitian:
+            # Hermitian messages (identity start) give a Hermitian rho
+            assert np.allclose(rho[b], rho[b].conj().T, atol=1e-8 * np.abs(rho[b]).max())
+    assert n_cmp >= len(ref) - 2
+    return ss, e
+
+
+def test_finite_cfg1_t1_fp64():
+    """4x4-cell open patch, 2x2-cell blocks, D=2, chi=4 (truncated
+    boundary chains), identity start."""
+    ts = syn.finite_patch_tensors(4, 4, 2, seed=1)
+    P, g, O = _run("finite", ts, 3, Lx=4, Ly=4, bLx=2, bLy=2, D=2, chi=4)
+    assert message_diff(g, O, P) < 1e-10
+    _check_expect(P, g, O, 1e-10)
+
+
+def test_hex_n2_t1_fp64():
+    ts = syn.random_unit_cell(2, seed=3)
+    P, g, O = _run("infinite", ts, 4, N=2, D=2, chi=8)
+    assert message_diff(g, O, P) < 1e-10
+    ss, e = _check_expect(P, g, O, 1e-10)
+    assert abs(e - sum(ss) / 3) < 1e-14
+
+
+def test_hex_n2_t2_fp64_random_start():
+    ts = syn.random_unit_cell(2, seed=3)
+    P, g, O = _run("infinite", ts, 3, randmsg=11, N=2, D=2, chi=8, trunc=1, q=1, p=2, seed=5)
+    assert not bb.GAUGE_AMBIGUOUS
+    assert message_diff(g, O, P) < 1e-10
+    _check_expect(P, g, O, 1e-10, hermitian=False)
+
+
+def test_hex_n3_cfg2_shape_t2_fp64():
+    """The benchmark workload's shape: hexagonal block N=3 (57 sites), D=3,
+    chi=16, simple-update tensors; T2 (q=2, p=8), one sweep from a seeded
+    generic start."""
+    ts = syn.simple_update_cell(3, seed=2)
+    P, g, O = _run("infinite", ts, 1, randmsg=12, N=3, D=3, chi=16, trunc=1, q=2, p=8, seed=7)
+    assert message_diff(g, O, P) < 1e-10
+
+
+def test_graph_replay_equals_direct_launches():
+    ts = syn.random_unit_cell(2, seed=4)
+    P, desc = problem("infinite", N=2, D=2, chi=8)
+    a = pn.PepsNet(desc, ts)
+    b = pn.PepsNet(desc, ts)
+    b.use_graph(True)
+    for _ in range(4):
+        ea = a.blockbp_sweep(1, 0.0)[1]
+        eb = b.blockbp_sweep(1, 0.0)[1]
+        assert ea == eb
+    for x, y in zip(a.get_messages(), b.get_messages()):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_reduced_precision_contraction(prec):
+    """FP32 and split-BF16 (three products, FP32 accumulation) contraction
+    GEMMs; QR, SVD and normalisation in FP64.  Energy per site within 1e-5
+    of the FP64 oracle after converging (D=3, chi=16, N=2)."""
+    ts = syn.simple_update_cell(3, seed=2)
+    P, desc = problem("infinite", N=2, D=3, chi=16, prec=prec)
+    g = pn.PepsNet(desc, ts)
+    g.blockbp_sweep(25, 1e-9)
+    O = oracle_for(P, ts, 16, 0, 2, 8, 0)
+    O.run(tol=1e-9, max_sweeps=25)
+    _, ss, e = g.blockbp_expect()
+    eo = O.energy_per_site()
+    print(f"precision {prec}: E gpu {e:.12f} oracle {eo:.12f} diff {abs(e - eo):.3e}")
+    assert abs(e - eo) < 1e-5

@@ -1,0 +1,127 @@
+"""Host-side checks of the HIP library (no GPU needed): it loads, exports every
+symbol declared in include/pepsnet.h, and its own C++ geometry produces the
+same faces and sweep orders as the oracle's independent implementation."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import geometry as geo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pepsnet.h")
+
+pn = pytest.importorskip("paper_2603_13304_amd.binding")
+
+
+def _lib():
+    try:
+        return pn.load_library()
+    except ImportError as e:
+        pytest.fail(f"library not built: {e}")
+
+
+def test_exports_every_declared_symbol():
+    lib = _lib()
+    text = open(HEADER).read()
+    names = re.findall(r"^\s*(?:int32_t|void\s*\*|void|const char\s*\*)\s*(\w+)\s*\(", text, re.M)
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+        ctypes.cast(getattr(lib, n), ctypes.c_void_p)
+
+
+def _faces_from_lib(desc, b):
+    buf = pn.describe(desc, 0, b)
+    nf, o, faces = int(buf[0]), 1, []
+    for _ in range(nf):
+        kt, key, nl = int(buf[o]), int(buf[o + 1]), int(buf[o + 2])
+        o += 3
+        legs = [(int(buf[o + 2 * k]), int(buf[o + 2 * k + 1])) for k in range(nl)]
+        o += 2 * nl
+        faces.append((kt, key, legs))
+    return faces
+
+
+def _sched_from_lib(desc, b, f, opens=()):
+    buf = pn.describe(desc, 1, b, f, opens)
+    n, o, steps = int(buf[0]), 1, []
+    for _ in range(n):
+        site, pos, r, s = (int(x) for x in buf[o:o + 4])
+        o += 4
+        ins = [int(x) for x in buf[o:o + r]]
+        o += r
+        outs = [int(x) for x in buf[o:o + s]]
+        o += s
+        op, ab = int(buf[o]), int(buf[o + 1])
+        o += 2
+        steps.append((site, pos, ins, outs, bool(op), ab))
+    nfin = int(buf[o])
+    o += 1
+    fin = [(int(buf[o + 2 * k]), int(buf[o + 2 * k + 1])) for k in range(nfin)]
+    return steps, fin
+
+
+def _oracle_sched(P, b, f, opens=()):
+    steps, fin = geo.sweep_schedule(P.net, P.blocks[b], P.faces[b], f, opens)
+    ab = {None: -1, "right": 0, "left": 1}
+    return [(st["site"], st["pos"], st["in_slots"], st["out_slots"], st["open"],
+             ab[st["absorb"]]) for st in steps], fin
+
+
+def _oracle_faces(P, b):
+    out = []
+    for f in P.faces[b]:
+        k = f["key"]
+        if k[0] == "hex":
+            kt, key = 2, k[1]
+        elif k[0] == "block":
+            kt, key = 0, k[1]
+        else:
+            kt, key = 1, k[1] * 8 + k[2]
+        out.append((kt, key, [tuple(x) for x in f["legs"]]))
+    return out
+
+
+@pytest.mark.parametrize("N", [2, 3, 4, 5])
+def test_hex_geometry_matches_oracle(N):
+    _lib()
+    desc = pn.make_desc(pn.BBP_KAGOME_INF_HEX, D=2, chi=4, hex_N=N)
+    P = geo.HexProblem(N)
+    summ = pn.describe(desc, 2)
+    assert list(summ[:3]) == [len(P.net.sites), 1, 6]
+    assert _faces_from_lib(desc, 0) == _oracle_faces(P, 0)
+    for f in range(6):
+        assert _sched_from_lib(desc, 0, f) == _oracle_sched(P, 0, f)
+    bonds = P.central_bonds()
+    for i, j in bonds[:2]:
+        assert _sched_from_lib(desc, 0, 0, (i, j)) == _oracle_sched(P, 0, 0, (i, j))
+
+
+def test_finite_geometry_matches_oracle():
+    _lib()
+    desc = pn.make_desc(pn.BBP_KAGOME_OPEN, D=2, chi=4, Lx=4, Ly=4, bLx=2, bLy=2)
+    P = geo.FiniteProblem(4, 4, 2, 2)
+    assert list(pn.describe(desc, 2)) == [48, 4, 10, 81]
+    for b in range(4):
+        assert _faces_from_lib(desc, b) == _oracle_faces(P, b)
+        for f in range(len(P.faces[b])):
+            if P.faces[b][f]["key"][0] == "block":
+                assert _sched_from_lib(desc, b, f) == _oracle_sched(P, b, f)
+
+
+def test_bad_descriptors_are_rejected():
+    lib = _lib()
+    desc = pn.make_desc(pn.BBP_KAGOME_INF_HEX, D=2, chi=4, hex_N=1)
+    with pytest.raises(pn.PepsnetError) as e:
+        pn.describe(desc, 2)
+    assert e.value.code == -5
+    desc = pn.make_desc(pn.BBP_KAGOME_OPEN, D=2, chi=4, Lx=3, Ly=4, bLx=2, bLy=2)
+    with pytest.raises(pn.PepsnetError):
+        pn.describe(desc, 2)
+    # create validates before touching the device
+    desc = pn.make_desc(pn.BBP_KAGOME_INF_HEX, D=2, chi=4, hex_N=2, chi_env=8)
+    h = ctypes.c_void_p()
+    rc = lib.pepsnet_create(ctypes.byref(desc), None, 0, ctypes.byref(h))
+    assert rc == -1 and not h.value
