@@ -131,6 +131,17 @@ int32_t pepsnet_use_graph(pepsnet_t h, int32_t on);
 int32_t pepsnet_sweep_stats(pepsnet_t h, double* contraction_flops, double* gemm_flops,
                             int64_t* launches);
 
+/* Per-kernel live timing: run n_sweeps sweeps with HIP events recorded on
+ * the handle's stream around every launch and accumulate, per kernel slot
+ * (slot = kind * 3 + precision, kinds: 0 GEMM, 1 transpose, 2 QR, 3 Jacobi,
+ * 4 sketch, 5 norm, 6 pad, 7 message phase, 8 split gauge), the elapsed
+ * milliseconds, the launch count, and the algorithmic flops (8 per complex
+ * multiply-add) and bytes of the launches.  Arrays hold
+ * PEPSNET_PROFILE_SLOTS entries; NULL skips an output. */
+#define PEPSNET_PROFILE_SLOTS 27
+int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_t* launches,
+                               double* flops, double* bytes);
+
 void pepsnet_destroy(pepsnet_t h);
 const char* pepsnet_last_error(void);
 

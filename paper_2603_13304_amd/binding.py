@@ -64,6 +64,7 @@ def load_library():
         "pepsnet_timing": (i32, [vp, i32, P(dbl), P(i64)]),
         "pepsnet_use_graph": (i32, [vp, i32]),
         "pepsnet_sweep_stats": (i32, [vp, P(dbl), P(dbl), P(i64)]),
+        "pepsnet_profile_sweeps": (i32, [vp, i32, P(dbl), P(i64), P(dbl), P(dbl)]),
         "pepsnet_destroy": (None, [vp]),
         "pepsnet_last_error": (C.c_char_p, []),
         "pepsnet_describe": (i32, [P(Desc), i32, i32, i32, i32, P(i32), P(i32), i64, P(i64)]),
@@ -211,3 +212,27 @@ class PepsNet:
         cf, gf, nl = C.c_double(0.0), C.c_double(0.0), C.c_int64(0)
         _check(self.lib.pepsnet_sweep_stats(self.h, C.byref(cf), C.byref(gf), C.byref(nl)))
         return cf.value, gf.value, nl.value
+
+PROFILE_KINDS = ["gemm", "transpose", "qr", "jacobi", "sketch", "norm", "pad", "msg_phase",
+                 "split_gauge"]
+PREC_NAMES = ["fp64", "fp32", "bf16x3"]
+
+
+def profile_sweeps(net, n_sweeps):
+    """Per-kernel HIP-event timing of ``n_sweeps`` sweeps: dict slot name ->
+    (ms, launches, flops, bytes)."""
+    n = 27
+    ms = np.zeros(n)
+    nl = np.zeros(n, np.int64)
+    fl = np.zeros(n)
+    by = np.zeros(n)
+    _check(net.lib.pepsnet_profile_sweeps(net.h, n_sweeps, _dptr(ms),
+                                          nl.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          _dptr(fl), _dptr(by)))
+    out = {}
+    for k in range(n):
+        if nl[k]:
+            kind, prec = PROFILE_KINDS[k // 3], k % 3
+            name = f"{kind}_{PREC_NAMES[prec]}" if kind == "gemm" else kind
+            out[name] = (float(ms[k]), int(nl[k]), float(fl[k]), float(by[k]))
+    return out

@@ -47,6 +47,8 @@ struct LaunchRec {
   dim3 grid;
   size_t lds = 0;
   double gemm_flops = 0.0, contraction_flops = 0.0;
+  double flops = 0.0;    // algorithmic flops of the launch (8 per complex MAC)
+  double bytes = 0.0;    // algorithmic bytes moved (operands read once, results written once)
 };
 
 struct Compiled {
@@ -145,6 +147,8 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             mN = std::max<int64_t>(mN, g.N);
             double f = 8.0 * double(g.M) * double(g.N) * double(g.K);
             rec.gemm_flops += f;
+            rec.flops += f;
+            rec.bytes += 16.0 * (double(g.M) * g.K + double(g.K) * g.N + double(g.M) * g.N);
             if (op->i[9]) rec.contraction_flops += f;
             v.push_back(g);
           }
@@ -167,6 +171,7 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
               p.total *= p.dims[k];
             }
             mt = std::max(mt, p.total);
+            rec.bytes += 32.0 * double(p.total);
             v.push_back(p);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
@@ -175,15 +180,23 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
         }
         case OPK_QR: {
           std::vector<QrDesc> v;
+          int64_t lds_elems = 0;
           for (const Op* op : ops) {
             QrDesc q;
             q.A = resolve(h, op->a); q.work = resolve(h, op->b);
             q.Q = resolve(h, op->c); q.R = resolve(h, op->d);
             q.m = int(op->i[0]); q.n = int(op->i[1]); q.lda = int(op->i[2]); q.conjT = int(op->i[3]);
+            double m = q.m, n = q.n, k = std::min(q.m, q.n);
+            // Householder R (complex: 8 flops per MAC) plus explicit Q
+            rec.flops += 8.0 * 2.0 * (m * n * k - (m + n) * k * k / 2.0 + k * k * k / 3.0);
+            rec.bytes += 16.0 * (m * n + m * k + k * n);
+            int64_t need = int64_t(q.m) * (q.n + std::min(q.m, q.n));
+            if (need <= QR_LDS_MAX) lds_elems = std::max(lds_elems, need);
             v.push_back(q);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
           rec.grid = dim3(unsigned(v.size()));
+          rec.lds = size_t(lds_elems) * sizeof(cplx);
           break;
         }
         case OPK_JACOBI: {
@@ -195,6 +208,10 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             jd.sigma = reinterpret_cast<double*>(resolve(h, op->d));
             jd.k = int(op->i[0]);
             if (jd.k <= JAC_LDS_MAX) klds = std::max(klds, jd.k);
+            // one sweep of k(k-1)/2 rotations, each 3 dot products and 2
+            // column updates of A and J (count of one sweep, the minimum)
+            rec.flops += 8.0 * 0.5 * jd.k * (jd.k - 1.0) * 7.0 * jd.k;
+            rec.bytes += 16.0 * 3.0 * double(jd.k) * jd.k;
             v.push_back(jd);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
@@ -212,6 +229,7 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             o.prefix = op->key;
             o.last_tag = op->i[2] ? h->scal + Compiler::kSweepSlot : nullptr;
             mt = std::max<int64_t>(mt, int64_t(o.n) * o.k);
+            rec.bytes += 16.0 * double(o.n) * o.k;
             v.push_back(o);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
@@ -224,6 +242,7 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             NormDesc nd;
             nd.x = resolve(h, op->a);
             nd.len = op->i[0];
+            rec.bytes += 32.0 * double(nd.len);
             nd.logscale = op->s0.off >= 0 ? h->scal + op->s0.off : nullptr;
             nd.norm_out = op->s1.off >= 0 ? h->scal + op->s1.off : nullptr;
             v.push_back(nd);
@@ -243,6 +262,7 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             p.off_l = int(op->i[5]); p.off_r = int(op->i[6]); p.mode = int(op->i[7]);
             p.sign = op->x[0];
             mt = std::max<int64_t>(mt, int64_t(p.l2) * p.P * p.r2);
+            rec.bytes += 16.0 * (double(p.l1) * p.P * p.r1 + double(p.l2) * p.P * p.r2);
             v.push_back(p);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
@@ -305,7 +325,7 @@ hipError_t launch(pepsnet_s* h, const LaunchRec& r) {
       hipLaunchKernelGGL(k_permute, r.grid, blk, 0, h->stream, (const PermDesc*)d);
       break;
     case OPK_QR:
-      hipLaunchKernelGGL(k_qr, r.grid, blk, 0, h->stream, (const QrDesc*)d);
+      hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, h->stream, (const QrDesc*)d);
       break;
     case OPK_JACOBI:
       hipLaunchKernelGGL(k_jacobi, r.grid, blk, r.lds, h->stream, (const JacobiDesc*)d);
@@ -517,6 +537,8 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
     return fail(BBP_ENOMEM, "pinned host buffer");
   PN_HIP(hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(2 * JAC_LDS_MAX * JAC_LDS_MAX * sizeof(cplx))));
+  PN_HIP(hipFuncSetAttribute((const void*)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(QR_LDS_MAX * sizeof(cplx))));
   PN_HIP(hipEventCreate(&h->ev0));
   PN_HIP(hipEventCreate(&h->ev1));
   PN_HIP(hipStreamSynchronize(h->stream));
@@ -695,6 +717,49 @@ int32_t pepsnet_sweep_stats(pepsnet_t h, double* cflops, double* gflops, int64_t
   if (cflops) *cflops = h->sweep[0].contraction_flops;
   if (gflops) *gflops = h->sweep[0].gemm_flops;
   if (launches) *launches = int64_t(h->sweep[0].launches.size());
+  return BBP_OK;
+}
+
+int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_t* launches,
+                               double* flops, double* bytes) {
+  if (!h || n_sweeps <= 0) return fail(BBP_EINVAL, "bad arguments");
+  const int nk = PEPSNET_PROFILE_SLOTS;
+  std::vector<double> tms(nk, 0.0), tfl(nk, 0.0), tby(nk, 0.0);
+  std::vector<int64_t> tl(nk, 0);
+  for (int s = 0; s < n_sweeps; ++s) {
+    Compiled& c = h->sweep[h->parity];
+    std::vector<hipEvent_t> ev(2 * c.launches.size());
+    for (auto& e : ev) PN_HIP(hipEventCreate(&e));
+    h->pinned[0] = double(h->sweeps_total);
+    PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
+    for (size_t i = 0; i < c.launches.size(); ++i) {
+      PN_HIP(hipEventRecord(ev[2 * i], h->stream));
+      hipError_t e = launch(h, c.launches[i]);
+      if (e != hipSuccess) return fail(BBP_EDEVICE, hipGetErrorString(e));
+      PN_HIP(hipEventRecord(ev[2 * i + 1], h->stream));
+    }
+    PN_HIP(hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i < c.launches.size(); ++i) {
+      float x = 0.0f;
+      PN_HIP(hipEventElapsedTime(&x, ev[2 * i], ev[2 * i + 1]));
+      const LaunchRec& r = c.launches[i];
+      int slot = r.type * 3 + (r.type == OPK_GEMM ? r.prec : 0);
+      tms[slot] += x;
+      tl[slot] += 1;
+      tfl[slot] += r.flops;
+      tby[slot] += r.bytes;
+    }
+    for (auto& e : ev) hipEventDestroy(e);
+    h->parity ^= 1;
+    h->sweeps_total += 1;
+  }
+  for (int k = 0; k < nk; ++k) {
+    if (ms) ms[k] = tms[k];
+    if (launches) launches[k] = tl[k];
+    if (flops) flops[k] = tfl[k];
+    if (bytes) bytes[k] = tby[k];
+  }
   return BBP_OK;
 }
 

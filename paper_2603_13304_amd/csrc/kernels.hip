@@ -229,150 +229,156 @@ __device__ double block_sum(double v, double* sh) {
 
 // --------------------------------------------------------------------- QR
 // Householder reflections H = I - tau v v^H with v[j] = x[j] - alpha,
-// alpha = -e^{i arg x_j} ||x||, stored in the lower part of the work matrix.
-__global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
-  const QrDesc d = descs[blockIdx.x];
+// alpha = -e^{i arg x_j} ||x||.  Working copies are column-major (W[c*m+i],
+// Qt[c*m+i]) in LDS when m*(n+k) <= QR_LDS_MAX, else in the work buffer
+// (W) and a column-major staging area behind it (Qt).  Column operations use
+// one 16-lane group per column, 16 columns at a time.
+constexpr int QR_LDS_MAX = 8192;   // complex elements (128 KB)
+
+// Sum over the 16 lanes of a DPP row, result in every lane: xor-1 and xor-2
+// quad permutations, then half-row and row mirrors (VALU moves, no LDS).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double group16_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
+  return v;
+}
+
+// W and Qt point into LDS (INLDS) or into the work buffer; keeping the two
+// cases apart lets the compiler use ds_read/ds_write for LDS data.
+template <bool INLDS>
+__device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, double* tau_s,
+                                        cplx* phs, cplx* alpha_s, double (*part_s)[4]) {
   const int m = d.m, n = d.n, k = m < n ? m : n;
-  cplx* W = d.work;
-  __shared__ double sh[8];
-  __shared__ double tau_s[256];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
   for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
     int r = (int)(e / n), c = (int)(e % n);
     cplx v;
     if (d.conjT) { v = d.A[(int64_t)c * d.lda + r]; v.im = -v.im; }
     else v = d.A[(int64_t)r * d.lda + c];
-    W[e] = v;
+    W[(int64_t)c * m + r] = v;
   }
   __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
   for (int j = 0; j < k; ++j) {
+    cplx* wj = W + (int64_t)j * m;
+    // column norm: wave sums, one barrier, every thread finishes the sum
     double part = 0.0;
-    for (int i = j + tid; i < m; i += 256) {
-      cplx x = W[(int64_t)i * n + j];
-      part += x.re * x.re + x.im * x.im;
-    }
-    double nx2 = block_sum<256>(part, sh);
-    cplx x0 = W[(int64_t)j * n + j];
-    double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im);
-    double nx = sqrt(nx2);
+    for (int i = j + tid; i < m; i += 256) part += wj[i].re * wj[i].re + wj[i].im * wj[i].im;
+    part = wave_sum(part);
+    if (lane == 0) part_s[j & 1][wave] = part;
+    __syncthreads();
+    const double nx2 = part_s[j & 1][0] + part_s[j & 1][1] + part_s[j & 1][2] + part_s[j & 1][3];
+    const cplx x0 = wj[j];
+    const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
     double tau = 0.0;
-    cplx alpha = {0.0, 0.0};
+    cplx alpha = {0.0, 0.0}, v0 = x0;
     if (nx > 0.0) {
       cplx ph = ax0 > 0.0 ? cplx{x0.re / ax0, x0.im / ax0} : cplx{1.0, 0.0};
       alpha = cplx{-ph.re * nx, -ph.im * nx};
-      cplx v0 = {x0.re - alpha.re, x0.im - alpha.im};
+      v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
       double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
       tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
-      __syncthreads();
-      if (tid == 0) W[(int64_t)j * n + j] = v0;
     }
-    __syncthreads();
     if (tid == 0) tau_s[j] = tau;
-    // apply to trailing columns: one wave per column
     if (tau != 0.0) {
-      for (int c = j + 1 + wave; c < n; c += 4) {
+      for (int c = j + 1 + grp; c < n; c += 16) {
+        cplx* wc = W + (int64_t)c * m;
         double wr = 0.0, wi = 0.0;
-        for (int i = j + lane; i < m; i += 64) {
-          cplx v = W[(int64_t)i * n + j], a = W[(int64_t)i * n + c];
+        for (int i = j + gl; i < m; i += 16) {
+          cplx v = (i == j) ? v0 : wj[i], a = wc[i];
           wr += v.re * a.re + v.im * a.im;   // conj(v) * a
           wi += v.re * a.im - v.im * a.re;
         }
-        wr = wave_sum(wr);
-        wi = wave_sum(wi);
-        for (int i = j + lane; i < m; i += 64) {
-          cplx v = W[(int64_t)i * n + j];
-          cplx& a = W[(int64_t)i * n + c];
-          a.re -= tau * (v.re * wr - v.im * wi);
-          a.im -= tau * (v.re * wi + v.im * wr);
+        wr = group16_sum(wr);
+        wi = group16_sum(wi);
+        for (int i = j + gl; i < m; i += 16) {
+          cplx v = (i == j) ? v0 : wj[i];
+          wc[i].re -= tau * (v.re * wr - v.im * wi);
+          wc[i].im -= tau * (v.re * wi + v.im * wr);
         }
       }
     }
-    __syncthreads();
-    // row j of R
-    for (int c = tid; c < n; c += 256) {
-      cplx rv = {0.0, 0.0};
-      if (c == j) rv = (nx > 0.0) ? alpha : cplx{0.0, 0.0};
-      else if (c > j) rv = W[(int64_t)j * n + c];
-      d.R[(int64_t)j * n + c] = rv;
+    // diag(R) is alpha; the rest of row j of R stays in W (rows above the
+    // diagonal are final once their step is done) and is written at the end
+    if (tid == 0) {
+      double a = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
+      phs[j] = a > 0.0 ? cplx{alpha.re / a, alpha.im / a} : cplx{1.0, 0.0};
+      alpha_s[j] = cplx{a, 0.0};
     }
     __syncthreads();
-  }
-  // canonical gauge: diag(R) real non-negative (Q columns take the phase)
-  __shared__ cplx phs[256];
-  for (int j = tid; j < k; j += 256) {
-    cplx r = d.R[(int64_t)j * n + j];
-    double a = sqrt(r.re * r.re + r.im * r.im);
-    phs[j] = a > 0.0 ? cplx{r.re / a, r.im / a} : cplx{1.0, 0.0};
+    // the reflector's head replaces x0 only after every column used x0
+    if (tid == 0 && tau != 0.0) wj[j] = v0;
   }
   __syncthreads();
+  // R with the canonical gauge: diag(R) real non-negative, row j * conj(phase_j)
   for (int64_t e = tid; e < (int64_t)k * n; e += 256) {
-    cplx ph = phs[e / n], x = d.R[e];
-    d.R[e] = cplx{x.re * ph.re + x.im * ph.im, x.im * ph.re - x.re * ph.im};  // x * conj(ph)
+    int j = (int)(e / n), c = (int)(e % n);
+    cplx x = {0.0, 0.0};
+    if (c == j) x = alpha_s[j];
+    else if (c > j) {
+      cplx w = W[(int64_t)c * m + j], ph = phs[j];
+      x = cplx{w.re * ph.re + w.im * ph.im, w.im * ph.re - w.re * ph.im};
+    }
+    d.R[e] = x;
   }
-  // Q = H_0 ... H_{k-1} [I; 0], built backwards into d.Q (m x k)
+  // Q = H_0 ... H_{k-1} [I; 0], built backwards (column-major Qt)
   for (int64_t e = tid; e < (int64_t)m * k; e += 256) {
-    int r = (int)(e / k), c = (int)(e % k);
-    d.Q[e] = cplx{r == c ? 1.0 : 0.0, 0.0};
+    int c = (int)(e / m), r = (int)(e % m);
+    Qt[e] = cplx{r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
   for (int j = k - 1; j >= 0; --j) {
     const double tau = tau_s[j];
     if (tau != 0.0) {
-      for (int c = j + wave; c < k; c += 4) {
+      const cplx* wj = W + (int64_t)j * m;
+      for (int c = j + grp; c < k; c += 16) {
+        cplx* qc = Qt + (int64_t)c * m;
         double wr = 0.0, wi = 0.0;
-        for (int i = j + lane; i < m; i += 64) {
-          cplx v = W[(int64_t)i * n + j], a = d.Q[(int64_t)i * k + c];
+        for (int i = j + gl; i < m; i += 16) {
+          cplx v = wj[i], a = qc[i];
           wr += v.re * a.re + v.im * a.im;
           wi += v.re * a.im - v.im * a.re;
         }
-        wr = wave_sum(wr);
-        wi = wave_sum(wi);
-        for (int i = j + lane; i < m; i += 64) {
-          cplx v = W[(int64_t)i * n + j];
-          cplx& a = d.Q[(int64_t)i * k + c];
-          a.re -= tau * (v.re * wr - v.im * wi);
-          a.im -= tau * (v.re * wi + v.im * wr);
+        wr = group16_sum(wr);
+        wi = group16_sum(wi);
+        for (int i = j + gl; i < m; i += 16) {
+          cplx v = wj[i];
+          qc[i].re -= tau * (v.re * wr - v.im * wi);
+          qc[i].im -= tau * (v.re * wi + v.im * wr);
         }
       }
     }
     __syncthreads();
   }
   for (int64_t e = tid; e < (int64_t)m * k; e += 256) {
-    cplx ph = phs[e % k], x = d.Q[e];
+    int r = (int)(e / k), c = (int)(e % k);
+    cplx ph = phs[c], x = Qt[(int64_t)c * m + r];
     d.Q[e] = cplx{x.re * ph.re - x.im * ph.im, x.re * ph.im + x.im * ph.re};
   }
 }
 
-__global__ __launch_bounds__(256) void k_colphase(const ColPhaseDesc* __restrict__ descs) {
-  const ColPhaseDesc d = descs[blockIdx.x];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < d.keep; j += 4) {
-    double best = -1.0;
-    int bi = 0;
-    for (int i = lane; i < d.m; i += 64) {
-      cplx x = d.L[(int64_t)i * d.keep + j];
-      double v = x.re * x.re + x.im * x.im;
-      if (v > best) { best = v; bi = i; }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      double ob = __shfl_xor(best, o);
-      int oi = __shfl_xor(bi, o);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-    }
-    cplx x = d.L[(int64_t)bi * d.keep + j];
-    double a = sqrt(x.re * x.re + x.im * x.im);
-    if (a > 0.0) {
-      cplx ph = {x.re / a, x.im / a};
-      for (int i = lane; i < d.m; i += 64) {
-        cplx y = d.L[(int64_t)i * d.keep + j];
-        d.L[(int64_t)i * d.keep + j] = cplx{y.re * ph.re + y.im * ph.im, y.im * ph.re - y.re * ph.im};
-      }
-      for (int c = lane; c < d.n; c += 64) {
-        cplx y = d.R[(int64_t)j * d.n + c];
-        d.R[(int64_t)j * d.n + c] = cplx{y.re * ph.re - y.im * ph.im, y.re * ph.im + y.im * ph.re};
-      }
-    }
-  }
+__global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
+  const QrDesc d = descs[blockIdx.x];
+  const int m = d.m, n = d.n, k = m < n ? m : n;
+  extern __shared__ cplx qlds[];
+  __shared__ double tau_s[256];
+  __shared__ cplx phs[256];
+  __shared__ cplx alpha_s[256];
+  __shared__ double part_s[2][4];
+  if ((int64_t)m * (n + k) <= QR_LDS_MAX)
+    qr_body<true>(d, qlds, qlds + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
+  else
+    qr_body<false>(d, d.work, d.work + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
 }
 
 // ----------------------------------------------------------------- Jacobi
@@ -381,34 +387,37 @@ __global__ __launch_bounds__(256) void k_colphase(const ColPhaseDesc* __restrict
 // [a_p, a_q] <- [a_p, a_q] [[c, s], [-s e^{-i phi}, c e^{-i phi}]] with the
 // symmetric Schur pair (c, s) of [[a, |g|], [|g|, b]] makes the columns
 // orthogonal; the same rotation is applied to J (initially I).  Columns are
-// kept contiguous (column-major working copies At, Jt).
+// kept contiguous (column-major working copies At, Jt); every pair of a
+// round-robin round is handled by its own 16-lane group.
 constexpr int JAC_LDS_MAX = 64;
 
-__device__ __forceinline__ void jac_pair(cplx* At, cplx* Jt, int k, int p, int q, int lane,
+__device__ __forceinline__ void jac_pair(cplx* At, cplx* Jt, int k, int p, int q, int gl,
                                          int* rotated) {
   cplx* x_ = At + (int64_t)p * k;
   cplx* y_ = At + (int64_t)q * k;
   double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
-  for (int i = lane; i < k; i += 64) {
+  for (int i = gl; i < k; i += 16) {
     cplx x = x_[i], y = y_[i];
     a += x.re * x.re + x.im * x.im;
     b += y.re * y.re + y.im * y.im;
     gr += x.re * y.re + x.im * y.im;
     gi += x.re * y.im - x.im * y.re;
   }
-  a = wave_sum(a);
-  b = wave_sum(b);
-  gr = wave_sum(gr);
-  gi = wave_sum(gi);
+  a = group16_sum(a);
+  b = group16_sum(b);
+  gr = group16_sum(gr);
+  gi = group16_sum(gi);
   double ag = sqrt(gr * gr + gi * gi);
-  if (ag == 0.0 || ag <= 1e-15 * sqrt(a * b)) return;
+  // orthogonal to working precision: |g| <= k eps sqrt(a b) (rounding of a
+  // length-k dot product); a stricter test is never met and wastes sweeps
+  if (ag == 0.0 || ag <= 2.220446049250313e-16 * (k > 16 ? k : 16) * sqrt(a * b)) return;
   double zeta = (b - a) / (2.0 * ag);
   double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
   double er = gr / ag, ei = -gi / ag;  // e^{-i phi}
   cplx* u_ = Jt + (int64_t)p * k;
   cplx* v_ = Jt + (int64_t)q * k;
-  for (int i = lane; i < k; i += 64) {
+  for (int i = gl; i < k; i += 16) {
     cplx x = x_[i], y = y_[i];
     cplx ye = {y.re * er - y.im * ei, y.re * ei + y.im * er};  // y e^{-i phi}
     x_[i] = cplx{c * x.re - s * ye.re, c * x.im - s * ye.im};
@@ -418,20 +427,16 @@ __device__ __forceinline__ void jac_pair(cplx* At, cplx* Jt, int k, int p, int q
     u_[i] = cplx{c * u.re - s * ve.re, c * u.im - s * ve.im};
     v_[i] = cplx{s * u.re + c * ve.re, s * u.im + c * ve.im};
   }
-  if (lane == 0) *rotated = 1;
+  if (gl == 0) *rotated = 1;
 }
 
-__global__ __launch_bounds__(256) void k_jacobi(const JacobiDesc* __restrict__ descs) {
-  const JacobiDesc d = descs[blockIdx.x];
+template <bool INLDS>
+__device__ __forceinline__ void jacobi_body(const JacobiDesc& d, cplx* At, cplx* Jt, int* rotated_p,
+                                            double* sig, int* order) {
   const int k = d.k;
-  extern __shared__ cplx jlds[];
-  const bool in_lds = k <= JAC_LDS_MAX;
-  cplx* At = in_lds ? jlds : d.work;
-  cplx* Jt = in_lds ? jlds + k * k : d.V;
-  __shared__ int rotated;
-  __shared__ double sig[256];
-  __shared__ int order[256];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bool in_lds = INLDS;
+  int& rotated = *rotated_p;
+  const int tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
   for (int e = tid; e < k * k; e += 256) {
     int i = e / k, c = e % k;
     At[(int64_t)c * k + i] = d.R[e];
@@ -443,12 +448,12 @@ __global__ __launch_bounds__(256) void k_jacobi(const JacobiDesc* __restrict__ d
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < n - 1; ++r) {
-      for (int pi = wave; pi < n / 2; pi += 4) {
+      for (int pi = grp; pi < n / 2; pi += 16) {
         int p, q;
         if (pi == 0) { p = r; q = n - 1; }
         else { p = (r + pi) % (n - 1); q = (r - pi + n - 1) % (n - 1); }
         if (p > q) { int t = p; p = q; q = t; }
-        if (q < k) jac_pair(At, Jt, k, p, q, lane, &rotated);
+        if (q < k) jac_pair(At, Jt, k, p, q, gl, &rotated);
       }
       __syncthreads();
     }
@@ -483,6 +488,50 @@ __global__ __launch_bounds__(256) void k_jacobi(const JacobiDesc* __restrict__ d
     d.V[e] = Jsrc[(int64_t)order[c] * k + i];
   }
   for (int c = tid; c < k; c += 256) d.sigma[c] = sig[order[c]];
+}
+
+__global__ __launch_bounds__(256) void k_jacobi(const JacobiDesc* __restrict__ descs) {
+  const JacobiDesc d = descs[blockIdx.x];
+  extern __shared__ cplx jlds[];
+  __shared__ int rotated;
+  __shared__ double sig[256];
+  __shared__ int order[256];
+  if (d.k <= JAC_LDS_MAX)
+    jacobi_body<true>(d, jlds, jlds + d.k * d.k, &rotated, sig, order);
+  else
+    jacobi_body<false>(d, d.work, d.V, &rotated, sig, order);
+}
+
+__global__ __launch_bounds__(256) void k_colphase(const ColPhaseDesc* __restrict__ descs) {
+  const ColPhaseDesc d = descs[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = wave; j < d.keep; j += 4) {
+    double best = -1.0;
+    int bi = 0;
+    for (int i = lane; i < d.m; i += 64) {
+      cplx x = d.L[(int64_t)i * d.keep + j];
+      double v = x.re * x.re + x.im * x.im;
+      if (v > best) { best = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ob = __shfl_xor(best, o);
+      int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    cplx x = d.L[(int64_t)bi * d.keep + j];
+    double a = sqrt(x.re * x.re + x.im * x.im);
+    if (a > 0.0) {
+      cplx ph = {x.re / a, x.im / a};
+      for (int i = lane; i < d.m; i += 64) {
+        cplx y = d.L[(int64_t)i * d.keep + j];
+        d.L[(int64_t)i * d.keep + j] = cplx{y.re * ph.re + y.im * ph.im, y.im * ph.re - y.re * ph.im};
+      }
+      for (int c = lane; c < d.n; c += 64) {
+        cplx y = d.R[(int64_t)j * d.n + c];
+        d.R[(int64_t)j * d.n + c] = cplx{y.re * ph.re - y.im * ph.im, y.re * ph.im + y.im * ph.re};
+      }
+    }
+  }
 }
 
 // ------------------------------------------------------------ small kernels

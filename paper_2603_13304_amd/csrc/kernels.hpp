@@ -40,8 +40,9 @@ struct PermDesc {
 };
 
 // Householder QR of the m x n matrix A (row-major, lda) or, with conjT, of
-// A^H where A is n x m.  Work is an m x n scratch; Q (m x k, ldq = k) and
-// R (k x n, ldr = n) with k = min(m, n) are written explicitly.
+// A^H where A is n x m.  Work is an m x (n + k) scratch (used when the working
+// copies do not fit in LDS); Q (m x k, ldq = k) and R (k x n, ldr = n) with
+// k = min(m, n) are written explicitly, diag(R) real non-negative.
 struct QrDesc {
   const cplx* A;
   cplx* work;

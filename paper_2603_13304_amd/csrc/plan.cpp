@@ -143,7 +143,7 @@ struct Compiler::Lane {
     if (std::min(m, n) > 256) { err = "QR width above 256"; return; }
     Op op;
     op.type = OPK_QR;
-    op.a = A; op.b = scratch(m * n); op.c = Q; op.d = R;
+    op.a = A; op.b = scratch(m * (n + std::min(m, n))); op.c = Q; op.d = R;
     op.i[0] = m; op.i[1] = n; op.i[2] = lda; op.i[3] = conjT;
     push(op);
   }

@@ -87,6 +87,14 @@ def test_hex_n3_cfg2_shape_t2_fp64():
     assert message_diff(g, O, P) < 1e-10
 
 
+def test_hex_n3_cfg2_shape_t1_fp64():
+    """The benchmark workload with exact truncated SVDs (T1), one sweep from
+    a seeded generic start and one from identity."""
+    ts = syn.simple_update_cell(3, seed=2)
+    P, g, O = _run("infinite", ts, 1, randmsg=13, N=3, D=3, chi=16)
+    assert message_diff(g, O, P) < 1e-10
+
+
 def test_graph_replay_equals_direct_launches():
     ts = syn.random_unit_cell(2, seed=4)
     P, desc = problem("infinite", N=2, D=2, chi=8)
