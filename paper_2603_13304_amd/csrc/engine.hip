@@ -46,6 +46,7 @@ struct LaunchRec {
   int count = 0;
   dim3 grid;
   size_t lds = 0;
+  int variant = 0;       // kernel variant (Jacobi: 1 = rows split LDS / work buffer)
   double gemm_flops = 0.0, contraction_flops = 0.0;
   double flops = 0.0;    // algorithmic flops of the launch (8 per complex MAC)
   double bytes = 0.0;    // algorithmic bytes moved (operands read once, results written once)
@@ -187,10 +188,12 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             q.Q = resolve(h, op->c); q.R = resolve(h, op->d);
             q.m = int(op->i[0]); q.n = int(op->i[1]); q.lda = int(op->i[2]); q.conjT = int(op->i[3]);
             double m = q.m, n = q.n, k = std::min(q.m, q.n);
-            // Householder R (complex: 8 flops per MAC) plus explicit Q
-            rec.flops += 8.0 * 2.0 * (m * n * k - (m + n) * k * k / 2.0 + k * k * k / 3.0);
-            rec.bytes += 16.0 * (m * n + m * k + k * n);
-            int64_t need = int64_t(q.m) * (q.n + std::min(q.m, q.n));
+            // Householder R (complex: 8 flops per MAC), plus the same again
+            // for the explicit Q
+            double fr = 8.0 * 2.0 * (m * n * k - (m + n) * k * k / 2.0 + k * k * k / 3.0);
+            rec.flops += q.Q ? 2.0 * fr : fr;
+            rec.bytes += 16.0 * (m * n + (q.Q ? m * k : 0.0) + k * n);
+            int64_t need = int64_t(q.m) * (q.n + (q.Q ? std::min(q.m, q.n) : 0));
             if (need <= QR_LDS_MAX) lds_elems = std::max(lds_elems, need);
             v.push_back(q);
           }
@@ -201,22 +204,29 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
         }
         case OPK_JACOBI: {
           std::vector<JacobiDesc> v;
-          int klds = 0;
+          int64_t lds_elems = 0;
+          bool split = false;
           for (const Op* op : ops) {
             JacobiDesc jd;
-            jd.R = resolve(h, op->a); jd.work = resolve(h, op->b); jd.V = resolve(h, op->c);
+            jd.A = resolve(h, op->a); jd.work = resolve(h, op->b); jd.U = resolve(h, op->c);
             jd.sigma = reinterpret_cast<double*>(resolve(h, op->d));
-            jd.k = int(op->i[0]);
-            if (jd.k <= JAC_LDS_MAX) klds = std::max(klds, jd.k);
-            // one sweep of k(k-1)/2 rotations, each 3 dot products and 2
-            // column updates of A and J (count of one sweep, the minimum)
-            rec.flops += 8.0 * 0.5 * jd.k * (jd.k - 1.0) * 7.0 * jd.k;
-            rec.bytes += 16.0 * 3.0 * double(jd.k) * jd.k;
+            jd.rows = int(op->i[0]); jd.cols = int(op->i[1]); jd.lda = int(op->i[2]);
+            jd.conjT = int(op->i[3]); jd.keep = int(op->i[4]);
+            const int nl = jacobi_lds_slices(jd.rows, jd.cols);
+            if (nl < (jd.rows + 15) / 16) split = true;
+            lds_elems = std::max<int64_t>(lds_elems, int64_t(nl) * 16 * jd.cols);
+            // one sweep of cols(cols-1)/2 rotations, each three length-rows dot
+            // products (a, b, g: 2 + 2 + 4 real flops per row) and the update
+            // of two columns (2 x 8 per row): the count of one sweep, the
+            // minimum any converged run performs
+            rec.flops += 0.5 * jd.cols * (jd.cols - 1.0) * 24.0 * jd.rows;
+            rec.bytes += 16.0 * (double(jd.rows) * jd.cols + double(jd.rows) * jd.keep);
             v.push_back(jd);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
           rec.grid = dim3(unsigned(v.size()));
-          rec.lds = size_t(2) * klds * klds * sizeof(cplx);
+          rec.lds = size_t(lds_elems) * sizeof(cplx);
+          rec.variant = split ? 1 : 0;
           break;
         }
         case OPK_OMEGA: {
@@ -328,7 +338,12 @@ hipError_t launch(pepsnet_s* h, const LaunchRec& r) {
       hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, h->stream, (const QrDesc*)d);
       break;
     case OPK_JACOBI:
-      hipLaunchKernelGGL(k_jacobi, r.grid, blk, r.lds, h->stream, (const JacobiDesc*)d);
+      if (r.variant)
+        hipLaunchKernelGGL(k_jacobi<true>, r.grid, dim3(JAC_THREADS), r.lds, h->stream,
+                           (const JacobiDesc*)d);
+      else
+        hipLaunchKernelGGL(k_jacobi<false>, r.grid, dim3(JAC_THREADS), r.lds, h->stream,
+                           (const JacobiDesc*)d);
       break;
     case OPK_OMEGA:
       hipLaunchKernelGGL(k_omega, r.grid, blk, 0, h->stream, (const OmegaDesc*)d);
@@ -535,8 +550,9 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
     h->rho_descs[par] = reinterpret_cast<RhoDesc*>(h->desc_dev + size_t(h->rho_descs[par]));
   if (hipHostMalloc(&h->pinned, size_t(C.msg.off.size() + 8) * sizeof(double), 0) != hipSuccess)
     return fail(BBP_ENOMEM, "pinned host buffer");
-  PN_HIP(hipFuncSetAttribute((const void*)k_jacobi, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             int(2 * JAC_LDS_MAX * JAC_LDS_MAX * sizeof(cplx))));
+  for (const void* f : {(const void*)k_jacobi<false>, (const void*)k_jacobi<true>})
+    PN_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               int(JAC_LDS_MAX * sizeof(cplx))));
   PN_HIP(hipFuncSetAttribute((const void*)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(QR_LDS_MAX * sizeof(cplx))));
   PN_HIP(hipEventCreate(&h->ev0));

@@ -10,9 +10,12 @@
 //                 hi + lo (bf16 each), product hi*hi + hi*lo + lo*hi, FP32 acc
 //   Operands are staged through LDS; storage stays complex128.
 // * k_permute: batched tensor transpose (rank <= 16).
-// * k_qr: Householder QR with explicit thin Q and R, one workgroup per item.
-// * k_jacobi: one-sided (Hestenes) Jacobi SVD of a small square matrix, one
-//   workgroup per item, LDS-resident when it fits, parallel round-robin pairs.
+// * k_qr: Householder QR with R and (optionally) the explicit thin Q, one
+//   workgroup per item.
+// * k_jacobi: one-sided (Hestenes) Jacobi SVD, one workgroup per item, one
+//   16-lane group per column pair of a round-robin round, working copy in
+//   LDS (the leading rows when the matrix does not fit) and the work buffer;
+//   returns the leading left singular vectors and singular values.
 // * small kernels: sketch generation (SplitMix64), normalisation with
 //   log-scale, zero-padded copies, message trace phase fix.
 #include <hip/hip_runtime.h>
@@ -331,6 +334,7 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, doub
     }
     d.R[e] = x;
   }
+  if (d.Q == nullptr) return;
   // Q = H_0 ... H_{k-1} [I; 0], built backwards (column-major Qt)
   for (int64_t e = tid; e < (int64_t)m * k; e += 256) {
     int c = (int)(e / m), r = (int)(e % m);
@@ -375,132 +379,263 @@ __global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
   __shared__ cplx phs[256];
   __shared__ cplx alpha_s[256];
   __shared__ double part_s[2][4];
-  if ((int64_t)m * (n + k) <= QR_LDS_MAX)
+  if ((int64_t)m * (n + (d.Q ? k : 0)) <= QR_LDS_MAX)
     qr_body<true>(d, qlds, qlds + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
   else
     qr_body<false>(d, d.work, d.work + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
 }
 
 // ----------------------------------------------------------------- Jacobi
-// One-sided Jacobi on the columns of A (k x k): for a pair (p, q) with
-// a = ||a_p||^2, b = ||a_q||^2, g = a_p^H a_q = |g| e^{i phi}, the rotation
-// [a_p, a_q] <- [a_p, a_q] [[c, s], [-s e^{-i phi}, c e^{-i phi}]] with the
-// symmetric Schur pair (c, s) of [[a, |g|], [|g|, b]] makes the columns
-// orthogonal; the same rotation is applied to J (initially I).  Columns are
-// kept contiguous (column-major working copies At, Jt); every pair of a
-// round-robin round is handled by its own 16-lane group.
-constexpr int JAC_LDS_MAX = 64;
+// One-sided (Hestenes) Jacobi on the columns of A (rows x cols).  For a pair
+// (p, q) with a = ||a_p||^2, b = ||a_q||^2 and g = a_p^H a_q = |g| e^{i phi},
+// the rotation [a_p, a_q] <- [a_p, a_q] [[c, s], [-s e^{-i phi}, c e^{-i phi}]]
+// with the symmetric Schur pair (c, s) of [[a, |g|], [|g|, b]] makes the two
+// columns orthogonal.  At convergence A W = U Sigma: the column norms are the
+// singular values and the normalised columns the left singular vectors, so
+// the rotations W are never accumulated.
+//
+// Every pair of a round-robin round is handled by one 16-lane group that
+// loads its two columns into registers (up to JAC_RC rows per lane, all loads
+// in flight together), reduces the three dot products over the group with
+// DPP and writes the rotated columns back.
+constexpr int JAC_G = 16;                      // lanes per column pair
+constexpr int JAC_RC = 9;                      // rows per lane (max)
+constexpr int JAC_THREADS = 1024;              // 64 pairs per pass
+constexpr int JAC_MAX_ROWS = JAC_G * JAC_RC;   // 144
+constexpr int JAC_MAX_COLS = JAC_MAX_ROWS;   // the plan keeps cols <= rows
+constexpr int JAC_LDS_MAX = 9216;              // complex elements (144 KB)
+constexpr int JAC_MAX_SWEEPS = 60;
+static_assert(JAC_MAX_ROWS == kJacobiMaxRows && JAC_MAX_COLS == kJacobiMaxCols,
+              "Jacobi limits of the plan compiler and the kernel differ");
 
-__device__ __forceinline__ void jac_pair(cplx* At, cplx* Jt, int k, int p, int q, int gl,
-                                         int* rotated) {
-  cplx* x_ = At + (int64_t)p * k;
-  cplx* y_ = At + (int64_t)q * k;
+// (re, im) pairs as a vector type so that address-space qualified pointers
+// (global: global_load/store, LDS: ds_read/write) can be used directly
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) d2v gd2;   // global memory
+typedef __attribute__((address_space(3))) d2v ld2;   // LDS
+
+// The working copy of column c is split by rows: its first NL 16-row slices
+// live in LDS (L[c * NL * 16 + ...]) and the remaining NT - NL slices in the
+// work buffer (G[c * (NT - NL) * 16 + ...]).  Columns are padded with zero
+// rows to rows_pad = 16 NT, so every lane owns NT rows and no row needs a
+// bounds test (rotations keep zero rows zero).
+template <int NT, int NL>
+struct JacStore {
+  ld2* L;
+  gd2* G;
+  __device__ __forceinline__ d2v ld(int c, int t, int gl) const {
+    if (t < NL) return L[(c * NL + t) * JAC_G + gl];
+    return G[(c * (NT - NL) + (t - NL)) * JAC_G + gl];
+  }
+  __device__ __forceinline__ void st(int c, int t, int gl, d2v v) const {
+    if (t < NL) L[(c * NL + t) * JAC_G + gl] = v;
+    else G[(c * (NT - NL) + (t - NL)) * JAC_G + gl] = v;
+  }
+};
+
+template <int NT, int NL>
+__device__ __forceinline__ void jac_pair(const JacStore<NT, NL>& S, int p, int q, int gl,
+                                         double tol, double floor2, int* rotated) {
+  d2v x[NT], y[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    x[t] = S.ld(p, t, gl);
+    y[t] = S.ld(q, t, gl);
+  }
   double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
-  for (int i = gl; i < k; i += 16) {
-    cplx x = x_[i], y = y_[i];
-    a += x.re * x.re + x.im * x.im;
-    b += y.re * y.re + y.im * y.im;
-    gr += x.re * y.re + x.im * y.im;
-    gi += x.re * y.im - x.im * y.re;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    a += x[t].x * x[t].x + x[t].y * x[t].y;
+    b += y[t].x * y[t].x + y[t].y * y[t].y;
+    gr += x[t].x * y[t].x + x[t].y * y[t].y;
+    gi += x[t].x * y[t].y - x[t].y * y[t].x;
   }
   a = group16_sum(a);
   b = group16_sum(b);
   gr = group16_sum(gr);
   gi = group16_sum(gi);
-  double ag = sqrt(gr * gr + gi * gi);
-  // orthogonal to working precision: |g| <= k eps sqrt(a b) (rounding of a
-  // length-k dot product); a stricter test is never met and wastes sweeps
-  if (ag == 0.0 || ag <= 2.220446049250313e-16 * (k > 16 ? k : 16) * sqrt(a * b)) return;
-  double zeta = (b - a) / (2.0 * ag);
-  double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-  double er = gr / ag, ei = -gi / ag;  // e^{-i phi}
-  cplx* u_ = Jt + (int64_t)p * k;
-  cplx* v_ = Jt + (int64_t)q * k;
-  for (int i = gl; i < k; i += 16) {
-    cplx x = x_[i], y = y_[i];
-    cplx ye = {y.re * er - y.im * ei, y.re * ei + y.im * er};  // y e^{-i phi}
-    x_[i] = cplx{c * x.re - s * ye.re, c * x.im - s * ye.im};
-    y_[i] = cplx{s * x.re + c * ye.re, s * x.im + c * ye.im};
-    cplx u = u_[i], v = v_[i];
-    cplx ve = {v.re * er - v.im * ei, v.re * ei + v.im * er};
-    u_[i] = cplx{c * u.re - s * ve.re, c * u.im - s * ve.im};
-    v_[i] = cplx{s * u.re + c * ve.re, s * u.im + c * ve.im};
+  // columns at the rounding floor of the matrix are left alone (their
+  // direction is noise, and their squares may be denormal)
+  if (a <= floor2 || b <= floor2) return;
+  const double ag = sqrt(gr * gr + gi * gi);
+  if (ag == 0.0 || ag <= tol * sqrt(a * b)) return;
+  const double zeta = (b - a) / (2.0 * ag);
+  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
+  const double er = gr / ag, ei = -gi / ag;  // e^{-i phi}
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double yr = y[t].x * er - y[t].y * ei, yi = y[t].x * ei + y[t].y * er;
+    S.st(p, t, gl, d2v{c * x[t].x - s * yr, c * x[t].y - s * yi});
+    S.st(q, t, gl, d2v{s * x[t].x + c * yr, s * x[t].y + c * yi});
   }
   if (gl == 0) *rotated = 1;
 }
 
-template <bool INLDS>
-__device__ __forceinline__ void jacobi_body(const JacobiDesc& d, cplx* At, cplx* Jt, int* rotated_p,
-                                            double* sig, int* order) {
-  const int k = d.k;
-  const bool in_lds = INLDS;
+template <int NT, int NL>
+__device__ __forceinline__ void jacobi_body(const JacobiDesc& d, const JacStore<NT, NL>& S,
+                                            int* rotated_p, double* sig, int* order,
+                                            double* fro_s) {
+  constexpr int rows_pad = NT * JAC_G;
+  const int rows = d.rows, cols = d.cols;
+  const int tid = threadIdx.x, grp = tid / JAC_G, gl = tid % JAC_G;
+  constexpr int NG = JAC_THREADS / JAC_G;
   int& rotated = *rotated_p;
-  const int tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
-  for (int e = tid; e < k * k; e += 256) {
-    int i = e / k, c = e % k;
-    At[(int64_t)c * k + i] = d.R[e];
-    Jt[e] = cplx{i == c ? 1.0 : 0.0, 0.0};
+  for (int e = tid; e < rows_pad * cols; e += JAC_THREADS) {
+    const int c = e / rows_pad, i = e % rows_pad;
+    cplx v = {0.0, 0.0};
+    if (i < rows) {
+      if (d.conjT) { v = d.A[(int64_t)c * d.lda + i]; v.im = -v.im; }
+      else v = d.A[(int64_t)i * d.lda + c];
+    }
+    const int t = i / JAC_G;
+    if (t < NL) S.L[(c * NL + t) * JAC_G + i % JAC_G] = d2v{v.re, v.im};
+    else S.G[(c * (NT - NL) + (t - NL)) * JAC_G + i % JAC_G] = d2v{v.re, v.im};
   }
   __syncthreads();
-  const int n = (k % 2) ? k + 1 : k;   // round-robin needs an even count
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  // squared Frobenius norm of A, summed by the lane groups
+  double f2 = 0.0;
+  for (int c = grp; c < cols; c += NG) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const d2v x = S.ld(c, t, gl);
+      f2 += x.x * x.x + x.y * x.y;
+    }
+  }
+  f2 = block_sum<JAC_THREADS>(f2, fro_s);
+  // singular values below 1e-15 ||A||_F are rounding noise: not rotated, and
+  // returned as zero columns of U
+  const double floor2 = 1e-30 * f2;
+  // orthogonal to working precision: |g| <= rows eps sqrt(a b), the rounding
+  // level of a length-rows dot product; a stricter test is never met
+  const double tol = 2.220446049250313e-16 * (rows > 16 ? rows : 16);
+  const int n = cols + (cols & 1);   // round-robin needs an even count
+  for (int sweep = 0; sweep < JAC_MAX_SWEEPS; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int r = 0; r < n - 1; ++r) {
-      for (int pi = grp; pi < n / 2; pi += 16) {
+      for (int pi = grp; pi < n / 2; pi += NG) {
         int p, q;
         if (pi == 0) { p = r; q = n - 1; }
-        else { p = (r + pi) % (n - 1); q = (r - pi + n - 1) % (n - 1); }
-        if (p > q) { int t = p; p = q; q = t; }
-        if (q < k) jac_pair(At, Jt, k, p, q, gl, &rotated);
+        else {
+          p = r + pi;
+          if (p >= n - 1) p -= n - 1;
+          q = r - pi;
+          if (q < 0) q += n - 1;
+        }
+        if (p > q) { const int t = p; p = q; q = t; }
+        if (q < cols) jac_pair<NT, NL>(S, p, q, gl, tol, floor2, &rotated);
       }
       __syncthreads();
     }
-    if (!rotated) break;
+    const bool again = rotated != 0;
     __syncthreads();
+    if (!again) break;
   }
-  for (int c = tid; c < k; c += 256) {
+  for (int c = grp; c < cols; c += NG) {
     double s = 0.0;
-    for (int i = 0; i < k; ++i) {
-      cplx x = At[(int64_t)c * k + i];
-      s += x.re * x.re + x.im * x.im;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const d2v x = S.ld(c, t, gl);
+      s += x.x * x.x + x.y * x.y;
     }
-    sig[c] = sqrt(s);
+    s = group16_sum(s);
+    if (gl == 0) sig[c] = sqrt(s);
   }
   __syncthreads();
-  for (int c = tid; c < k; c += 256) {
+  for (int c = tid; c < cols; c += JAC_THREADS) {
     int rank = 0;
-    for (int o = 0; o < k; ++o)
-      if (sig[o] > sig[c] || (sig[o] == sig[c] && o < c)) ++rank;
+    const double sc = sig[c];
+    for (int o = 0; o < cols; ++o)
+      if (sig[o] > sc || (sig[o] == sc && o < c)) ++rank;
     order[rank] = c;
   }
   __syncthreads();
-  const cplx* Jsrc = Jt;
-  if (!in_lds) {
-    // Jt lives in d.V: move it to the (now free) work buffer first
-    for (int e = tid; e < k * k; e += 256) d.work[e] = Jt[e];
-    __syncthreads();
-    Jsrc = d.work;
+  const int keep = d.keep;
+  for (int e = tid; e < rows * keep; e += JAC_THREADS) {
+    const int i = e / keep, j = e % keep;
+    const int c = order[j];
+    const double s = sig[c];
+    cplx v = {0.0, 0.0};
+    if (s * s > floor2) {
+      const d2v x = S.ld(c, i / JAC_G, i % JAC_G);
+      v = cplx{x.x / s, x.y / s};
+    }
+    d.U[e] = v;
   }
-  for (int e = tid; e < k * k; e += 256) {
-    int i = e / k, c = e % k;
-    d.V[e] = Jsrc[(int64_t)order[c] * k + i];
+  for (int j = tid; j < keep; j += JAC_THREADS) {
+    const double s = sig[order[j]];
+    d.sigma[j] = s * s > floor2 ? s : 0.0;
   }
-  for (int c = tid; c < k; c += 256) d.sigma[c] = sig[order[c]];
 }
 
-__global__ __launch_bounds__(256) void k_jacobi(const JacobiDesc* __restrict__ descs) {
-  const JacobiDesc d = descs[blockIdx.x];
-  extern __shared__ cplx jlds[];
-  __shared__ int rotated;
-  __shared__ double sig[256];
-  __shared__ int order[256];
-  if (d.k <= JAC_LDS_MAX)
-    jacobi_body<true>(d, jlds, jlds + d.k * d.k, &rotated, sig, order);
-  else
-    jacobi_body<false>(d, d.work, d.V, &rotated, sig, order);
+// slices kept in LDS for an item: all of them when the padded matrix fits,
+// else as many leading slices as fit (the kernels dispatch on the result)
+__host__ __device__ inline int jacobi_lds_slices(int rows, int cols) {
+  const int nt = (rows + JAC_G - 1) / JAC_G;
+  if (nt * JAC_G * cols <= JAC_LDS_MAX) return nt;
+  const int nl = JAC_LDS_MAX / (JAC_G * cols);
+  return nl < nt ? nl : nt;
 }
+
+template <int NT, int NL>
+__device__ __forceinline__ void jac_run(const JacobiDesc& d, ld2* L, int* rotated, double* sig,
+                                        int* order, double* fro_s) {
+  JacStore<NT, NL> S{L, (gd2*)d.work};
+  jacobi_body<NT, NL>(d, S, rotated, sig, order, fro_s);
+}
+
+template <int NT>
+__device__ __forceinline__ void jac_dispatch_nl(const JacobiDesc& d, int nl, ld2* L, int* rotated,
+                                                double* sig, int* order, double* fro_s) {
+  if (nl >= NT) { jac_run<NT, NT>(d, L, rotated, sig, order, fro_s); return; }
+  // a partial split only occurs for rows > 96 (NT >= 7) with cols <= rows <=
+  // 144, where at least 4 of the NT slices fit: JAC_LDS_MAX / (16 * 144) = 4
+  if constexpr (NT >= 7) {
+    switch (nl) {
+      case 4: jac_run<NT, 4>(d, L, rotated, sig, order, fro_s); return;
+      case 5: jac_run<NT, 5>(d, L, rotated, sig, order, fro_s); return;
+      case 6: jac_run<NT, 6>(d, L, rotated, sig, order, fro_s); return;
+      case 7: jac_run<NT, (NT > 7 ? 7 : 4)>(d, L, rotated, sig, order, fro_s); return;
+      case 8: jac_run<NT, (NT > 8 ? 8 : 4)>(d, L, rotated, sig, order, fro_s); return;
+      default: return;   // excluded by the plan compiler (cols <= rows <= 144)
+    }
+  }
+}
+
+// SPLIT = false: every slice in LDS; true: the leading slices in LDS and
+// the rest in the work buffer (separate kernels keep the register budget of
+// the common all-LDS case apart)
+template <bool SPLIT>
+__device__ __forceinline__ void jacobi_dispatch(const JacobiDesc& d, ld2* L, int* rotated,
+                                                double* sig, int* order, double* fro_s) {
+  const int nl = SPLIT ? jacobi_lds_slices(d.rows, d.cols) : 99;
+  switch ((d.rows + JAC_G - 1) / JAC_G) {
+    case 1: jac_dispatch_nl<1>(d, nl, L, rotated, sig, order, fro_s); break;
+    case 2: jac_dispatch_nl<2>(d, nl, L, rotated, sig, order, fro_s); break;
+    case 3: jac_dispatch_nl<3>(d, nl, L, rotated, sig, order, fro_s); break;
+    case 4: jac_dispatch_nl<4>(d, nl, L, rotated, sig, order, fro_s); break;
+    case 5: jac_dispatch_nl<5>(d, nl, L, rotated, sig, order, fro_s); break;
+    case 6: jac_dispatch_nl<6>(d, nl, L, rotated, sig, order, fro_s); break;
+    case 7: jac_dispatch_nl<7>(d, nl, L, rotated, sig, order, fro_s); break;
+    case 8: jac_dispatch_nl<8>(d, nl, L, rotated, sig, order, fro_s); break;
+    default: jac_dispatch_nl<9>(d, nl, L, rotated, sig, order, fro_s); break;
+  }
+}
+
+// one workgroup per item; dynamic LDS holds the leading row slices
+template <bool SPLIT>
+__global__ __launch_bounds__(JAC_THREADS) void k_jacobi(const JacobiDesc* __restrict__ descs) {
+  const JacobiDesc d = descs[blockIdx.x];
+  extern __shared__ d2v jlds[];   // 16-byte aligned for ds_read/write_b128
+  __shared__ int rotated;
+  __shared__ double sig[JAC_MAX_COLS];
+  __shared__ int order[JAC_MAX_COLS];
+  __shared__ double fro_s[JAC_THREADS / 64];
+  jacobi_dispatch<SPLIT>(d, (ld2*)jlds, &rotated, sig, order, fro_s);
+}
+template __global__ void k_jacobi<false>(const JacobiDesc*);
+template __global__ void k_jacobi<true>(const JacobiDesc*);
 
 __global__ __launch_bounds__(256) void k_colphase(const ColPhaseDesc* __restrict__ descs) {
   const ColPhaseDesc d = descs[blockIdx.x];

@@ -41,8 +41,9 @@ struct PermDesc {
 
 // Householder QR of the m x n matrix A (row-major, lda) or, with conjT, of
 // A^H where A is n x m.  Work is an m x (n + k) scratch (used when the working
-// copies do not fit in LDS); Q (m x k, ldq = k) and R (k x n, ldr = n) with
-// k = min(m, n) are written explicitly, diag(R) real non-negative.
+// copies do not fit in LDS); R (k x n, ldr = n) with k = min(m, n) and, unless
+// Q is null, Q (m x k, ldq = k) are written explicitly, diag(R) real
+// non-negative.
 struct QrDesc {
   const cplx* A;
   cplx* work;
@@ -51,15 +52,21 @@ struct QrDesc {
   int m, n, lda, conjT;
 };
 
-// One-sided Jacobi on the columns of the k x k matrix R (row-major, ld k):
-// R J = W with orthogonal columns.  Writes J with columns sorted by
-// decreasing column norm into V (k x k) and the norms into sigma.
+// One-sided Jacobi SVD of the rows x cols matrix A with element (i, c) at
+// A[i * lda + c], or conj(A[c * lda + i]) with conjT.  Rotating the columns to
+// mutual orthogonality gives A W = U Sigma; the `keep` columns of largest norm
+// are written normalised, in decreasing order, as U (rows x keep, ld keep) and
+// their norms into sigma.  Singular values at or below 1e-15 ||A||_F are
+// rounding noise: they are returned as 0 with a zero column of U.
+constexpr int kJacobiMaxRows = 144;
+inline int64_t jacobi_work_elems(int64_t rows, int64_t cols) { return (rows + 15) / 16 * 16 * cols; }
+constexpr int kJacobiMaxCols = 144;   // and cols <= rows
 struct JacobiDesc {
-  const cplx* R;
-  cplx* work;   // k x k scratch (used when the matrix does not fit in LDS)
-  cplx* V;      // k x k output
+  const cplx* A;
+  cplx* work;   // cols x roundup(rows, 16) scratch (used when it does not fit in LDS)
+  cplx* U;
   double* sigma;
-  int k;
+  int rows, cols, lda, conjT, keep;
 };
 
 // Random sign sketch: out[i, j] = (+-1 +- 1j)/sqrt(2) from SplitMix64 output

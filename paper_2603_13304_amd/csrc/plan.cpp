@@ -139,20 +139,26 @@ struct Compiler::Lane {
     for (size_t k = 0; k < od.size(); ++k) { op.i[2 + k] = od[k]; op.i[18 + k] = os[k]; }
     push(op);
   }
+  // Q may be an invalid Ref: only R is produced
   void qr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R) {
     if (std::min(m, n) > 256) { err = "QR width above 256"; return; }
     Op op;
     op.type = OPK_QR;
-    op.a = A; op.b = scratch(m * (n + std::min(m, n))); op.c = Q; op.d = R;
+    op.a = A; op.b = scratch(m * (n + (Q.valid() ? std::min(m, n) : 0))); op.c = Q; op.d = R;
     op.i[0] = m; op.i[1] = n; op.i[2] = lda; op.i[3] = conjT;
     push(op);
   }
-  void jacobi(Ref R, int64_t k, Ref V, Ref sig) {
-    if (k > 256) { err = "Jacobi size above 256"; return; }
+  // leading `keep` left singular vectors U (rows x keep) and values of the
+  // rows x cols matrix A (element (i, c) at A[i*lda + c], conj(A[c*lda + i])
+  // with conjT)
+  void jacobi(Ref A, int64_t rows, int64_t cols, int64_t lda, int conjT, int64_t keep, Ref U,
+              Ref sig) {
+    if (rows > kJacobiMaxRows) { err = "Jacobi SVD with more than 144 rows"; return; }
+    if (cols > rows || cols > kJacobiMaxCols) { err = "Jacobi SVD needs cols <= rows"; return; }
     Op op;
     op.type = OPK_JACOBI;
-    op.a = R; op.b = scratch(k * k); op.c = V; op.d = sig;
-    op.i[0] = k;
+    op.a = A; op.b = scratch(jacobi_work_elems(rows, cols)); op.c = U; op.d = sig;
+    op.i[0] = rows; op.i[1] = cols; op.i[2] = lda; op.i[3] = conjT; op.i[4] = keep;
     push(op);
   }
   void omega(Ref dst, int64_t n, int64_t k, uint64_t prefix, bool sweep_tag) {
@@ -265,36 +271,42 @@ struct Compiler::Lane {
       }
       Ref Q = scratch(m * k), Rq = scratch(k * k);
       qr(Y, m, k, k, 0, Q, Rq);
+      // B = Q^H M (k x n) = R3^H Q3^H with B^H = Q3 R3; the columns of R3^H
+      // rotated to orthogonality are U Sigma of B, so M ~ (Q U) Sigma (...)^H
       Ref B = scratch(k * n);
       gemm(Q, M, B, k, n, m, k, n, n, OP_C, OP_N, o.precision, 1);
-      Ref Q3 = scratch(n * k), R3 = scratch(k * k);
-      qr(B, n, k, n, 1, Q3, R3);
-      Ref V = scratch(k * k), sig = scratch(k);
-      jacobi(R3, k, V, sig);
-      gemm(Q, V, Lout, m, keep, k, k, k, keep, OP_N, OP_N, PREC_FP64);
-      gemm(V, B, Rout, keep, n, k, k, n, n, OP_C, OP_N, PREC_FP64);
+      Ref R3 = scratch(k * k);
+      qr(B, n, k, n, 1, Ref(), R3);
+      Ref U = scratch(k * keep), sig = scratch(keep);
+      jacobi(R3, k, k, k, 1, keep, U, sig);
+      gemm(Q, U, Lout, m, keep, k, k, keep, keep, OP_N, OP_N, PREC_FP64);
+      gemm(U, B, Rout, keep, n, k, keep, n, n, OP_C, OP_N, PREC_FP64);
       colphase(Lout, Rout, m, keep, n);
       return 0;
     }
-    if (m <= n) {
-      Ref Q3 = scratch(n * m), R3 = scratch(m * m);
-      qr(M, n, m, n, 1, Q3, R3);
-      Ref V = scratch(m * m), sig = scratch(m);
-      jacobi(R3, m, V, sig);
-      pad(V, Lout, int(m), 1, int(m), int(m), int(keep), 0, 0, 0);
-      gemm(V, M, Rout, keep, n, m, m, n, n, OP_C, OP_N, PREC_FP64);
-      colphase(Lout, Rout, m, keep, n);
+    if (m >= n && m <= kJacobiMaxRows) {
+      // M W = U Sigma directly on the columns of M
+      Ref sig = scratch(keep);
+      jacobi(M, m, n, n, 0, keep, Lout, sig);
+      gemm(Lout, M, Rout, keep, n, m, keep, n, n, OP_C, OP_N, PREC_FP64);
+    } else if (m < n) {
+      // M^H = Q3 R3, M = R3^H Q3^H: the left singular vectors of M are those
+      // of R3^H (m x m, the conjugated rows of R3); Q3 is not needed
+      Ref R3 = scratch(m * m);
+      qr(M, n, m, n, 1, Ref(), R3);
+      Ref sig = scratch(keep);
+      jacobi(R3, m, m, m, 1, keep, Lout, sig);
+      gemm(Lout, M, Rout, keep, n, m, keep, n, n, OP_C, OP_N, PREC_FP64);
     } else {
+      // tall: M = Q R, left singular vectors Q U with U those of R (n x n)
       Ref Q = scratch(m * n), R = scratch(n * n);
       qr(M, m, n, n, 0, Q, R);
-      Ref Q3 = scratch(n * n), R3 = scratch(n * n);
-      qr(R, n, n, n, 1, Q3, R3);
-      Ref V = scratch(n * n), sig = scratch(n);
-      jacobi(R3, n, V, sig);
-      gemm(Q, V, Lout, m, keep, n, n, n, keep, OP_N, OP_N, PREC_FP64);
-      gemm(V, R, Rout, keep, n, n, n, n, n, OP_C, OP_N, PREC_FP64);
-      colphase(Lout, Rout, m, keep, n);
+      Ref U = scratch(n * keep), sig = scratch(keep);
+      jacobi(R, n, n, n, 0, keep, U, sig);
+      gemm(Q, U, Lout, m, keep, n, n, keep, keep, OP_N, OP_N, PREC_FP64);
+      gemm(U, R, Rout, keep, n, n, keep, n, n, OP_C, OP_N, PREC_FP64);
     }
+    colphase(Lout, Rout, m, keep, n);
     return 0;
   }
 
