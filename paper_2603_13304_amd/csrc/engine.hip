@@ -154,7 +154,8 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             v.push_back(g);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
-          rec.grid = dim3(unsigned((mN + 63) / 64), unsigned((mM + 63) / 64), unsigned(v.size()));
+          rec.grid = dim3(unsigned((mN + 63) / 64),
+                          unsigned(std::min<int64_t>(65535, (mM + 63) / 64)), unsigned(v.size()));
           break;
         }
         case OPK_PERM: {
@@ -182,6 +183,7 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
         case OPK_QR: {
           std::vector<QrDesc> v;
           int64_t lds_elems = 0;
+          bool tall = false;
           for (const Op* op : ops) {
             QrDesc q;
             q.A = resolve(h, op->a); q.work = resolve(h, op->b);
@@ -195,11 +197,14 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             rec.bytes += 16.0 * (m * n + (q.Q ? m * k : 0.0) + k * n);
             int64_t need = int64_t(q.m) * (q.n + (q.Q ? std::min(q.m, q.n) : 0));
             if (need <= QR_LDS_MAX) lds_elems = std::max(lds_elems, need);
+            else tall = true;
             v.push_back(q);
           }
           rec.desc_off = push_descs(&h->desc_host, v);
           rec.grid = dim3(unsigned(v.size()));
-          rec.lds = size_t(lds_elems) * sizeof(cplx);
+          // blocked kernel (panel in LDS) when any working copy overflows LDS
+          rec.variant = tall ? 1 : 0;
+          rec.lds = tall ? size_t(QRT_LDS) * sizeof(cplx) : size_t(lds_elems) * sizeof(cplx);
           break;
         }
         case OPK_JACOBI: {
@@ -335,7 +340,11 @@ hipError_t launch(pepsnet_s* h, const LaunchRec& r) {
       hipLaunchKernelGGL(k_permute, r.grid, blk, 0, h->stream, (const PermDesc*)d);
       break;
     case OPK_QR:
-      hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, h->stream, (const QrDesc*)d);
+      if (r.variant)
+        hipLaunchKernelGGL(k_qr_tall, r.grid, dim3(QRT_THREADS), r.lds, h->stream,
+                           (const QrDesc*)d);
+      else
+        hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, h->stream, (const QrDesc*)d);
       break;
     case OPK_JACOBI:
       if (r.variant)
@@ -555,6 +564,8 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
                                int(JAC_LDS_MAX * sizeof(cplx))));
   PN_HIP(hipFuncSetAttribute((const void*)k_qr, hipFuncAttributeMaxDynamicSharedMemorySize,
                              int(QR_LDS_MAX * sizeof(cplx))));
+  PN_HIP(hipFuncSetAttribute((const void*)k_qr_tall, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(QRT_LDS * sizeof(cplx))));
   PN_HIP(hipEventCreate(&h->ev0));
   PN_HIP(hipEventCreate(&h->ev1));
   PN_HIP(hipStreamSynchronize(h->stream));

@@ -11,7 +11,9 @@
 //   Operands are staged through LDS; storage stays complex128.
 // * k_permute: batched tensor transpose (rank <= 16).
 // * k_qr: Householder QR with R and (optionally) the explicit thin Q, one
-//   workgroup per item.
+//   workgroup per item, working copy in LDS; k_qr_tall: the same
+//   factorisation blocked in panels (compact WY) for working copies that do
+//   not fit in LDS.
 // * k_jacobi: one-sided (Hestenes) Jacobi SVD, one workgroup per item, one
 //   16-lane group per column pair of a round-robin round, working copy in
 //   LDS (the leading rows when the matrix does not fit) and the work buffer;
@@ -62,10 +64,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   constexpr int TK = GemmCfg<P>::TK;
   constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;
   const GemmDesc g = descs[blockIdx.z];
-  const int m0 = blockIdx.y * GT_M, n0 = blockIdx.x * GT_N;
-  if (m0 >= g.M || n0 >= g.N) return;
+  const int n0 = blockIdx.x * GT_N;
+  if (n0 >= g.N) return;
   __shared__ T As_r[TK][GT_M + PAD], As_i[TK][GT_M + PAD];
   __shared__ T Bs_r[TK][GT_N + PAD], Bs_i[TK][GT_N + PAD];
+  // M tiles are grid-strided (the grid's y extent is capped at 65535)
+  for (int m0 = blockIdx.y * GT_M; m0 < g.M; m0 += gridDim.y * GT_M) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   typedef typename std::conditional<P == PREC_FP64, d4, f4>::type acc_t;
@@ -188,6 +192,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
           *cp = out;
         }
       }
+  }
 }
 
 template __global__ void k_gemm<PREC_FP64>(const GemmDesc*);
@@ -383,6 +388,278 @@ __global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
     qr_body<true>(d, qlds, qlds + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
   else
     qr_body<false>(d, d.work, d.work + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
+}
+
+// --------------------------------------------------------------- tall QR
+// Blocked Householder QR for matrices whose working copy does not fit in LDS
+// (same reflectors, phases and outputs as k_qr).  Panels of pb <= 8 columns
+// are factorised in LDS (in place in the work buffer when the panel does not
+// fit); the panel's reflectors H_1 .. H_pb = I - V T V^H
+// (compact WY, T upper triangular) are then applied to every trailing column
+// in two passes over its rows (s = V^H a, a -= V T^H s), one wave per
+// column.  The explicit Q is formed backwards with the same block reflectors.
+constexpr int QRT_THREADS = 1024;
+constexpr int QRT_PB = 8;
+constexpr int QRT_LDS = 9216;   // complex elements of the LDS panel (144 KB)
+
+// sum over the 64 lanes of a wave, result in every lane
+__device__ __forceinline__ double wave_sum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// sum over the workgroup (QRT_THREADS), result in every thread
+__device__ __forceinline__ double qrt_block_sum(double v, double* sh) {
+  v = wave_sum64(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < QRT_THREADS / 64; ++w) s += sh[w];
+  __syncthreads();
+  return s;
+}
+
+// V[i][j] of the panel (column-major, leading dimension ldp): unit structure
+// with the reflector head v0 stored on the diagonal
+__device__ __forceinline__ cplx qrt_v(const cplx* P, int64_t ldp, int i, int j) {
+  return i < j ? cplx{0.0, 0.0} : P[j * ldp + i];
+}
+
+// a[p0 + i] -= sum_j V[i][j] w[j] after s = V^H a (w = T^H s for the
+// factorisation, w = T s for forming Q); one wave per column
+// (kept out of line: inlining both instantiations exhausts the registers)
+template <bool TRANS>
+__device__ __noinline__ void qrt_apply(cplx* col, const cplx* P, int64_t ldp, const cplx* T, int mr,
+                                       int pb, int lane) {
+  double sr[QRT_PB], si[QRT_PB];
+#pragma unroll
+  for (int j = 0; j < QRT_PB; ++j) { sr[j] = 0.0; si[j] = 0.0; }
+  for (int i = lane; i < mr; i += 64) {
+    const cplx a = col[i];
+#pragma unroll
+    for (int j = 0; j < QRT_PB; ++j)
+      if (j < pb) {
+        const cplx v = qrt_v(P, ldp, i, j);
+        sr[j] += v.re * a.re + v.im * a.im;   // conj(v) a
+        si[j] += v.re * a.im - v.im * a.re;
+      }
+  }
+  double wr[QRT_PB], wi[QRT_PB];
+#pragma unroll
+  for (int j = 0; j < QRT_PB; ++j) {
+    sr[j] = wave_sum64(sr[j]);
+    si[j] = wave_sum64(si[j]);
+  }
+  // w = T^H s (TRANS) or T s
+#pragma unroll
+  for (int r = 0; r < QRT_PB; ++r) {
+    double xr = 0.0, xi = 0.0;
+#pragma unroll
+    for (int c = 0; c < QRT_PB; ++c)
+      if (r < pb && c < pb) {
+        cplx t;
+        if (TRANS) { t = T[c * QRT_PB + r]; t.im = -t.im; }   // (T^H)[r][c]
+        else t = T[r * QRT_PB + c];
+        xr += t.re * sr[c] - t.im * si[c];
+        xi += t.re * si[c] + t.im * sr[c];
+      }
+    wr[r] = xr;
+    wi[r] = xi;
+  }
+  for (int i = lane; i < mr; i += 64) {
+    cplx a = col[i];
+#pragma unroll
+    for (int j = 0; j < QRT_PB; ++j)
+      if (j < pb) {
+        const cplx v = qrt_v(P, ldp, i, j);
+        a.re -= v.re * wr[j] - v.im * wi[j];
+        a.im -= v.re * wi[j] + v.im * wr[j];
+      }
+    col[i] = a;
+  }
+}
+
+// T (pb x pb, row-major in LDS) of the panel: T[j][j] = tau_j,
+// T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^H v_j)
+__device__ void qrt_form_t(const cplx* P, int64_t ldp, const double* tau, cplx* T, cplx* G, int mr,
+                           int pb) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // G[a][b] = V[:, a]^H V[:, b] for a < b: one wave per entry
+  for (int e = wave; e < pb * pb; e += QRT_THREADS / 64) {
+    const int a = e / pb, b = e % pb;
+    if (a >= b) continue;
+    double gr = 0.0, gi = 0.0;
+    for (int i = lane; i < mr; i += 64) {
+      const cplx x = qrt_v(P, ldp, i, a), y = qrt_v(P, ldp, i, b);
+      gr += x.re * y.re + x.im * y.im;
+      gi += x.re * y.im - x.im * y.re;
+    }
+    gr = wave_sum64(gr);
+    gi = wave_sum64(gi);
+    if (lane == 0) G[a * QRT_PB + b] = cplx{gr, gi};
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int j = 0; j < pb; ++j) {
+      for (int r = 0; r < QRT_PB; ++r) if (r >= j) T[r * QRT_PB + j] = cplx{0.0, 0.0};
+      T[j * QRT_PB + j] = cplx{tau[j], 0.0};
+      for (int r = 0; r < j; ++r) {
+        double xr = 0.0, xi = 0.0;
+        for (int c = r; c < j; ++c) {
+          const cplx t = T[r * QRT_PB + c], g = G[c * QRT_PB + j];
+          xr += t.re * g.re - t.im * g.im;
+          xi += t.re * g.im + t.im * g.re;
+        }
+        T[r * QRT_PB + j] = cplx{-tau[j] * xr, -tau[j] * xi};
+      }
+    }
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(QRT_THREADS) void k_qr_tall(const QrDesc* __restrict__ descs) {
+  const QrDesc d = descs[blockIdx.x];
+  const int m = d.m, n = d.n, k = m < n ? m : n;
+  extern __shared__ cplx Pn[];            // panel, column-major
+  __shared__ cplx T[QRT_PB * QRT_PB], G[QRT_PB * QRT_PB];
+  __shared__ double tau_s[256];
+  __shared__ cplx phs[256];
+  __shared__ double alpha_s[256];
+  __shared__ double red[QRT_THREADS / 64];
+  __shared__ int pstart[257];             // panel starts (for forming Q)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = QRT_THREADS / 64;
+  cplx* W = d.work;                       // m x n column-major
+  cplx* Qt = d.work + (int64_t)m * n;     // m x k column-major
+  for (int64_t e = tid; e < (int64_t)m * n; e += QRT_THREADS) {
+    const int r = (int)(e % m), c = (int)(e / m);
+    cplx v;
+    if (d.conjT) { v = d.A[(int64_t)c * d.lda + r]; v.im = -v.im; }
+    else v = d.A[(int64_t)r * d.lda + c];
+    W[e] = v;
+  }
+  __syncthreads();
+  int np = 0;
+  for (int p0 = 0; p0 < k; ) {
+    const int mr = m - p0;
+    const int pb = k - p0 < QRT_PB ? k - p0 : QRT_PB;
+    const bool inl = (int64_t)pb * mr <= QRT_LDS;
+    cplx* P = inl ? Pn : W + (int64_t)p0 * m + p0;
+    const int64_t ldp = inl ? mr : m;
+    if (tid == 0) pstart[np] = p0;
+    ++np;
+    if (inl) {
+      for (int e = tid; e < pb * mr; e += QRT_THREADS) {
+        const int c = e / mr, i = e % mr;
+        Pn[e] = W[(int64_t)(p0 + c) * m + p0 + i];
+      }
+    }
+    __syncthreads();
+    // factor the panel
+    for (int j = 0; j < pb; ++j) {
+      cplx* xj = P + j * ldp;
+      double part = 0.0;
+      for (int i = j + tid; i < mr; i += QRT_THREADS) part += xj[i].re * xj[i].re + xj[i].im * xj[i].im;
+      const double nx2 = qrt_block_sum(part, red);
+      const cplx x0 = xj[j];
+      const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
+      double tau = 0.0;
+      cplx alpha = {0.0, 0.0}, v0 = x0;
+      if (nx > 0.0) {
+        const cplx ph = ax0 > 0.0 ? cplx{x0.re / ax0, x0.im / ax0} : cplx{1.0, 0.0};
+        alpha = cplx{-ph.re * nx, -ph.im * nx};
+        v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
+        const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
+        tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
+      }
+      // remaining panel columns, one wave each
+      if (tau != 0.0) {
+        for (int c = j + 1 + wave; c < pb; c += NW) {
+          cplx* xc = P + c * ldp;
+          double wr = 0.0, wi = 0.0;
+          for (int i = j + lane; i < mr; i += 64) {
+            const cplx v = (i == j) ? v0 : xj[i], a = xc[i];
+            wr += v.re * a.re + v.im * a.im;
+            wi += v.re * a.im - v.im * a.re;
+          }
+          wr = wave_sum64(wr);
+          wi = wave_sum64(wi);
+          for (int i = j + lane; i < mr; i += 64) {
+            const cplx v = (i == j) ? v0 : xj[i];
+            xc[i].re -= tau * (v.re * wr - v.im * wi);
+            xc[i].im -= tau * (v.re * wi + v.im * wr);
+          }
+        }
+      }
+      if (tid == 0) {
+        tau_s[p0 + j] = tau;
+        const double a = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
+        phs[p0 + j] = a > 0.0 ? cplx{alpha.re / a, alpha.im / a} : cplx{1.0, 0.0};
+        alpha_s[p0 + j] = a;
+      }
+      __syncthreads();
+      // the reflector head replaces x0 once every column used x0
+      if (tid == 0 && tau != 0.0) xj[j] = v0;
+      __syncthreads();
+    }
+    qrt_form_t(P, ldp, tau_s + p0, T, G, mr, pb);
+    if (inl) {
+      // write the panel back (R rows above, reflectors below / on the diagonal)
+      for (int e = tid; e < pb * mr; e += QRT_THREADS) {
+        const int c = e / mr, i = e % mr;
+        W[(int64_t)(p0 + c) * m + p0 + i] = Pn[e];
+      }
+    }
+    // trailing columns: A <- (I - V T V^H)^H A
+    for (int c = p0 + pb + wave; c < n; c += NW)
+      qrt_apply<true>(W + (int64_t)c * m + p0, P, ldp, T, mr, pb, lane);
+    __syncthreads();
+    p0 += pb;
+  }
+  // R with the canonical gauge: diag(R) real non-negative, row j * conj(phase_j)
+  for (int64_t e = tid; e < (int64_t)k * n; e += QRT_THREADS) {
+    const int j = (int)(e / n), c = (int)(e % n);
+    cplx x = {0.0, 0.0};
+    if (c == j) x = cplx{alpha_s[j], 0.0};
+    else if (c > j) {
+      const cplx w = W[(int64_t)c * m + j], ph = phs[j];
+      x = cplx{w.re * ph.re + w.im * ph.im, w.im * ph.re - w.re * ph.im};
+    }
+    d.R[e] = x;
+  }
+  if (d.Q == nullptr) return;
+  // Q = H_0 ... H_{k-1} [I; 0], panels applied backwards
+  for (int64_t e = tid; e < (int64_t)m * k; e += QRT_THREADS) {
+    const int c = (int)(e / m), r = (int)(e % m);
+    Qt[e] = cplx{r == c ? 1.0 : 0.0, 0.0};
+  }
+  __syncthreads();
+  if (tid == 0) pstart[np] = k;
+  __syncthreads();
+  for (int q = np - 1; q >= 0; --q) {
+    const int p0 = pstart[q], mr = m - p0;
+    const int pb = pstart[q + 1] - p0;
+    const bool inl = (int64_t)pb * mr <= QRT_LDS;
+    const cplx* P = inl ? Pn : W + (int64_t)p0 * m + p0;
+    const int64_t ldp = inl ? mr : m;
+    if (inl) {
+      for (int e = tid; e < pb * mr; e += QRT_THREADS) {
+        const int c = e / mr, i = e % mr;
+        Pn[e] = W[(int64_t)(p0 + c) * m + p0 + i];
+      }
+    }
+    __syncthreads();
+    qrt_form_t(P, ldp, tau_s + p0, T, G, mr, pb);
+    for (int c = p0 + wave; c < k; c += NW)
+      qrt_apply<false>(Qt + (int64_t)c * m + p0, P, ldp, T, mr, pb, lane);
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)m * k; e += QRT_THREADS) {
+    const int r = (int)(e / k), c = (int)(e % k);
+    const cplx ph = phs[c], x = Qt[(int64_t)c * m + r];
+    d.Q[e] = cplx{x.re * ph.re - x.im * ph.im, x.re * ph.im + x.im * ph.re};
+  }
 }
 
 // ----------------------------------------------------------------- Jacobi
