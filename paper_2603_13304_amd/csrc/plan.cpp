@@ -35,6 +35,10 @@
 namespace pn {
 namespace {
 
+// largest fully merged in-leg run (complex elements) before the swallow
+// switches to the progressive contraction order
+constexpr int64_t kMergedPeakElems = int64_t(1) << 25;
+
 uint64_t mix_out0(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -322,22 +326,17 @@ struct Compiler::Lane {
     reset_scratch();
     at(stage, stepno, 0);
     move_center(ch, center, pos, pos + r - 1);
-    // --- merge
+    // --- merge the in-leg run and absorb the ket tensor.  Two orders give
+    // the same Y[a, (b_j, Q_j)..., b, p, ko...]:
+    //   merged:      multiply the run into Theta[a, (k_j b_j Q_j)..., b]
+    //                (a D^(2r) b elements), then one GEMM over all k_j;
+    //   progressive: contract the ket tensor with the first chain site over
+    //                k_1, then each further site over its left bond and k_j
+    //                together (intermediates of a D^r d Kout chi elements).
+    // The merged order is used when its Theta is small and it is not more
+    // expensive; the progressive one otherwise (many in-legs, large D).
     at(stage, stepno, 1);
-    Ref th = ch[pos].buf;
-    int64_t a = ch[pos].l, rows = int64_t(ch[pos].l) * ch[pos].P;
-    int64_t b = ch[pos].r;
-    for (int j = 1; j < r; ++j) {
-      const CSite& A = ch[pos + j];
-      Ref dst = scratch(rows * A.P * A.r);
-      gemm(th, A.buf, dst, rows, int64_t(A.P) * A.r, b, b, int64_t(A.P) * A.r,
-           int64_t(A.P) * A.r, OP_N, OP_N, o.precision, 1);
-      th = dst;
-      rows *= A.P;
-      b = A.r;
-    }
-    // --- absorb: Theta dims [a, (k_j, b_j, Q_j)..., b]
-    at(stage, stepno, 2);
+    const int64_t a = ch[pos].l, b = ch[pos + r - 1].r;
     std::vector<int> Din(r), Qin(r), carry_ids;
     for (int j = 0; j < r; ++j) {
       Din[j] = ch[pos + j].D;
@@ -348,23 +347,131 @@ struct Compiler::Lane {
     std::vector<int> Dout(s);
     for (int j = 0; j < s; ++j) Dout[j] = td[1 + st.out_slots[j]];
     if (st.open) carry_ids.push_back(st.site);
-    // theta axes: 0 = a, 1+3j = k_j, 2+3j = b_j, 3+3j = Q_j, 1+3r = b
-    std::vector<int> thd = {int(a)};
-    for (int j = 0; j < r; ++j) { thd.push_back(Din[j]); thd.push_back(Din[j]); thd.push_back(Qin[j]); }
-    thd.push_back(int(b));
-    std::vector<int> p1 = {0};
-    for (int j = 0; j < r; ++j) { p1.push_back(2 + 3 * j); p1.push_back(3 + 3 * j); }
-    p1.push_back(1 + 3 * r);
-    for (int j = 0; j < r; ++j) p1.push_back(1 + 3 * j);
-    int64_t Kin = prod(Din), Qtot_in = prod(Qin);
-    int64_t M1 = a * b * Kin * Qtot_in;     // rows (a, b_j, Q_j, b)
-    Ref X = scratch(M1 * Kin);
-    perm(th, X, thd, p1);
-    int64_t Kout = prod(Dout);
-    int64_t N1 = d * Kout;
-    Ref Y = scratch(M1 * N1);
     auto sm = C->ensure_smat(t, st.in_slots, st.out_slots, st.open);
-    gemm(X, sm.first, Y, M1, N1, Kin, Kin, N1, N1, OP_N, OP_N, o.precision, 1);
+    const int64_t Kin = prod(Din), Qtot_in = prod(Qin), Kout = prod(Dout);
+    int64_t M1 = a * b * Kin * Qtot_in;     // rows (a, b_j, Q_j, b)
+    int64_t N1 = d * Kout;
+    // cost model (complex multiply-adds) and peak intermediate of each order
+    double merged_cma = 0.0, prog_cma = 0.0;
+    double merged_peak = double(a) * ch[pos].P * ch[pos].r, prog_peak = 0.0;
+    {
+      double rows = double(a) * ch[pos].P;
+      for (int j = 1; j < r; ++j) {
+        const CSite& A = ch[pos + j];
+        merged_cma += rows * double(A.P) * A.r * A.l;
+        rows *= A.P;
+        merged_peak = std::max(merged_peak, rows * A.r);
+      }
+      merged_cma += double(M1) * Kin * N1;
+      merged_peak = std::max(merged_peak, double(M1) * N1);
+      double rest = double(a) * Din[0] * Qin[0] * (double(Kin) / Din[0]) * d * Kout;
+      prog_cma += rest * ch[pos].r * Din[0];
+      prog_peak = rest * ch[pos].r;
+      for (int j = 1; j < r; ++j) {
+        const CSite& A = ch[pos + j];
+        rest = rest / Din[j] * Din[j] * Qin[j];   // kk_j out, (b_j, Q_j) in
+        prog_cma += rest * A.l * Din[j] * A.r;
+        prog_peak = std::max(prog_peak, rest * A.r);
+      }
+    }
+    const bool progressive = r > 1 && (merged_peak > double(kMergedPeakElems) ||
+                                       prog_cma < merged_cma);
+    Ref Y;
+    if (!progressive) {
+      Ref th = ch[pos].buf;
+      int64_t rows = int64_t(ch[pos].l) * ch[pos].P, bb = ch[pos].r;
+      for (int j = 1; j < r; ++j) {
+        const CSite& A = ch[pos + j];
+        Ref dst = scratch(rows * A.P * A.r);
+        gemm(th, A.buf, dst, rows, int64_t(A.P) * A.r, bb, bb, int64_t(A.P) * A.r,
+             int64_t(A.P) * A.r, OP_N, OP_N, o.precision, 1);
+        th = dst;
+        rows *= A.P;
+        bb = A.r;
+      }
+      at(stage, stepno, 2);
+      // theta axes: 0 = a, 1+3j = k_j, 2+3j = b_j, 3+3j = Q_j, 1+3r = b
+      std::vector<int> thd = {int(a)};
+      for (int j = 0; j < r; ++j) { thd.push_back(Din[j]); thd.push_back(Din[j]); thd.push_back(Qin[j]); }
+      thd.push_back(int(b));
+      std::vector<int> p1 = {0};
+      for (int j = 0; j < r; ++j) { p1.push_back(2 + 3 * j); p1.push_back(3 + 3 * j); }
+      p1.push_back(1 + 3 * r);
+      for (int j = 0; j < r; ++j) p1.push_back(1 + 3 * j);
+      Ref X = scratch(M1 * Kin);
+      perm(th, X, thd, p1);
+      Y = scratch(M1 * N1);
+      gemm(X, sm.first, Y, M1, N1, Kin, Kin, N1, N1, OP_N, OP_N, o.precision, 1);
+    } else {
+      // axis ids: a, bond x, p, chain ket k_j, bra b_j, carry Q_j, pending
+      // ket-tensor leg kk_j, ket out-leg ko_m
+      enum { AX_A = 0, AX_X = 1, AX_P = 2 };
+      auto AX_K = [](int j) { return 100 + j; };
+      auto AX_B = [](int j) { return 200 + j; };
+      auto AX_Q = [](int j) { return 300 + j; };
+      auto AX_KK = [](int j) { return 400 + j; };
+      auto AX_KO = [](int m) { return 500 + m; };
+      struct Axes { std::vector<int> id, dim; };
+      auto reorder = [&](Ref src, const Axes& in, const std::vector<int>& order, Axes* out) {
+        std::vector<int> pm;
+        out->id = order;
+        out->dim.clear();
+        for (int id : order) {
+          int k = int(std::find(in.id.begin(), in.id.end(), id) - in.id.begin());
+          pm.push_back(k);
+          out->dim.push_back(in.dim[k]);
+        }
+        Ref dst = scratch(prod(out->dim));
+        perm(src, dst, in.dim, pm);
+        return dst;
+      };
+      // chain site [a, (k_0 b_0 Q_0), x] -> rows (a, b_0, Q_0, x), cols k_0
+      Axes c0{{AX_A, AX_K(0), AX_B(0), AX_Q(0), AX_X},
+              {int(a), Din[0], Din[0], Qin[0], ch[pos].r}};
+      Axes xm;
+      Ref Xm = reorder(ch[pos].buf, c0, {AX_A, AX_B(0), AX_Q(0), AX_X, AX_K(0)}, &xm);
+      const int64_t M0 = a * Din[0] * Qin[0] * ch[pos].r;
+      const int64_t N0 = (Kin / Din[0]) * d * Kout;
+      Y = scratch(M0 * N0);
+      gemm(Xm, sm.first, Y, M0, N0, Din[0], Din[0], N0, N0, OP_N, OP_N, o.precision, 1);
+      Axes ya{{AX_A, AX_B(0), AX_Q(0), AX_X}, {int(a), Din[0], Qin[0], ch[pos].r}};
+      for (int j = 1; j < r; ++j) { ya.id.push_back(AX_KK(j)); ya.dim.push_back(Din[j]); }
+      ya.id.push_back(AX_P);
+      ya.dim.push_back(d);
+      for (int m = 0; m < s; ++m) { ya.id.push_back(AX_KO(m)); ya.dim.push_back(Dout[m]); }
+      for (int j = 1; j < r; ++j) {
+        // contract (x, kk_j) of Y with (x, k_j) of chain site j [x, (k_j b_j Q_j), x']
+        const CSite& A = ch[pos + j];
+        std::vector<int> order;
+        for (int id : ya.id)
+          if (id != AX_X && id != AX_KK(j)) order.push_back(id);
+        const int64_t Mj = prod(ya.dim) / (int64_t(A.l) * Din[j]);
+        order.push_back(AX_X);
+        order.push_back(AX_KK(j));
+        Axes ym;
+        Ref Ym = reorder(Y, ya, order, &ym);
+        const int64_t Kj = int64_t(A.l) * Din[j], Nj = int64_t(Din[j]) * Qin[j] * A.r;
+        Ref Yn = scratch(Mj * Nj);
+        gemm(Ym, A.buf, Yn, Mj, Nj, Kj, Kj, Nj, Nj, OP_N, OP_N, o.precision, 1);
+        ya.id.assign(order.begin(), order.end() - 2);
+        ya.dim.assign(ym.dim.begin(), ym.dim.end() - 2);
+        ya.id.push_back(AX_B(j)); ya.dim.push_back(Din[j]);
+        ya.id.push_back(AX_Q(j)); ya.dim.push_back(Qin[j]);
+        ya.id.push_back(AX_X); ya.dim.push_back(A.r);
+        Y = Yn;
+      }
+      at(stage, stepno, 2);
+      // to the layout [a, (b_j, Q_j)..., b, p, ko...]
+      std::vector<int> order = {AX_A};
+      for (int j = 0; j < r; ++j) { order.push_back(AX_B(j)); order.push_back(AX_Q(j)); }
+      order.push_back(AX_X);
+      order.push_back(AX_P);
+      for (int m = 0; m < s; ++m) order.push_back(AX_KO(m));
+      if (order != ya.id) {
+        Axes yo;
+        Y = reorder(Y, ya, order, &yo);
+      }
+    }
     // Y axes: 0 = a, 1+2j = b_j, 2+2j = Q_j, 1+2r = b, 2+2r = p, 3+2r+m = ko_m
     std::vector<int> yd = {int(a)};
     for (int j = 0; j < r; ++j) { yd.push_back(Din[j]); yd.push_back(Qin[j]); }
