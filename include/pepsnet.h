@@ -142,6 +142,28 @@ int32_t pepsnet_sweep_stats(pepsnet_t h, double* contraction_flops, double* gemm
 int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_t* launches,
                                double* flops, double* bytes);
 
+/* ---- batched sweeps (independent blocks of uneven N, D, chi in one launch
+ * sequence).  BlockBP message updates of different blocks are independent
+ * (Sec. "The Block Belief-Propagation Algorithm", complexity discussion:
+ * the sides can be computed in parallel); a batch merges the sweep plans of
+ * n handles so that every kernel launch serves the same stage of every
+ * handle's message updates, optionally replayed as one captured HIP graph.
+ * Results are bit-identical to sweeping each handle on its own. */
+typedef struct pepsnet_batch_s* pepsnet_batch_t;
+
+/* Merge the sweep plans of hs[0..n) (distinct handles, borrowed: they must
+ * outlive the batch).  stream: borrowed hipStream_t, NULL to create one. */
+int32_t pepsnet_batch_create(const pepsnet_t* hs, int32_t n, void* stream, pepsnet_batch_t* out);
+int32_t pepsnet_batch_use_graph(pepsnet_batch_t b, int32_t on);
+/* Run `sweeps` Jacobi sweeps of every handle.  max_err[i] (n doubles, may be
+ * NULL) receives handle i's largest message distance of the last sweep, *ms
+ * (may be NULL) the device time of the sweeps from HIP events.  Fails with
+ * BBP_EINVAL if a handle was swept on its own since the batch was made. */
+int32_t blockbp_sweep_batch(pepsnet_batch_t b, int32_t sweeps, double* max_err, double* ms);
+/* GEMM flops of one merged sweep and its number of kernel launches. */
+int32_t pepsnet_batch_stats(pepsnet_batch_t b, double* gemm_flops, int64_t* launches);
+void pepsnet_batch_destroy(pepsnet_batch_t b);
+
 void pepsnet_destroy(pepsnet_t h);
 const char* pepsnet_last_error(void);
 

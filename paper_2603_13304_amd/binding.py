@@ -68,6 +68,11 @@ def load_library():
         "pepsnet_destroy": (None, [vp]),
         "pepsnet_last_error": (C.c_char_p, []),
         "pepsnet_describe": (i32, [P(Desc), i32, i32, i32, i32, P(i32), P(i32), i64, P(i64)]),
+        "pepsnet_batch_create": (i32, [P(vp), i32, vp, P(vp)]),
+        "pepsnet_batch_use_graph": (i32, [vp, i32]),
+        "blockbp_sweep_batch": (i32, [vp, i32, P(dbl), P(dbl)]),
+        "pepsnet_batch_stats": (i32, [vp, P(dbl), P(i64)]),
+        "pepsnet_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -212,6 +217,46 @@ class PepsNet:
         cf, gf, nl = C.c_double(0.0), C.c_double(0.0), C.c_int64(0)
         _check(self.lib.pepsnet_sweep_stats(self.h, C.byref(cf), C.byref(gf), C.byref(nl)))
         return cf.value, gf.value, nl.value
+
+class Batch:
+    """Batched sweeps over several handles (pepsnet_batch_*): one launch
+    sequence serves the same stage of every handle's message updates."""
+
+    def __init__(self, nets, stream=None):
+        self.lib = load_library()
+        self.nets = list(nets)          # keep the handles alive
+        arr = (C.c_void_p * len(self.nets))(*[n.h.value for n in self.nets])
+        h = C.c_void_p()
+        _check(self.lib.pepsnet_batch_create(arr, len(self.nets),
+                                             None if stream is None else C.c_void_p(stream),
+                                             C.byref(h)))
+        self.h = h
+
+    def use_graph(self, on=True):
+        _check(self.lib.pepsnet_batch_use_graph(self.h, int(on)))
+
+    def sweep(self, n=1):
+        errs = np.zeros(len(self.nets))
+        ms = C.c_double(0.0)
+        _check(self.lib.blockbp_sweep_batch(self.h, n, _dptr(errs), C.byref(ms)))
+        return errs, ms.value
+
+    def stats(self):
+        gf, nl = C.c_double(0.0), C.c_int64(0)
+        _check(self.lib.pepsnet_batch_stats(self.h, C.byref(gf), C.byref(nl)))
+        return gf.value, nl.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pepsnet_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 PROFILE_KINDS = ["gemm", "transpose", "qr", "jacobi", "sketch", "norm", "pad", "msg_phase",
                  "split_gauge"]

@@ -46,7 +46,8 @@ struct LaunchRec {
   int count = 0;
   dim3 grid;
   size_t lds = 0;
-  int variant = 0;       // kernel variant (Jacobi: 1 = rows split LDS / work buffer)
+  int variant = 0;       // kernel variant (QR: 1 = blocked tall kernel; Jacobi: 1 = rows
+                         // split between LDS and the work buffer)
   double gemm_flops = 0.0, contraction_flops = 0.0;
   double flops = 0.0;    // algorithmic flops of the launch (8 per complex MAC)
   double bytes = 0.0;    // algorithmic bytes moved (operands read once, results written once)
@@ -74,6 +75,8 @@ struct pepsnet_s {
   char* desc_dev = nullptr;
   std::vector<char> desc_host;
   Compiled prep, sweep[2], expect[2];
+  // the sweep plans' ops per lane, kept for merging into batches
+  std::vector<std::vector<std::pair<WaveKey, Op>>> sweep_lanes[2];
   std::vector<std::vector<int>> carry_order[2];
   std::vector<int64_t> rho_off[2];
   std::vector<std::pair<int, int>> bonds;
@@ -88,6 +91,24 @@ struct pepsnet_s {
   int64_t timed_sweeps = 0;
   int64_t site_len = 0;
   double* pinned = nullptr;   // host pinned: [0] sweep counter, [1..] distances
+};
+
+
+// A batch merges the sweep plans of several handles into one launch
+// sequence: ops of every handle at the same wave key share a launch.
+// Variant v of the merged plan runs handle i on message set
+// base_parity[i] ^ v.
+struct pepsnet_batch_s {
+  std::vector<pepsnet_s*> hs;
+  std::vector<int> base_parity;
+  Compiled sweep[2];
+  std::vector<char> desc_host[2];
+  char* desc_dev[2] = {nullptr, nullptr};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool use_graph = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double last_ms = 0.0;
 };
 
 namespace {
@@ -105,12 +126,37 @@ size_t push_descs(std::vector<char>* blob, const std::vector<T>& v) {
   return off;
 }
 
-void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, Op>>>& lanes,
-                 Compiled* out) {
-  // (wave key, lane, op index)
-  std::vector<std::tuple<WaveKey, int, int>> all;
-  for (size_t L = 0; L < lanes.size(); ++L)
-    for (size_t k = 0; k < lanes[L].size(); ++k) all.emplace_back(lanes[L][k].first, int(L), int(k));
+// kernel variant an op runs with (part of its bucket key, so that an item
+// runs the same kernel whether it is launched alone or in a batch)
+int op_variant(const Op& op) {
+  if (op.type == OPK_QR) {
+    const int64_t m = op.i[0], n = op.i[1], k = std::min(m, n);
+    return m * (n + (op.c.valid() ? k : 0)) <= QR_LDS_MAX ? 0 : 1;
+  }
+  if (op.type == OPK_JACOBI) {
+    const int rows = int(op.i[0]), cols = int(op.i[1]);
+    return jacobi_lds_slices(rows, cols) < (rows + 15) / 16 ? 1 : 0;
+  }
+  return 0;
+}
+
+typedef std::vector<std::vector<std::pair<WaveKey, Op>>> LaneList;
+struct OpSource {
+  pepsnet_s* h;          // resolves the op's references
+  const LaneList* lanes;
+};
+
+// Bucket the ops of every source by wave key, then by (kind, precision,
+// variant), and emit one launch per bucket with its descriptors in `blob`.
+void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Compiled* out) {
+  // (wave key, source, lane, op index)
+  std::vector<std::tuple<WaveKey, int, int, int>> all;
+  for (size_t S = 0; S < srcs.size(); ++S) {
+    const LaneList& lanes = *srcs[S].lanes;
+    for (size_t L = 0; L < lanes.size(); ++L)
+      for (size_t k = 0; k < lanes[L].size(); ++k)
+        all.emplace_back(lanes[L][k].first, int(S), int(L), int(k));
+  }
   std::stable_sort(all.begin(), all.end(), [](const auto& a, const auto& b) {
     return std::get<0>(a) < std::get<0>(b);
   });
@@ -120,23 +166,27 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
     while (j < all.size() && !(std::get<0>(all[i]) < std::get<0>(all[j])) &&
            !(std::get<0>(all[j]) < std::get<0>(all[i])))
       ++j;
-    std::map<std::pair<int, int>, std::vector<const Op*>> buckets;
+    std::map<std::tuple<int, int, int>, std::vector<std::pair<pepsnet_s*, const Op*>>> buckets;
     for (size_t t = i; t < j; ++t) {
-      const Op& op = lanes[std::get<1>(all[t])][std::get<2>(all[t])].second;
+      const OpSource& src = srcs[std::get<1>(all[t])];
+      const Op& op = (*src.lanes)[std::get<2>(all[t])][std::get<3>(all[t])].second;
       int prec = op.type == OPK_GEMM ? int(op.i[8]) : 0;
-      buckets[{op.type, prec}].push_back(&op);
+      buckets[{op.type, prec, op_variant(op)}].push_back({src.h, &op});
     }
     for (auto& bk : buckets) {
       LaunchRec rec;
-      rec.type = bk.first.first;
-      rec.prec = bk.first.second;
+      rec.type = std::get<0>(bk.first);
+      rec.prec = std::get<1>(bk.first);
+      rec.variant = std::get<2>(bk.first);
       rec.count = int(bk.second.size());
       const auto& ops = bk.second;
       switch (rec.type) {
         case OPK_GEMM: {
           std::vector<GemmDesc> v;
           int64_t mM = 1, mN = 1;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             GemmDesc g;
             g.A = resolve(h, op->a); g.B = resolve(h, op->b); g.C = resolve(h, op->c);
             g.M = int(op->i[0]); g.N = int(op->i[1]); g.K = int(op->i[2]);
@@ -153,7 +203,7 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             if (op->i[9]) rec.contraction_flops += f;
             v.push_back(g);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned((mN + 63) / 64),
                           unsigned(std::min<int64_t>(65535, (mM + 63) / 64)), unsigned(v.size()));
           break;
@@ -161,7 +211,9 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
         case OPK_PERM: {
           std::vector<PermDesc> v;
           int64_t mt = 1;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             PermDesc p;
             std::memset(&p, 0, sizeof p);
             p.src = resolve(h, op->a); p.dst = resolve(h, op->b);
@@ -176,15 +228,16 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             rec.bytes += 32.0 * double(p.total);
             v.push_back(p);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(std::min<int64_t>(4096, (mt + 255) / 256)), unsigned(v.size()));
           break;
         }
         case OPK_QR: {
           std::vector<QrDesc> v;
           int64_t lds_elems = 0;
-          bool tall = false;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             QrDesc q;
             q.A = resolve(h, op->a); q.work = resolve(h, op->b);
             q.Q = resolve(h, op->c); q.R = resolve(h, op->d);
@@ -197,28 +250,26 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             rec.bytes += 16.0 * (m * n + (q.Q ? m * k : 0.0) + k * n);
             int64_t need = int64_t(q.m) * (q.n + (q.Q ? std::min(q.m, q.n) : 0));
             if (need <= QR_LDS_MAX) lds_elems = std::max(lds_elems, need);
-            else tall = true;
             v.push_back(q);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(v.size()));
-          // blocked kernel (panel in LDS) when any working copy overflows LDS
-          rec.variant = tall ? 1 : 0;
-          rec.lds = tall ? size_t(QRT_LDS) * sizeof(cplx) : size_t(lds_elems) * sizeof(cplx);
+          // blocked kernel (panel in LDS) for working copies that overflow LDS
+          rec.lds = rec.variant ? size_t(QRT_LDS) * sizeof(cplx) : size_t(lds_elems) * sizeof(cplx);
           break;
         }
         case OPK_JACOBI: {
           std::vector<JacobiDesc> v;
           int64_t lds_elems = 0;
-          bool split = false;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             JacobiDesc jd;
             jd.A = resolve(h, op->a); jd.work = resolve(h, op->b); jd.U = resolve(h, op->c);
             jd.sigma = reinterpret_cast<double*>(resolve(h, op->d));
             jd.rows = int(op->i[0]); jd.cols = int(op->i[1]); jd.lda = int(op->i[2]);
             jd.conjT = int(op->i[3]); jd.keep = int(op->i[4]);
             const int nl = jacobi_lds_slices(jd.rows, jd.cols);
-            if (nl < (jd.rows + 15) / 16) split = true;
             lds_elems = std::max<int64_t>(lds_elems, int64_t(nl) * 16 * jd.cols);
             // one sweep of cols(cols-1)/2 rotations, each three length-rows dot
             // products (a, b, g: 2 + 2 + 4 real flops per row) and the update
@@ -228,16 +279,17 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             rec.bytes += 16.0 * (double(jd.rows) * jd.cols + double(jd.rows) * jd.keep);
             v.push_back(jd);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(v.size()));
           rec.lds = size_t(lds_elems) * sizeof(cplx);
-          rec.variant = split ? 1 : 0;
           break;
         }
         case OPK_OMEGA: {
           std::vector<OmegaDesc> v;
           int64_t mt = 1;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             OmegaDesc o;
             o.out = resolve(h, op->a);
             o.n = int(op->i[0]); o.k = int(op->i[1]);
@@ -247,13 +299,15 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             rec.bytes += 16.0 * double(o.n) * o.k;
             v.push_back(o);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(std::min<int64_t>(1024, (mt + 255) / 256)), unsigned(v.size()));
           break;
         }
         case OPK_NORM: {
           std::vector<NormDesc> v;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             NormDesc nd;
             nd.x = resolve(h, op->a);
             nd.len = op->i[0];
@@ -262,14 +316,16 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             nd.norm_out = op->s1.off >= 0 ? h->scal + op->s1.off : nullptr;
             v.push_back(nd);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(v.size()));
           break;
         }
         case OPK_PAD: {
           std::vector<PadDesc> v;
           int64_t mt = 1;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             PadDesc p;
             p.src = resolve(h, op->a); p.dst = resolve(h, op->b);
             p.l1 = int(op->i[0]); p.P = int(op->i[1]); p.r1 = int(op->i[2]);
@@ -280,25 +336,29 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             rec.bytes += 16.0 * (double(p.l1) * p.P * p.r1 + double(p.l2) * p.P * p.r2);
             v.push_back(p);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(std::min<int64_t>(4096, (mt + 255) / 256)), unsigned(v.size()));
           break;
         }
         case OPK_COLPHASE: {
           std::vector<ColPhaseDesc> v;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             ColPhaseDesc c;
             c.L = resolve(h, op->a); c.R = resolve(h, op->b);
             c.m = int(op->i[0]); c.keep = int(op->i[1]); c.n = int(op->i[2]);
             v.push_back(c);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(v.size()));
           break;
         }
         case OPK_PHASE: {
           std::vector<PhaseDesc> v;
-          for (const Op* op : ops) {
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
             PhaseDesc p;
             std::memset(&p, 0, sizeof p);
             p.nsites = int(op->i[0]);
@@ -311,7 +371,7 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
             }
             v.push_back(p);
           }
-          rec.desc_off = push_descs(&h->desc_host, v);
+          rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(v.size()));
           break;
         }
@@ -324,78 +384,82 @@ void compile_ops(pepsnet_s* h, const std::vector<std::vector<std::pair<WaveKey, 
   }
 }
 
-hipError_t launch(pepsnet_s* h, const LaunchRec& r) {
-  const void* d = h->desc_dev + r.desc_off;
+hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r) {
+  const void* d = desc_dev + r.desc_off;
   dim3 blk(256);
   switch (r.type) {
     case OPK_GEMM:
       if (r.prec == PREC_FP64)
-        hipLaunchKernelGGL(k_gemm<PREC_FP64>, r.grid, blk, 0, h->stream, (const GemmDesc*)d);
+        hipLaunchKernelGGL(k_gemm<PREC_FP64>, r.grid, blk, 0, stream, (const GemmDesc*)d);
       else if (r.prec == PREC_FP32)
-        hipLaunchKernelGGL(k_gemm<PREC_FP32>, r.grid, blk, 0, h->stream, (const GemmDesc*)d);
+        hipLaunchKernelGGL(k_gemm<PREC_FP32>, r.grid, blk, 0, stream, (const GemmDesc*)d);
       else
-        hipLaunchKernelGGL(k_gemm<PREC_BF16X3>, r.grid, blk, 0, h->stream, (const GemmDesc*)d);
+        hipLaunchKernelGGL(k_gemm<PREC_BF16X3>, r.grid, blk, 0, stream, (const GemmDesc*)d);
       break;
     case OPK_PERM:
-      hipLaunchKernelGGL(k_permute, r.grid, blk, 0, h->stream, (const PermDesc*)d);
+      hipLaunchKernelGGL(k_permute, r.grid, blk, 0, stream, (const PermDesc*)d);
       break;
     case OPK_QR:
       if (r.variant)
-        hipLaunchKernelGGL(k_qr_tall, r.grid, dim3(QRT_THREADS), r.lds, h->stream,
+        hipLaunchKernelGGL(k_qr_tall, r.grid, dim3(QRT_THREADS), r.lds, stream,
                            (const QrDesc*)d);
       else
-        hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, h->stream, (const QrDesc*)d);
+        hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, stream, (const QrDesc*)d);
       break;
     case OPK_JACOBI:
       if (r.variant)
-        hipLaunchKernelGGL(k_jacobi<true>, r.grid, dim3(JAC_THREADS), r.lds, h->stream,
+        hipLaunchKernelGGL(k_jacobi<true>, r.grid, dim3(JAC_THREADS), r.lds, stream,
                            (const JacobiDesc*)d);
       else
-        hipLaunchKernelGGL(k_jacobi<false>, r.grid, dim3(JAC_THREADS), r.lds, h->stream,
+        hipLaunchKernelGGL(k_jacobi<false>, r.grid, dim3(JAC_THREADS), r.lds, stream,
                            (const JacobiDesc*)d);
       break;
     case OPK_OMEGA:
-      hipLaunchKernelGGL(k_omega, r.grid, blk, 0, h->stream, (const OmegaDesc*)d);
+      hipLaunchKernelGGL(k_omega, r.grid, blk, 0, stream, (const OmegaDesc*)d);
       break;
     case OPK_NORM:
-      hipLaunchKernelGGL(k_normalize, r.grid, blk, 0, h->stream, (const NormDesc*)d);
+      hipLaunchKernelGGL(k_normalize, r.grid, blk, 0, stream, (const NormDesc*)d);
       break;
     case OPK_PAD:
-      hipLaunchKernelGGL(k_pad, r.grid, blk, 0, h->stream, (const PadDesc*)d);
+      hipLaunchKernelGGL(k_pad, r.grid, blk, 0, stream, (const PadDesc*)d);
       break;
     case OPK_PHASE:
-      hipLaunchKernelGGL(k_phase, r.grid, blk, 0, h->stream, (const PhaseDesc*)d);
+      hipLaunchKernelGGL(k_phase, r.grid, blk, 0, stream, (const PhaseDesc*)d);
       break;
     case OPK_COLPHASE:
-      hipLaunchKernelGGL(k_colphase, r.grid, blk, 0, h->stream, (const ColPhaseDesc*)d);
+      hipLaunchKernelGGL(k_colphase, r.grid, blk, 0, stream, (const ColPhaseDesc*)d);
       break;
   }
   return hipGetLastError();
 }
 
-int32_t run_compiled(pepsnet_s* h, Compiled* c, bool allow_graph) {
-  if (allow_graph && h->use_graph) {
+int32_t run_launches(const char* desc_dev, hipStream_t stream, Compiled* c, bool graph) {
+  if (graph) {
     if (!c->exec) {
-      PN_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+      PN_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
       for (const LaunchRec& r : c->launches) {
-        hipError_t e = launch(h, r);
+        hipError_t e = launch(desc_dev, stream, r);
         if (e != hipSuccess) {
           hipGraph_t g;
-          hipStreamEndCapture(h->stream, &g);
+          hipStreamEndCapture(stream, &g);
           return fail(BBP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
         }
       }
-      PN_HIP(hipStreamEndCapture(h->stream, &c->graph));
+      PN_HIP(hipStreamEndCapture(stream, &c->graph));
       PN_HIP(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
     }
-    PN_HIP(hipGraphLaunch(c->exec, h->stream));
+    PN_HIP(hipGraphLaunch(c->exec, stream));
     return BBP_OK;
   }
   for (const LaunchRec& r : c->launches) {
-    hipError_t e = launch(h, r);
+    hipError_t e = launch(desc_dev, stream, r);
     if (e != hipSuccess) return fail(BBP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   }
   return BBP_OK;
+}
+
+int32_t run_compiled(pepsnet_s* h, Compiled* c, bool allow_graph) {
+  return run_launches(h->desc_dev, h->stream, c, allow_graph && h->use_graph);
 }
 
 std::string build_problem(const pepsnet_desc* d, Problem* P) {
@@ -524,15 +588,14 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
       prep[0].push_back({wk, C.prep_ops[k]});
     }
     // prep ops are independent: one wave
-    compile_ops(h.get(), prep, &h->prep);
+    compile_ops({{h.get(), &prep}}, &h->desc_host, &h->prep);
   }
   for (int par = 0; par < 2; ++par) {
-    std::vector<std::vector<std::pair<WaveKey, Op>>> lanes;
-    for (auto& L : sp[par].lanes) lanes.push_back(L.ops);
-    compile_ops(h.get(), lanes, &h->sweep[par]);
-    lanes.clear();
+    for (auto& L : sp[par].lanes) h->sweep_lanes[par].push_back(L.ops);
+    compile_ops({{h.get(), &h->sweep_lanes[par]}}, &h->desc_host, &h->sweep[par]);
+    LaneList lanes;
     for (auto& L : ep[par].lanes) lanes.push_back(L.ops);
-    compile_ops(h.get(), lanes, &h->expect[par]);
+    compile_ops({{h.get(), &lanes}}, &h->desc_host, &h->expect[par]);
   }
   int nb = int(h->bonds.size());
   if (hipMalloc(&h->rho_mat, size_t(std::max(nb, 1)) * 16 * sizeof(cplx)) != hipSuccess ||
@@ -762,7 +825,7 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
                           hipMemcpyHostToDevice, h->stream));
     for (size_t i = 0; i < c.launches.size(); ++i) {
       PN_HIP(hipEventRecord(ev[2 * i], h->stream));
-      hipError_t e = launch(h, c.launches[i]);
+      hipError_t e = launch(h->desc_dev, h->stream, c.launches[i]);
       if (e != hipSuccess) return fail(BBP_EDEVICE, hipGetErrorString(e));
       PN_HIP(hipEventRecord(ev[2 * i + 1], h->stream));
     }
@@ -788,6 +851,118 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
     if (bytes) bytes[k] = tby[k];
   }
   return BBP_OK;
+}
+
+int32_t pepsnet_batch_create(const pepsnet_t* hs, int32_t n, void* stream, pepsnet_batch_t* out) {
+  if (!hs || n < 1 || !out) return fail(BBP_EINVAL, "bad arguments");
+  std::unique_ptr<pepsnet_batch_s> b(new pepsnet_batch_s());
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i]) return fail(BBP_EINVAL, "null handle in batch");
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == hs[i]) return fail(BBP_EINVAL, "handle listed twice in batch");
+    b->hs.push_back(hs[i]);
+    b->base_parity.push_back(hs[i]->parity);
+  }
+  if (stream) {
+    b->stream = static_cast<hipStream_t>(stream);
+  } else {
+    PN_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->own_stream = true;
+  }
+  for (int v = 0; v < 2; ++v) {
+    std::vector<OpSource> srcs;
+    for (int i = 0; i < n; ++i)
+      srcs.push_back({b->hs[i], &b->hs[i]->sweep_lanes[b->base_parity[i] ^ v]});
+    compile_ops(srcs, &b->desc_host[v], &b->sweep[v]);
+    if (hipMalloc(&b->desc_dev[v], std::max<size_t>(b->desc_host[v].size(), 256)) != hipSuccess)
+      return fail(BBP_ENOMEM, "batch descriptor allocation failed");
+    PN_HIP(hipMemcpyAsync(b->desc_dev[v], b->desc_host[v].data(), b->desc_host[v].size(),
+                          hipMemcpyHostToDevice, b->stream));
+  }
+  PN_HIP(hipEventCreate(&b->ev0));
+  PN_HIP(hipEventCreate(&b->ev1));
+  PN_HIP(hipStreamSynchronize(b->stream));
+  *out = b.release();
+  return BBP_OK;
+}
+
+int32_t pepsnet_batch_use_graph(pepsnet_batch_t b, int32_t on) {
+  if (!b) return fail(BBP_EINVAL, "null batch");
+  b->use_graph = on != 0;
+  return BBP_OK;
+}
+
+int32_t blockbp_sweep_batch(pepsnet_batch_t b, int32_t sweeps, double* max_err, double* ms) {
+  if (!b || sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
+  const int n = int(b->hs.size());
+  const int v = b->hs[0]->parity ^ b->base_parity[0];
+  for (int i = 0; i < n; ++i)
+    if ((b->hs[i]->parity ^ b->base_parity[i]) != v)
+      return fail(BBP_EINVAL, "a handle of the batch was swept on its own; recreate the batch");
+  // work already queued on the handles' own streams comes first
+  for (pepsnet_s* h : b->hs) PN_HIP(hipStreamSynchronize(h->stream));
+  std::vector<double> errs(n, 0.0);
+  double total_ms = 0.0;
+  for (int s = 0; s < sweeps; ++s) {
+    const int var = b->hs[0]->parity ^ b->base_parity[0];
+    for (pepsnet_s* h : b->hs) {
+      h->pinned[0] = double(h->sweeps_total);
+      PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
+                            hipMemcpyHostToDevice, b->stream));
+    }
+    PN_HIP(hipEventRecord(b->ev0, b->stream));
+    int32_t rc = run_launches(b->desc_dev[var], b->stream, &b->sweep[var], b->use_graph);
+    if (rc) return rc;
+    PN_HIP(hipEventRecord(b->ev1, b->stream));
+    for (pepsnet_s* h : b->hs) {
+      const int nm = int(h->P.msg_keys.size());
+      PN_HIP(hipMemcpyAsync(h->pinned + 1, h->scal + h->comp->err_slot(0), nm * sizeof(double),
+                            hipMemcpyDeviceToHost, b->stream));
+    }
+    PN_HIP(hipStreamSynchronize(b->stream));
+    float e_ms = 0.0f;
+    PN_HIP(hipEventElapsedTime(&e_ms, b->ev0, b->ev1));
+    total_ms += e_ms;
+    for (int i = 0; i < n; ++i) {
+      pepsnet_s* h = b->hs[i];
+      const int nm = int(h->P.msg_keys.size());
+      double e = 0.0;
+      for (int m = 0; m < nm; ++m) {
+        if (!std::isfinite(h->pinned[1 + m])) return fail(BBP_ENUMERIC, "non-finite message after a sweep");
+        e = std::max(e, h->pinned[1 + m]);
+      }
+      errs[i] = e;
+      h->parity ^= 1;
+      h->sweeps_total += 1;
+    }
+  }
+  b->last_ms = total_ms;
+  if (max_err)
+    for (int i = 0; i < n; ++i) max_err[i] = errs[i];
+  if (ms) *ms = total_ms;
+  return BBP_OK;
+}
+
+int32_t pepsnet_batch_stats(pepsnet_batch_t b, double* gemm_flops, int64_t* launches) {
+  if (!b) return fail(BBP_EINVAL, "null batch");
+  const int v = b->hs[0]->parity ^ b->base_parity[0];
+  if (gemm_flops) *gemm_flops = b->sweep[v].gemm_flops;
+  if (launches) *launches = int64_t(b->sweep[v].launches.size());
+  return BBP_OK;
+}
+
+void pepsnet_batch_destroy(pepsnet_batch_t b) {
+  if (!b) return;
+  if (b->stream) hipStreamSynchronize(b->stream);
+  for (int v = 0; v < 2; ++v) {
+    if (b->sweep[v].exec) hipGraphExecDestroy(b->sweep[v].exec);
+    if (b->sweep[v].graph) hipGraphDestroy(b->sweep[v].graph);
+    if (b->desc_dev[v]) hipFree(b->desc_dev[v]);
+  }
+  if (b->ev0) hipEventDestroy(b->ev0);
+  if (b->ev1) hipEventDestroy(b->ev1);
+  if (b->own_stream && b->stream) hipStreamDestroy(b->stream);
+  delete b;
 }
 
 void pepsnet_destroy(pepsnet_t h) {
