@@ -42,6 +42,7 @@ typedef struct pepsnet_s* pepsnet_t;
 enum {
   BBP_OK = 0,
   BBP_NOT_CONVERGED = 1, /* warning: max_sweeps reached, outputs valid */
+  BBP_PENDING = 2,       /* bbp_server_poll: the request has not finished yet */
   BBP_EINVAL = -1,       /* bad argument; nothing changed */
   BBP_ENOMEM = -2,       /* device allocation failed */
   BBP_EDEVICE = -3,      /* HIP runtime error */
@@ -163,6 +164,50 @@ int32_t blockbp_sweep_batch(pepsnet_batch_t b, int32_t sweeps, double* max_err, 
 /* GEMM flops of one merged sweep and its number of kernel launches. */
 int32_t pepsnet_batch_stats(pepsnet_batch_t b, double* gemm_flops, int64_t* launches);
 void pepsnet_batch_destroy(pepsnet_batch_t b);
+
+/* ---- device memory of a handle.  Resident: site tensors, their permuted
+ * matrices, both message sets, expectation outputs and descriptors.
+ * Workspace: the boundary chains and scratch of the message updates, needed
+ * only while a sweep or expectation runs.  Releasing it keeps the state
+ * (messages stay on the device); acquiring it again re-resolves the launch
+ * descriptors (batches made before become invalid).  Sweeps, expectations
+ * and profiling fail with BBP_EINVAL while the workspace is released. */
+int32_t pepsnet_memory(pepsnet_t h, int64_t* resident_bytes, int64_t* workspace_bytes);
+int32_t pepsnet_release_workspace(pepsnet_t h);
+int32_t pepsnet_acquire_workspace(pepsnet_t h);
+
+/* ---- serving loop (continuous batching of expectation requests on
+ * resident states).  A request on a state optionally replaces its site
+ * tensors (an imaginary-time step: messages are kept, a warm start as in the
+ * thesis's ITE algorithm), sweeps to tol or max_sweeps and evaluates the
+ * default bonds' <S_i . S_j> and the energy per site.  A worker thread admits
+ * queued requests in arrival order whenever an in-flight slot is free and the
+ * state's workspace fits in the HBM budget (a request that does not fit lets
+ * later ones pass; one request per state at a time), acquires the workspace
+ * for the request's duration, and advances every in-flight request on its
+ * state's own stream, so requests overlap on the device.  Results are those
+ * of running the request alone.  States must not be used by the caller while
+ * they have requests in the server; give each state its own stream (desc
+ * stream NULL) for overlap.  submit and poll are thread-safe. */
+typedef struct bbp_server_s* bbp_server_t;
+int32_t bbp_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, bbp_server_t* out);
+/* new_sites: NULL (unchanged) or sites_len doubles as for pepsnet_set_sites. */
+int32_t bbp_server_submit(bbp_server_t s, pepsnet_t state, const double* new_sites,
+                          int64_t sites_len, double tol, int32_t max_sweeps, uint64_t* ticket);
+/* Collect a request: BBP_PENDING if not finished and wait == 0; otherwise the
+ * request's code (BBP_OK, BBP_NOT_CONVERGED or an error) with the outputs:
+ * energy per site, up to cap bond values (*n_bonds gets the count), sweeps
+ * run, last message distance and the submit-to-completion latency in
+ * seconds.  A ticket is collected once. */
+int32_t bbp_server_poll(bbp_server_t s, uint64_t ticket, int32_t wait, double* energy_per_site,
+                        double* bond_ss, int32_t cap, int32_t* n_bonds, int32_t* sweeps_done,
+                        double* max_err, double* latency_s);
+/* Peak workspace bytes held and peak in-flight requests so far, requests
+ * completed and requests still queued. */
+int32_t bbp_server_stats(bbp_server_t s, int64_t* peak_bytes, int32_t* peak_inflight,
+                         int64_t* completed, int32_t* queued);
+/* Finishes queued and in-flight requests, then stops the worker. */
+void bbp_server_destroy(bbp_server_t s);
 
 void pepsnet_destroy(pepsnet_t h);
 const char* pepsnet_last_error(void);

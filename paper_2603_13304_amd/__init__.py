@@ -6,5 +6,5 @@ it and nothing else.  There is no CPU fallback: importing the binding fails
 when the library has not been built.
 """
 from .binding import (BBP_BF16X3, BBP_FP32, BBP_FP64, BBP_KAGOME_INF_HEX,  # noqa: F401
-                      BBP_KAGOME_OPEN, BBP_SVD_FULL, BBP_SVD_RAND, Batch, PepsNet,
+                      BBP_KAGOME_OPEN, BBP_SVD_FULL, BBP_SVD_RAND, Batch, PepsNet, Server,
                       PepsnetError, describe, library_path, load_library)

@@ -12,6 +12,7 @@ import os
 import numpy as np
 
 BBP_KAGOME_OPEN, BBP_KAGOME_INF_HEX = 1, 2
+BBP_OK, BBP_NOT_CONVERGED, BBP_PENDING = 0, 1, 2
 BBP_FP64, BBP_FP32, BBP_BF16X3 = 0, 1, 2
 BBP_SVD_FULL, BBP_SVD_RAND = 0, 1
 ABI_VERSION = 1
@@ -73,6 +74,15 @@ def load_library():
         "blockbp_sweep_batch": (i32, [vp, i32, P(dbl), P(dbl)]),
         "pepsnet_batch_stats": (i32, [vp, P(dbl), P(i64)]),
         "pepsnet_batch_destroy": (None, [vp]),
+        "pepsnet_memory": (i32, [vp, P(i64), P(i64)]),
+        "pepsnet_release_workspace": (i32, [vp]),
+        "pepsnet_acquire_workspace": (i32, [vp]),
+        "bbp_server_create": (i32, [i64, i32, P(vp)]),
+        "bbp_server_submit": (i32, [vp, vp, P(dbl), i64, dbl, i32, P(C.c_uint64)]),
+        "bbp_server_poll": (i32, [vp, C.c_uint64, i32, P(dbl), P(dbl), i32, P(i32), P(i32),
+                                  P(dbl), P(dbl)]),
+        "bbp_server_stats": (i32, [vp, P(i64), P(i32), P(i64), P(i32)]),
+        "bbp_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -213,6 +223,18 @@ class PepsNet:
     def use_graph(self, on=True):
         _check(self.lib.pepsnet_use_graph(self.h, int(on)))
 
+    def memory(self):
+        """(resident bytes, workspace bytes)."""
+        r, w = C.c_int64(0), C.c_int64(0)
+        _check(self.lib.pepsnet_memory(self.h, C.byref(r), C.byref(w)))
+        return r.value, w.value
+
+    def release_workspace(self):
+        _check(self.lib.pepsnet_release_workspace(self.h))
+
+    def acquire_workspace(self):
+        _check(self.lib.pepsnet_acquire_workspace(self.h))
+
     def sweep_stats(self):
         cf, gf, nl = C.c_double(0.0), C.c_double(0.0), C.c_int64(0)
         _check(self.lib.pepsnet_sweep_stats(self.h, C.byref(cf), C.byref(gf), C.byref(nl)))
@@ -249,6 +271,60 @@ class Batch:
     def close(self):
         if getattr(self, "h", None):
             self.lib.pepsnet_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop (bbp_server_*): continuous batching of expectation
+    requests on resident states under an HBM budget."""
+
+    def __init__(self, hbm_budget_bytes, max_inflight):
+        self.lib = load_library()
+        h = C.c_void_p()
+        _check(self.lib.bbp_server_create(int(hbm_budget_bytes), int(max_inflight), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, net, sites=None, tol=1e-8, max_sweeps=50):
+        t = C.c_uint64(0)
+        if sites is None:
+            _check(self.lib.bbp_server_submit(self.h, net.h, None, 0, tol, max_sweeps, C.byref(t)))
+        else:
+            flat = _flatten_sites(sites)
+            _check(self.lib.bbp_server_submit(self.h, net.h, _dptr(flat), flat.size, tol, max_sweeps,
+                                              C.byref(t)))
+        self._keep[t.value] = net
+        return t.value
+
+    def poll(self, ticket, wait=True):
+        """None while pending, else a dict with the request's results."""
+        e, err, lat = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
+        nb, sw = C.c_int32(0), C.c_int32(0)
+        ss = np.zeros(256)
+        rc = self.lib.bbp_server_poll(self.h, C.c_uint64(ticket), int(wait), C.byref(e), _dptr(ss),
+                                      ss.size, C.byref(nb), C.byref(sw), C.byref(err), C.byref(lat))
+        if rc == BBP_PENDING:
+            return None
+        self._keep.pop(ticket, None)
+        _check(rc)
+        return {"rc": rc, "energy": e.value, "ss": ss[:nb.value].copy(), "sweeps": sw.value,
+                "err": err.value, "latency_s": lat.value}
+
+    def stats(self):
+        pb, pi, done, q = C.c_int64(0), C.c_int32(0), C.c_int64(0), C.c_int32(0)
+        _check(self.lib.bbp_server_stats(self.h, C.byref(pb), C.byref(pi), C.byref(done), C.byref(q)))
+        return {"peak_bytes": pb.value, "peak_inflight": pi.value, "completed": done.value,
+                "queued": q.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bbp_server_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -8,12 +8,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pepsnet.h"
@@ -68,15 +73,19 @@ struct pepsnet_s {
   std::unique_ptr<Compiler> comp;
   hipStream_t stream = nullptr;
   bool own_stream = false;
-  cplx* arena = nullptr;
+  cplx* arena = nullptr;      // resident: sites, site matrices, messages, constants, rho
   int64_t arena_len = 0;
+  cplx* work = nullptr;       // workspace: the lanes' chain and scratch regions
+  int64_t work_len = 0;
+  int64_t work_epoch = 0;     // bumped whenever the workspace moves
   double* scal = nullptr;
   std::vector<int64_t> region_base;
   char* desc_dev = nullptr;
   std::vector<char> desc_host;
   Compiled prep, sweep[2], expect[2];
-  // the sweep plans' ops per lane, kept for merging into batches
-  std::vector<std::vector<std::pair<WaveKey, Op>>> sweep_lanes[2];
+  // the plans' ops per lane, kept for batches and for re-resolving
+  // descriptors when the workspace moves
+  std::vector<std::vector<std::pair<WaveKey, Op>>> sweep_lanes[2], expect_lanes[2], prep_lanes;
   std::vector<std::vector<int>> carry_order[2];
   std::vector<int64_t> rho_off[2];
   std::vector<std::pair<int, int>> bonds;
@@ -94,6 +103,42 @@ struct pepsnet_s {
 };
 
 
+// ---- serving loop
+struct SrvReq {
+  uint64_t ticket = 0;
+  pepsnet_s* h = nullptr;
+  std::vector<double> sites;   // new site tensors (empty: unchanged)
+  double tol = 0.0;
+  int max_sweeps = 0;
+  int sweeps = 0;
+  double err = INFINITY;
+  int phase = 0;               // 0 queued, 1 sweeping, 2 expectation, 3 done (worker only)
+  bool ready = false;          // finished and retired (guarded by the server mutex)
+  int32_t rc = BBP_OK;
+  bool own_work = false;       // workspace acquired by the server for this request
+  int64_t ws_bytes = 0;
+  std::vector<double> ss;
+  double energy = 0.0;
+  std::chrono::steady_clock::time_point t_submit, t_done;
+  hipEvent_t ev = nullptr;
+};
+
+struct bbp_server_s {
+  int64_t budget = 0;
+  int max_inflight = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<SrvReq*> queue;
+  std::vector<SrvReq*> inflight;
+  std::map<uint64_t, SrvReq*> reqs;   // submitted and not yet collected
+  uint64_t next_ticket = 1;
+  int64_t in_use = 0, peak_in_use = 0;
+  int peak_inflight = 0;
+  int64_t completed = 0;
+  bool stop = false;
+  std::thread worker;
+};
+
 // A batch merges the sweep plans of several handles into one launch
 // sequence: ops of every handle at the same wave key share a launch.
 // Variant v of the merged plan runs handle i on message set
@@ -101,6 +146,7 @@ struct pepsnet_s {
 struct pepsnet_batch_s {
   std::vector<pepsnet_s*> hs;
   std::vector<int> base_parity;
+  std::vector<int64_t> work_epoch;
   Compiled sweep[2];
   std::vector<char> desc_host[2];
   char* desc_dev[2] = {nullptr, nullptr};
@@ -115,6 +161,7 @@ namespace {
 
 cplx* resolve(pepsnet_s* h, const Ref& r) {
   if (!r.valid()) return nullptr;
+  if (r.region >= RG_LANE0) return h->work + h->region_base[r.region] + r.off;
   return h->arena + h->region_base[r.region] + r.off;
 }
 
@@ -513,6 +560,226 @@ int32_t reset_messages(pepsnet_s* h) {
   return BBP_OK;
 }
 
+
+// ---- asynchronous sweep / expectation steps (the serving loop's units of
+// work): enqueue on the handle's stream, record `ev`, finish once it fired.
+int32_t enqueue_sweep(pepsnet_s* h, hipEvent_t ev) {
+  const int nm = int(h->P.msg_keys.size());
+  h->pinned[0] = double(h->sweeps_total);
+  PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
+                        hipMemcpyHostToDevice, h->stream));
+  int32_t rc = run_compiled(h, &h->sweep[h->parity], true);
+  if (rc) return rc;
+  PN_HIP(hipMemcpyAsync(h->pinned + 1, h->scal + h->comp->err_slot(0), nm * sizeof(double),
+                        hipMemcpyDeviceToHost, h->stream));
+  PN_HIP(hipEventRecord(ev, h->stream));
+  return BBP_OK;
+}
+
+int32_t finish_sweep(pepsnet_s* h, double* err) {
+  const int nm = int(h->P.msg_keys.size());
+  double e = 0.0;
+  for (int m = 0; m < nm; ++m) {
+    if (!std::isfinite(h->pinned[1 + m])) return fail(BBP_ENUMERIC, "non-finite message after a sweep");
+    e = std::max(e, h->pinned[1 + m]);
+  }
+  h->parity ^= 1;
+  h->sweeps_total += 1;
+  *err = e;
+  return BBP_OK;
+}
+
+int32_t enqueue_expect(pepsnet_s* h, hipEvent_t ev) {
+  const int nm = int(h->P.msg_keys.size()), nb = int(h->bonds.size());
+  int32_t rc = run_compiled(h, &h->expect[h->parity], false);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_rho_ss, dim3((nb + 63) / 64), dim3(64), 0, h->stream,
+                     h->rho_descs[h->parity], nb);
+  PN_HIP(hipGetLastError());
+  PN_HIP(hipMemcpyAsync(h->pinned + 1 + nm, h->ss_dev, nb * sizeof(double), hipMemcpyDeviceToHost,
+                        h->stream));
+  PN_HIP(hipEventRecord(ev, h->stream));
+  return BBP_OK;
+}
+
+int32_t finish_expect(pepsnet_s* h, std::vector<double>* ss, double* energy) {
+  const int nm = int(h->P.msg_keys.size()), nb = int(h->bonds.size());
+  ss->assign(h->pinned + 1 + nm, h->pinned + 1 + nm + nb);
+  double e = 0.0;
+  for (double x : *ss) {
+    if (!std::isfinite(x)) return fail(BBP_ENUMERIC, "non-finite expectation value");
+    e += x;
+  }
+  *energy = h->P.kind == 1 ? e / 3.0 : e / std::max(nb, 1);
+  return BBP_OK;
+}
+
+
+// (Re)compile every launch list against the current arena and workspace
+// addresses and upload the descriptors; drops captured graphs.
+int32_t build_launches(pepsnet_s* h) {
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep}) {
+    if (c->exec) hipGraphExecDestroy(c->exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    *c = Compiled();
+  }
+  h->desc_host.clear();
+  compile_ops({{h, &h->prep_lanes}}, &h->desc_host, &h->prep);
+  for (int par = 0; par < 2; ++par) {
+    compile_ops({{h, &h->sweep_lanes[par]}}, &h->desc_host, &h->sweep[par]);
+    compile_ops({{h, &h->expect_lanes[par]}}, &h->desc_host, &h->expect[par]);
+  }
+  const int nb = int(h->bonds.size());
+  size_t rho_off[2];
+  for (int par = 0; par < 2; ++par) {
+    std::vector<RhoDesc> rd(nb);
+    for (int b = 0; b < nb; ++b) {
+      rd[b].R = h->arena + h->region_base[RG_RHO] + h->rho_off[par][b];
+      rd[b].rho = h->rho_mat + 16 * b;
+      rd[b].ss = h->ss_dev + b;
+      rd[b].first_is_i = h->carry_order[par][b][0] == h->bonds[b].first ? 1 : 0;
+    }
+    rho_off[par] = push_descs(&h->desc_host, rd);
+  }
+  if (h->desc_dev) {
+    PN_HIP(hipStreamSynchronize(h->stream));
+    hipFree(h->desc_dev);
+    h->desc_dev = nullptr;
+  }
+  if (hipMalloc(&h->desc_dev, std::max<size_t>(h->desc_host.size(), 256)) != hipSuccess)
+    return fail(BBP_ENOMEM, "descriptor allocation failed");
+  PN_HIP(hipMemcpyAsync(h->desc_dev, h->desc_host.data(), h->desc_host.size(),
+                        hipMemcpyHostToDevice, h->stream));
+  for (int par = 0; par < 2; ++par)
+    h->rho_descs[par] = reinterpret_cast<RhoDesc*>(h->desc_dev + rho_off[par]);
+  PN_HIP(hipStreamSynchronize(h->stream));
+  return BBP_OK;
+}
+
+int32_t need_work(pepsnet_s* h) {
+  if (!h->work) return fail(BBP_EINVAL, "the handle's workspace is released");
+  return BBP_OK;
+}
+
+
+// Start an admitted request: workspace, new sites (messages kept: a warm
+// start), then its first sweep (or the expectation when max_sweeps == 0).
+void srv_start(SrvReq* r) {
+  pepsnet_s* h = r->h;
+  int32_t rc = BBP_OK;
+  if (!h->work) {
+    rc = pepsnet_acquire_workspace(h);
+    if (rc == BBP_OK) r->own_work = true;
+  }
+  if (rc == BBP_OK && !r->sites.empty()) rc = upload_sites(h, r->sites.data(), int64_t(r->sites.size()));
+  if (rc == BBP_OK && hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess)
+    rc = fail(BBP_EDEVICE, "event creation failed");
+  if (rc == BBP_OK) {
+    if (r->max_sweeps > 0) {
+      r->phase = 1;
+      rc = enqueue_sweep(h, r->ev);
+    } else {
+      r->phase = 2;
+      rc = enqueue_expect(h, r->ev);
+    }
+  }
+  if (rc != BBP_OK) {
+    r->rc = rc;
+    r->phase = 3;
+  }
+}
+
+// Advance a request whose last step finished; false if it is still running.
+bool srv_progress(SrvReq* r) {
+  if (r->phase == 3) return false;
+  if (hipEventQuery(r->ev) == hipErrorNotReady) return false;
+  pepsnet_s* h = r->h;
+  int32_t rc = BBP_OK;
+  if (r->phase == 1) {
+    rc = finish_sweep(h, &r->err);
+    r->sweeps += 1;
+    if (rc == BBP_OK) {
+      if (r->err <= r->tol || r->sweeps >= r->max_sweeps) {
+        r->phase = 2;
+        rc = enqueue_expect(h, r->ev);
+      } else {
+        rc = enqueue_sweep(h, r->ev);
+      }
+    }
+  } else {
+    rc = finish_expect(h, &r->ss, &r->energy);
+    r->phase = 3;
+    if (rc == BBP_OK && r->max_sweeps > 0 && !(r->err <= r->tol)) rc = BBP_NOT_CONVERGED;
+  }
+  if (rc != BBP_OK) {
+    r->rc = rc;
+    if (rc < 0) r->phase = 3;
+  }
+  return true;
+}
+
+void srv_loop(bbp_server_s* S) {
+  for (;;) {
+    std::vector<SrvReq*> admitted;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (S->inflight.empty())
+        S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty(); });
+      if (S->stop && S->queue.empty() && S->inflight.empty()) return;
+      // admit in arrival order as slots and memory free up; a request whose
+      // state is busy or whose workspace does not fit lets later ones pass
+      for (auto it = S->queue.begin();
+           it != S->queue.end() && int(S->inflight.size()) < S->max_inflight;) {
+        SrvReq* r = *it;
+        bool busy = false;
+        for (SrvReq* o : S->inflight) busy = busy || o->h == r->h;
+        const int64_t need = r->h->work ? 0 : r->h->work_len * int64_t(sizeof(cplx));
+        if (!busy && S->in_use + need <= S->budget) {
+          r->ws_bytes = need;
+          S->in_use += need;
+          S->inflight.push_back(r);
+          admitted.push_back(r);
+          it = S->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      S->peak_in_use = std::max(S->peak_in_use, S->in_use);
+      S->peak_inflight = std::max(S->peak_inflight, int(S->inflight.size()));
+    }
+    for (SrvReq* r : admitted) srv_start(r);
+    bool progressed = !admitted.empty();
+    std::vector<SrvReq*> snapshot;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      snapshot = S->inflight;
+    }
+    for (SrvReq* r : snapshot) progressed = srv_progress(r) || progressed;
+    std::vector<SrvReq*> done;
+    for (SrvReq* r : snapshot)
+      if (r->phase == 3) done.push_back(r);
+    for (SrvReq* r : done) {
+      if (r->h->stream) hipStreamSynchronize(r->h->stream);
+      if (r->own_work) pepsnet_release_workspace(r->h);
+      if (r->ev) hipEventDestroy(r->ev);
+      r->ev = nullptr;
+      r->sites.clear();
+      r->t_done = std::chrono::steady_clock::now();
+    }
+    if (!done.empty()) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (SrvReq* r : done) {
+        S->in_use -= r->ws_bytes;
+        S->inflight.erase(std::find(S->inflight.begin(), S->inflight.end(), r));
+        S->completed += 1;
+        r->ready = true;
+      }
+      S->cv_done.notify_all();
+    }
+    if (!progressed && done.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -558,12 +825,14 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   sizes[RG_RHO] = std::max<int64_t>(C.rho_size, 8);
   for (int L = 0; L < nl; ++L) sizes[RG_LANE0 + L] = C.lane_size[L];
   h->region_base.assign(sizes.size(), 0);
-  int64_t tot = 0;
+  int64_t tot = 0, wtot = 0;
   for (size_t r = 0; r < sizes.size(); ++r) {
-    h->region_base[r] = tot;
-    tot += (sizes[r] + 31) / 32 * 32;
+    int64_t& t = int(r) >= RG_LANE0 ? wtot : tot;
+    h->region_base[r] = t;
+    t += (sizes[r] + 31) / 32 * 32;
   }
   h->arena_len = tot;
+  h->work_len = std::max<int64_t>(wtot, 32);
   if (desc->stream) {
     h->stream = (hipStream_t)desc->stream;
   } else {
@@ -572,6 +841,10 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   }
   if (hipMalloc(&h->arena, size_t(tot) * sizeof(cplx)) != hipSuccess)
     return fail(BBP_ENOMEM, "device allocation of " + std::to_string(tot * 16) + " bytes failed");
+  if (hipMalloc(&h->work, size_t(h->work_len) * sizeof(cplx)) != hipSuccess)
+    return fail(BBP_ENOMEM, "workspace allocation of " + std::to_string(h->work_len * 16) +
+                                " bytes failed");
+  PN_HIP(hipMemsetAsync(h->work, 0, size_t(h->work_len) * sizeof(cplx), h->stream));
   if (hipMalloc(&h->scal, size_t(C.n_scalars) * sizeof(double)) != hipSuccess)
     return fail(BBP_ENOMEM, "scalar allocation failed");
   PN_HIP(hipMemsetAsync(h->arena, 0, size_t(tot) * sizeof(cplx), h->stream));
@@ -579,48 +852,29 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   cplx one = {1.0, 0.0};
   PN_HIP(hipMemcpyAsync(h->arena + h->region_base[RG_CONST], &one, sizeof one,
                         hipMemcpyHostToDevice, h->stream));
-  // compile and upload descriptors
-  {
-    std::vector<std::vector<std::pair<WaveKey, Op>>> prep(1);
-    for (size_t k = 0; k < C.prep_ops.size(); ++k) {
-      WaveKey wk;
-      wk.k = {0};
-      prep[0].push_back({wk, C.prep_ops[k]});
-    }
-    // prep ops are independent: one wave
-    compile_ops({{h.get(), &prep}}, &h->desc_host, &h->prep);
+  // keep the plans' op lists, then compile and upload descriptors
+  h->prep_lanes.resize(1);
+  for (size_t k = 0; k < C.prep_ops.size(); ++k) {
+    WaveKey wk;
+    wk.k = {0};   // prep ops are independent: one wave
+    h->prep_lanes[0].push_back({wk, C.prep_ops[k]});
   }
   for (int par = 0; par < 2; ++par) {
     for (auto& L : sp[par].lanes) h->sweep_lanes[par].push_back(L.ops);
-    compile_ops({{h.get(), &h->sweep_lanes[par]}}, &h->desc_host, &h->sweep[par]);
-    LaneList lanes;
-    for (auto& L : ep[par].lanes) lanes.push_back(L.ops);
-    compile_ops({{h.get(), &lanes}}, &h->desc_host, &h->expect[par]);
+    for (auto& L : ep[par].lanes) h->expect_lanes[par].push_back(L.ops);
   }
   int nb = int(h->bonds.size());
   if (hipMalloc(&h->rho_mat, size_t(std::max(nb, 1)) * 16 * sizeof(cplx)) != hipSuccess ||
       hipMalloc(&h->ss_dev, size_t(std::max(nb, 1)) * sizeof(double)) != hipSuccess)
     return fail(BBP_ENOMEM, "expectation buffers");
-  for (int par = 0; par < 2; ++par) {
-    std::vector<RhoDesc> rd(nb);
-    for (int b = 0; b < nb; ++b) {
-      const std::vector<int>& ord = h->carry_order[par][b];
-      if (ord.size() != 2) return fail(BBP_EGEOM, "expectation carries two open sites");
-      rd[b].R = h->arena + h->region_base[RG_RHO] + h->rho_off[par][b];
-      rd[b].rho = h->rho_mat + 16 * b;
-      rd[b].ss = h->ss_dev + b;
-      rd[b].first_is_i = ord[0] == h->bonds[b].first ? 1 : 0;
-    }
-    size_t off = push_descs(&h->desc_host, rd);
-    h->rho_descs[par] = reinterpret_cast<RhoDesc*>(off);  // fixed up below
-  }
-  if (hipMalloc(&h->desc_dev, std::max<size_t>(h->desc_host.size(), 256)) != hipSuccess)
-    return fail(BBP_ENOMEM, "descriptor allocation failed");
-  PN_HIP(hipMemcpyAsync(h->desc_dev, h->desc_host.data(), h->desc_host.size(),
-                        hipMemcpyHostToDevice, h->stream));
   for (int par = 0; par < 2; ++par)
-    h->rho_descs[par] = reinterpret_cast<RhoDesc*>(h->desc_dev + size_t(h->rho_descs[par]));
-  if (hipHostMalloc(&h->pinned, size_t(C.msg.off.size() + 8) * sizeof(double), 0) != hipSuccess)
+    for (int b = 0; b < nb; ++b)
+      if (h->carry_order[par][b].size() != 2)
+        return fail(BBP_EGEOM, "expectation carries two open sites");
+  rc = build_launches(h.get());
+  if (rc) return rc;
+  if (hipHostMalloc(&h->pinned, size_t(C.msg.off.size() + h->bonds.size() + 8) * sizeof(double),
+                    0) != hipSuccess)
     return fail(BBP_ENOMEM, "pinned host buffer");
   for (const void* f : {(const void*)k_jacobi<false>, (const void*)k_jacobi<true>})
     PN_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -652,6 +906,7 @@ int32_t pepsnet_set_sites(pepsnet_t h, const double* sites, int64_t len, int32_t
 int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
                       double* max_err) {
   if (!h || max_sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
+  if (int32_t rc = need_work(h)) return rc;
   const int nm = int(h->P.msg_keys.size());
   std::vector<double> errs(nm);
   double err = INFINITY;
@@ -693,6 +948,7 @@ int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* swee
 int32_t blockbp_expect(pepsnet_t h, double* rho_out, double* ss_out, double* energy,
                        int32_t* n_bonds_out) {
   if (!h) return fail(BBP_EINVAL, "null handle");
+  if (int32_t rc = need_work(h)) return rc;
   int nb = int(h->bonds.size());
   int32_t rc = run_compiled(h, &h->expect[h->parity], false);
   if (rc) return rc;
@@ -812,6 +1068,7 @@ int32_t pepsnet_sweep_stats(pepsnet_t h, double* cflops, double* gflops, int64_t
 
 int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_t* launches,
                                double* flops, double* bytes) {
+  if (h && !h->work) return fail(BBP_EINVAL, "the handle's workspace is released");
   if (!h || n_sweeps <= 0) return fail(BBP_EINVAL, "bad arguments");
   const int nk = PEPSNET_PROFILE_SLOTS;
   std::vector<double> tms(nk, 0.0), tfl(nk, 0.0), tby(nk, 0.0);
@@ -853,6 +1110,46 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
   return BBP_OK;
 }
 
+int32_t pepsnet_memory(pepsnet_t h, int64_t* resident_bytes, int64_t* workspace_bytes) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (resident_bytes)
+    *resident_bytes = h->arena_len * int64_t(sizeof(cplx)) +
+                      int64_t(h->comp->n_scalars) * int64_t(sizeof(double)) +
+                      int64_t(h->desc_host.size()) +
+                      int64_t(h->bonds.size()) * int64_t(17 * sizeof(cplx));
+  if (workspace_bytes) *workspace_bytes = h->work_len * int64_t(sizeof(cplx));
+  return BBP_OK;
+}
+
+int32_t pepsnet_release_workspace(pepsnet_t h) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (!h->work) return BBP_OK;
+  PN_HIP(hipStreamSynchronize(h->stream));
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1]}) {
+    if (c->exec) hipGraphExecDestroy(c->exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->exec = nullptr;
+    c->graph = nullptr;
+  }
+  PN_HIP(hipFree(h->work));
+  h->work = nullptr;
+  h->work_epoch += 1;
+  return BBP_OK;
+}
+
+int32_t pepsnet_acquire_workspace(pepsnet_t h) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (h->work) return BBP_OK;
+  if (hipMalloc(&h->work, size_t(h->work_len) * sizeof(cplx)) != hipSuccess) {
+    h->work = nullptr;
+    return fail(BBP_ENOMEM, "workspace allocation of " + std::to_string(h->work_len * 16) +
+                                " bytes failed");
+  }
+  PN_HIP(hipMemsetAsync(h->work, 0, size_t(h->work_len) * sizeof(cplx), h->stream));
+  h->work_epoch += 1;
+  return build_launches(h);
+}
+
 int32_t pepsnet_batch_create(const pepsnet_t* hs, int32_t n, void* stream, pepsnet_batch_t* out) {
   if (!hs || n < 1 || !out) return fail(BBP_EINVAL, "bad arguments");
   std::unique_ptr<pepsnet_batch_s> b(new pepsnet_batch_s());
@@ -860,8 +1157,10 @@ int32_t pepsnet_batch_create(const pepsnet_t* hs, int32_t n, void* stream, pepsn
     if (!hs[i]) return fail(BBP_EINVAL, "null handle in batch");
     for (int k = 0; k < i; ++k)
       if (hs[k] == hs[i]) return fail(BBP_EINVAL, "handle listed twice in batch");
+    if (!hs[i]->work) return fail(BBP_EINVAL, "a handle of the batch has no workspace");
     b->hs.push_back(hs[i]);
     b->base_parity.push_back(hs[i]->parity);
+    b->work_epoch.push_back(hs[i]->work_epoch);
   }
   if (stream) {
     b->stream = static_cast<hipStream_t>(stream);
@@ -896,9 +1195,12 @@ int32_t blockbp_sweep_batch(pepsnet_batch_t b, int32_t sweeps, double* max_err, 
   if (!b || sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
   const int n = int(b->hs.size());
   const int v = b->hs[0]->parity ^ b->base_parity[0];
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if ((b->hs[i]->parity ^ b->base_parity[i]) != v)
       return fail(BBP_EINVAL, "a handle of the batch was swept on its own; recreate the batch");
+    if (b->hs[i]->work_epoch != b->work_epoch[i])
+      return fail(BBP_EINVAL, "a handle's workspace moved since the batch was made");
+  }
   // work already queued on the handles' own streams comes first
   for (pepsnet_s* h : b->hs) PN_HIP(hipStreamSynchronize(h->stream));
   std::vector<double> errs(n, 0.0);
@@ -965,6 +1267,98 @@ void pepsnet_batch_destroy(pepsnet_batch_t b) {
   delete b;
 }
 
+int32_t bbp_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, bbp_server_t* out) {
+  if (!out || hbm_budget_bytes < 0 || max_inflight < 1) return fail(BBP_EINVAL, "bad arguments");
+  bbp_server_s* S = new bbp_server_s();
+  S->budget = hbm_budget_bytes;
+  S->max_inflight = max_inflight;
+  S->worker = std::thread(srv_loop, S);
+  *out = S;
+  return BBP_OK;
+}
+
+int32_t bbp_server_submit(bbp_server_t S, pepsnet_t state, const double* new_sites,
+                          int64_t sites_len, double tol, int32_t max_sweeps, uint64_t* ticket) {
+  if (!S || !state || !ticket || max_sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
+  if (new_sites && sites_len != state->site_len)
+    return fail(BBP_EINVAL, "site tensor buffer has the wrong length");
+  if (!state->work && state->work_len * int64_t(sizeof(cplx)) > S->budget)
+    return fail(BBP_ENOMEM, "the state's workspace exceeds the server's HBM budget");
+  SrvReq* r = new SrvReq();
+  r->h = state;
+  if (new_sites) r->sites.assign(new_sites, new_sites + sites_len);
+  r->tol = tol;
+  r->max_sweeps = max_sweeps;
+  r->t_submit = std::chrono::steady_clock::now();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) {
+      delete r;
+      return fail(BBP_EINVAL, "server is shutting down");
+    }
+    r->ticket = S->next_ticket++;
+    S->reqs[r->ticket] = r;
+    S->queue.push_back(r);
+  }
+  S->cv_work.notify_one();
+  *ticket = r->ticket;
+  return BBP_OK;
+}
+
+int32_t bbp_server_poll(bbp_server_t S, uint64_t ticket, int32_t wait, double* energy_per_site,
+                        double* bond_ss, int32_t cap, int32_t* n_bonds, int32_t* sweeps_done,
+                        double* max_err, double* latency_s) {
+  if (!S) return fail(BBP_EINVAL, "null server");
+  SrvReq* r = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return fail(BBP_EINVAL, "unknown or already collected ticket");
+    r = it->second;
+    auto finished = [&] { return r->ready; };
+    if (!finished()) {
+      if (!wait) return BBP_PENDING;
+      S->cv_done.wait(lk, finished);
+    }
+    S->reqs.erase(it);
+  }
+  std::unique_ptr<SrvReq> own(r);
+  const int nb = int(r->ss.size());
+  if (n_bonds) *n_bonds = nb;
+  if (bond_ss)
+    for (int b = 0; b < std::min(nb, int(cap)); ++b) bond_ss[b] = r->ss[b];
+  if (energy_per_site) *energy_per_site = r->energy;
+  if (sweeps_done) *sweeps_done = r->sweeps;
+  if (max_err) *max_err = r->err;
+  if (latency_s)
+    *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  if (r->rc < 0) return fail(r->rc, "request failed");
+  return r->rc;
+}
+
+int32_t bbp_server_stats(bbp_server_t S, int64_t* peak_bytes, int32_t* peak_inflight,
+                         int64_t* completed, int32_t* queued) {
+  if (!S) return fail(BBP_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (peak_bytes) *peak_bytes = S->peak_in_use;
+  if (peak_inflight) *peak_inflight = S->peak_inflight;
+  if (completed) *completed = S->completed;
+  if (queued) *queued = int32_t(S->queue.size());
+  return BBP_OK;
+}
+
+void bbp_server_destroy(bbp_server_t S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  for (auto& kv : S->reqs) delete kv.second;
+  delete S;
+}
+
 void pepsnet_destroy(pepsnet_t h) {
   if (!h) return;
   if (h->stream) hipStreamSynchronize(h->stream);
@@ -973,6 +1367,7 @@ void pepsnet_destroy(pepsnet_t h) {
     if (c->graph) hipGraphDestroy(c->graph);
   }
   if (h->arena) hipFree(h->arena);
+  if (h->work) hipFree(h->work);
   if (h->scal) hipFree(h->scal);
   if (h->desc_dev) hipFree(h->desc_dev);
   if (h->rho_mat) hipFree(h->rho_mat);
