@@ -181,6 +181,7 @@ int op_variant(const Op& op) {
     return m * (n + (op.c.valid() ? k : 0)) <= QR_LDS_MAX ? 0 : 1;
   }
   if (op.type == OPK_JACOBI) {
+    if (op.i[5]) return 2;   // k_svd_top
     const int rows = int(op.i[0]), cols = int(op.i[1]);
     return jacobi_lds_slices(rows, cols) < (rows + 15) / 16 ? 1 : 0;
   }
@@ -316,13 +317,19 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             jd.sigma = reinterpret_cast<double*>(resolve(h, op->d));
             jd.rows = int(op->i[0]); jd.cols = int(op->i[1]); jd.lda = int(op->i[2]);
             jd.conjT = int(op->i[3]); jd.keep = int(op->i[4]);
-            const int nl = jacobi_lds_slices(jd.rows, jd.cols);
-            lds_elems = std::max<int64_t>(lds_elems, int64_t(nl) * 16 * jd.cols);
-            // one sweep of cols(cols-1)/2 rotations, each three length-rows dot
-            // products (a, b, g: 2 + 2 + 4 real flops per row) and the update
-            // of two columns (2 x 8 per row): the count of one sweep, the
-            // minimum any converged run performs
-            rec.flops += 0.5 * jd.cols * (jd.cols - 1.0) * 24.0 * jd.rows;
+            if (rec.variant == 2) {
+              // complex Householder bidiagonalisation, 4 x (4 m n^2 - 4 n^3 / 3)
+              const double m = jd.rows, n = jd.cols;
+              rec.flops += 16.0 * (m * n * n - n * n * n / 3.0);
+            } else {
+              const int nl = jacobi_lds_slices(jd.rows, jd.cols);
+              lds_elems = std::max<int64_t>(lds_elems, int64_t(nl) * 16 * jd.cols);
+              // one sweep of cols(cols-1)/2 rotations, each three length-rows dot
+              // products (a, b, g: 2 + 2 + 4 real flops per row) and the update
+              // of two columns (2 x 8 per row): the count of one sweep, the
+              // minimum any converged run performs
+              rec.flops += 0.5 * jd.cols * (jd.cols - 1.0) * 24.0 * jd.rows;
+            }
             rec.bytes += 16.0 * (double(jd.rows) * jd.cols + double(jd.rows) * jd.keep);
             v.push_back(jd);
           }
@@ -454,7 +461,9 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r) 
         hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, stream, (const QrDesc*)d);
       break;
     case OPK_JACOBI:
-      if (r.variant)
+      if (r.variant == 2)
+        hipLaunchKernelGGL(k_svd_top, r.grid, dim3(SVT_THREADS), 0, stream, (const JacobiDesc*)d);
+      else if (r.variant)
         hipLaunchKernelGGL(k_jacobi<true>, r.grid, dim3(JAC_THREADS), r.lds, stream,
                            (const JacobiDesc*)d);
       else
@@ -1092,6 +1101,7 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
       PN_HIP(hipEventElapsedTime(&x, ev[2 * i], ev[2 * i + 1]));
       const LaunchRec& r = c.launches[i];
       int slot = r.type * 3 + (r.type == OPK_GEMM ? r.prec : 0);
+      if (r.type == OPK_JACOBI && r.variant == 2) slot += 2;
       tms[slot] += x;
       tl[slot] += 1;
       tfl[slot] += r.flops;

@@ -914,6 +914,440 @@ __global__ __launch_bounds__(JAC_THREADS) void k_jacobi(const JacobiDesc* __rest
 template __global__ void k_jacobi<false>(const JacobiDesc*);
 template __global__ void k_jacobi<true>(const JacobiDesc*);
 
+// ------------------------------------------------------------ top-k SVD
+// Exact leading k singular values and left singular vectors of A (rows x
+// cols, cols <= rows <= 144), for truncated splits that keep k << cols:
+//   1. Householder bidiagonalisation A = Q_L B Q_R^H (left reflectors kept in
+//      the working copy, right ones applied and dropped), then diagonal
+//      phases making B real: B = D_L B' D_R^H with d_j, e_j >= 0;
+//   2. the singular values of B' are the positive eigenvalues of the
+//      Golub-Kahan tridiagonal T (zero diagonal, off-diagonal d_0, e_0,
+//      d_1, ...): each of the k largest is found by multisection on Sturm
+//      counts, 64 shifts per step (one per lane of a wave);
+//   3. inverse iteration on T - sigma I (Gaussian elimination with partial
+//      pivoting fused with the forward solve, tiny pivots raised to
+//      eps ||T||), eigenvectors of close values re-orthogonalised; the odd
+//      entries of the eigenvector are the left singular vector u of B';
+//   4. U = Q_L D_L u through the stored reflectors.
+// Singular values at or below 1e-15 ||A||_F give zero columns, as k_jacobi.
+// The working copy is column-major with rows padded to 16-row slices (zero
+// rows), so the passes over a column or a row issue all their loads at once.
+constexpr int SVT_THREADS = 1024;
+constexpr int SVT_MAXN = 144;          // rows and cols limit, as k_jacobi
+constexpr int SVT_ITERS = 3;           // inverse iteration steps
+constexpr int SVT_BATCH = 12;          // values per inverse-iteration batch (LDS)
+
+// work buffer: the padded matrix, then per value the eigenvector of T (2n
+// doubles) and the complex output vector (rows)
+__host__ __device__ inline int64_t svt_stride(int64_t rows, int64_t cols) {
+  return 2 * cols + 2 * rows;
+}
+
+__device__ __forceinline__ double svt_block_sum(double v, double* sh) {
+  v = wave_sum64(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < SVT_THREADS / 64; ++w) s += sh[w];
+  return s;
+}
+
+// 1/q from the hardware estimate and two Newton steps (full precision for
+// |q| >= pivmin; cheaper than the IEEE division in the recurrences below)
+__device__ __forceinline__ double svt_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
+// number of eigenvalues below x of the symmetric tridiagonal with zero
+// diagonal and squared off-diagonal b2[0 .. N-2]
+__device__ int svt_count(const double* b2, int N, double x, double pivmin) {
+  double q = -x;
+  int cnt = q < 0.0;
+  for (int i = 0; i < N - 1; ++i) {
+    if (fabs(q) < pivmin) q = -pivmin;
+    q = -x - b2[i] * svt_rcp(q);
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+#define SVT_QP 2
+// Up to SVT_QP trailing columns of the left reflector, a -= tau v (v^H a),
+// with all loads in flight together; lane gl of the 16-lane group holds rows
+// gl + 16 t.  Columns c0 + 64 q (q < SVT_QP, c < n).  Kept out of line with the row
+// pass so that the two register sets are not live together.
+__device__ __noinline__ void svt_left_cols(cplx* W, int mp, int c0, int n, const cplx* vL, double tau,
+                                           int nt, int gl) {
+  cplx a[SVT_QP][9];
+#pragma unroll
+  for (int q = 0; q < SVT_QP; ++q) {
+    const int c = c0 + 64 * q;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      if (c < n && t < nt) a[q][t] = W[(int64_t)c * mp + gl + 16 * t];
+  }
+#pragma unroll
+  for (int q = 0; q < SVT_QP; ++q) {
+    const int c = c0 + 64 * q;
+    if (c >= n) break;
+    double wr = 0.0, wi = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      if (t < nt) {
+        const cplx v = vL[gl + 16 * t];
+        wr += v.re * a[q][t].re + v.im * a[q][t].im;
+        wi += v.re * a[q][t].im - v.im * a[q][t].re;
+      }
+    wr = group16_sum(wr);
+    wi = group16_sum(wi);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      if (t < nt) {
+        const cplx v = vL[gl + 16 * t];
+        a[q][t].re -= tau * (v.re * wr - v.im * wi);
+        a[q][t].im -= tau * (v.re * wi + v.im * wr);
+        W[(int64_t)c * mp + gl + 16 * t] = a[q][t];
+      }
+  }
+}
+
+// Up to SVT_QP rows of the right reflector, a -= tau2 (a . v2) conj(v2), all
+// loads in flight together; rows r0 + 64 q (< m), columns j1 + c for
+// c = gl + 16 t < nr.
+__device__ __noinline__ void svt_right_rows(cplx* W, int mp, int j1, int r0, int m, const cplx* vR,
+                                            double tau2, int nr, int gl) {
+  cplx a[SVT_QP][9];
+#pragma unroll
+  for (int q = 0; q < SVT_QP; ++q) {
+    const int r = r0 + 64 * q;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int c = gl + 16 * t;
+      if (r < m && c < nr) a[q][t] = W[(int64_t)(j1 + c) * mp + r];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < SVT_QP; ++q) {
+    const int r = r0 + 64 * q;
+    if (r >= m) break;
+    double wr = 0.0, wi = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int c = gl + 16 * t;
+      if (c < nr) {
+        const cplx v = vR[c];
+        wr += a[q][t].re * v.re - a[q][t].im * v.im;
+        wi += a[q][t].re * v.im + a[q][t].im * v.re;
+      }
+    }
+    wr = group16_sum(wr);
+    wi = group16_sum(wi);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int c = gl + 16 * t;
+      if (c < nr) {
+        const cplx v = vR[c];
+        a[q][t].re -= tau2 * (wr * v.re + wi * v.im);   // w conj(v)
+        a[q][t].im -= tau2 * (wi * v.re - wr * v.im);
+        W[(int64_t)(j1 + c) * mp + r] = a[q][t];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __restrict__ descs) {
+  const JacobiDesc dsc = descs[blockIdx.x];
+  const int m = dsc.rows, n = dsc.cols, k = dsc.keep, N = 2 * n;
+  const int nt = (m + 15) / 16, mp = nt * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, grp = tid >> 4, gl = tid & 15;
+  constexpr int NW = SVT_THREADS / 64, NG = SVT_THREADS / 16;
+  __shared__ double red[NW];
+  __shared__ double tauL[SVT_MAXN];
+  __shared__ cplx dcx[SVT_MAXN], ecx[SVT_MAXN], pL[SVT_MAXN];
+  __shared__ double off[2 * SVT_MAXN], b2[2 * SVT_MAXN], sig[SVT_MAXN];
+  __shared__ cplx vL[SVT_MAXN], vR[SVT_MAXN];
+  __shared__ double fro2_s;
+  // inverse iteration: dd, du, du2, x per value; the odd stride keeps the
+  // values' arrays in different LDS banks
+  __shared__ double iib[SVT_BATCH * (4 * 2 * SVT_MAXN + 1)];
+  if (n > SVT_MAXN || m > SVT_MAXN || n > m || k > n) return;   // excluded by the plan compiler
+  cplx* W = dsc.work;                                  // mp x n column-major
+  double* pv = reinterpret_cast<double*>(dsc.work + (int64_t)mp * n);
+  double f = 0.0;
+  for (int e = tid; e < mp * n; e += SVT_THREADS) {
+    const int c = e / mp, i = e % mp;
+    cplx v = {0.0, 0.0};
+    if (i < m) {
+      if (dsc.conjT) { v = dsc.A[(int64_t)c * dsc.lda + i]; v.im = -v.im; }
+      else v = dsc.A[(int64_t)i * dsc.lda + c];
+    }
+    W[e] = v;
+    f += v.re * v.re + v.im * v.im;
+  }
+  f = svt_block_sum(f, red);
+  if (tid == 0) fro2_s = f;
+  // ---- 1. bidiagonalisation
+  for (int j = 0; j < n; ++j) {
+    // left reflector from column j, rows j..m-1 (copied to vL, zero elsewhere)
+    const cplx* xj = W + (int64_t)j * mp;
+    double part = 0.0;
+    for (int i = tid; i < SVT_MAXN; i += SVT_THREADS) {
+      const cplx x = (i >= j && i < m) ? xj[i] : cplx{0.0, 0.0};
+      vL[i] = x;
+      part += x.re * x.re + x.im * x.im;
+    }
+    const double nx2 = svt_block_sum(part, red);   // (barrier: vL complete)
+    const cplx x0 = vL[j];
+    const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
+    double tau = 0.0;
+    cplx alpha = {0.0, 0.0}, v0 = x0;
+    if (nx > 0.0) {
+      const cplx ph = ax0 > 0.0 ? cplx{x0.re / ax0, x0.im / ax0} : cplx{1.0, 0.0};
+      alpha = cplx{-ph.re * nx, -ph.im * nx};
+      v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
+      const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
+      tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      vL[j] = v0;
+      tauL[j] = tau;
+      dcx[j] = alpha;
+    }
+    __syncthreads();
+    // trailing columns: a -= tau v (v^H a), one 16-lane group per column
+    if (tau != 0.0)
+      for (int c = j + 1 + grp; c < n; c += SVT_QP * NG) svt_left_cols(W, mp, c, n, vL, tau, nt, gl);
+    // the reflector (head v0) is stored in column j, rows j..
+    if (tid == 0 && tau != 0.0) W[(int64_t)j * mp + j] = v0;
+    __syncthreads();
+    if (j == n - 1) break;
+    // right reflector from row j, columns j+1..n-1: x = conj(W[j, j+1:])
+    const int nr = n - j - 1;
+    double p2 = 0.0;
+    for (int c = tid; c < SVT_MAXN; c += SVT_THREADS) {
+      cplx y = {0.0, 0.0};
+      if (c < nr) {
+        const cplx a = W[(int64_t)(j + 1 + c) * mp + j];
+        y = cplx{a.re, -a.im};
+      }
+      vR[c] = y;
+      p2 += y.re * y.re + y.im * y.im;
+    }
+    const double ny2 = svt_block_sum(p2, red);
+    const cplx y0 = vR[0];
+    const double ay0 = sqrt(y0.re * y0.re + y0.im * y0.im), ny = sqrt(ny2);
+    double tau2 = 0.0;
+    cplx beta = {0.0, 0.0}, u0 = y0;
+    if (ny > 0.0) {
+      const cplx ph = ay0 > 0.0 ? cplx{y0.re / ay0, y0.im / ay0} : cplx{1.0, 0.0};
+      beta = cplx{-ph.re * ny, -ph.im * ny};
+      u0 = cplx{y0.re - beta.re, y0.im - beta.im};
+      const double nv2 = ny2 - ay0 * ay0 + u0.re * u0.re + u0.im * u0.im;
+      tau2 = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      vR[0] = u0;
+      ecx[j] = cplx{beta.re, -beta.im};
+    }
+    __syncthreads();
+    // rows j+1..m-1: W[r, c] -= tau2 (sum_c' W[r, c'] v2[c']) conj(v2[c]),
+    // one 16-lane group per row, lanes over columns
+    if (tau2 != 0.0)
+      for (int r = j + 1 + grp; r < m; r += SVT_QP * NG) svt_right_rows(W, mp, j + 1, r, m, vR, tau2, nr, gl);
+    __syncthreads();
+  }
+  // ---- real bidiagonal: B = D_L B' D_R^H
+  if (tid == 0) {
+    cplx q = {1.0, 0.0};
+    for (int j = 0; j < n; ++j) {
+      const cplx z = {dcx[j].re * q.re - dcx[j].im * q.im, dcx[j].re * q.im + dcx[j].im * q.re};
+      const double a = sqrt(z.re * z.re + z.im * z.im);
+      pL[j] = a > 0.0 ? cplx{z.re / a, z.im / a} : cplx{1.0, 0.0};
+      off[2 * j] = a;
+      if (j < n - 1) {
+        // w = conj(p_j) e_j ; q_{j+1} = conj(w/|w|)
+        const cplx p = pL[j], e = ecx[j];
+        const cplx w = {p.re * e.re + p.im * e.im, p.re * e.im - p.im * e.re};
+        const double aw = sqrt(w.re * w.re + w.im * w.im);
+        q = aw > 0.0 ? cplx{w.re / aw, -w.im / aw} : cplx{1.0, 0.0};
+        off[2 * j + 1] = aw;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < N - 1; i += SVT_THREADS) b2[i] = off[i] * off[i];
+  __syncthreads();
+  double bound = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double l = i > 0 ? off[i - 1] : 0.0, r = i < N - 1 ? off[i] : 0.0;
+    bound = fmax(bound, l + r);
+  }
+  bound = bound * (1.0 + 1e-14) + 1e-300;
+  const double pivmin = fmax(2.2250738585072014e-308, 1e-300 * bound * bound);
+  // ---- 2. multisection: one wave per value
+  for (int v = wave; v < k; v += NW) {
+    const int target = N - 1 - v;   // ascending index of the v-th largest eigenvalue
+    double lo = 0.0, hi = bound;
+    for (int it = 0; it < 64; ++it) {
+      const double x = lo + (hi - lo) * double(lane + 1) / 65.0;
+      const int c = svt_count(b2, N, x, pivmin);
+      const unsigned long long above = __ballot(c > target);
+      const int first = above ? __ffsll((long long)above) - 1 : 64;
+      const double nlo = first == 0 ? lo : __shfl(x, first - 1);
+      const double nhi = first == 64 ? hi : __shfl(x, first);
+      // relative precision, or below 1e-18 ||T|| (values under the noise
+      // floor of 1e-15 ||A||_F are returned as zero anyway)
+      const bool done = (nhi - nlo) <= 2.2e-16 * fmax(fabs(nlo), fabs(nhi)) + 1e-18 * bound;
+      lo = nlo;
+      hi = nhi;
+      if (done) break;
+    }
+    if (lane == 0) sig[v] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // ---- 3. inverse iteration: one thread per value solves (T - sigma I) x = b
+  // in LDS (elimination with partial pivoting fused with the forward solve),
+  // then wave 0 normalises and re-orthogonalises close values in order
+  const double eps = 2.220446049250313e-16;
+  const double tiny = eps * bound;
+  const double ortol = 1e-3 * bound;
+  const int pstr = 4 * N + 1;
+  for (int v0b = 0; v0b < k; v0b += SVT_BATCH) {
+    const int kb = k - v0b < SVT_BATCH ? k - v0b : SVT_BATCH;
+    for (int it = 0; it < SVT_ITERS; ++it) {
+      if (tid < kb) {
+        const int v = v0b + tid;
+        double* dd = iib + (int64_t)tid * pstr;
+        double* du = dd + N;
+        double* du2 = du + N;
+        double* x = du2 + N;
+        const double lam = sig[v];
+        if (it == 0) {
+          // deterministic start vector (golden-ratio sequence)
+          for (int i = 0; i < N; ++i) {
+            const double fr = double(i + 1) * 0.6180339887498949 + 0.1 * v;
+            x[i] = 0.5 + (fr - floor(fr));
+          }
+        }
+        // eliminate row i+1 below the pivot row, carrying the right side x;
+        // dd keeps the reciprocal pivots for the back substitution
+        double di = -lam, ui = N > 1 ? off[0] : 0.0, bi = x[0];
+        for (int i = 0; i < N - 1; ++i) {
+          const double li = off[i];                       // sub-diagonal (row i+1, col i)
+          const double dn = -lam;                          // diagonal of row i+1
+          const double un = i + 1 < N - 1 ? off[i + 1] : 0.0;
+          const double bn = x[i + 1];
+          if (fabs(di) >= fabs(li)) {
+            const double piv = fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di;
+            const double rp = svt_rcp(piv);
+            const double fct = li * rp;
+            dd[i] = rp; du[i] = ui; du2[i] = 0.0; x[i] = bi;
+            di = dn - fct * ui;
+            ui = un;
+            bi = bn - fct * bi;
+          } else {
+            const double piv = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
+            const double rp = svt_rcp(piv);
+            const double fct = di * rp;
+            dd[i] = rp; du[i] = dn; du2[i] = un; x[i] = bn;
+            di = ui - fct * dn;
+            ui = -fct * un;
+            bi = bi - fct * bn;
+          }
+        }
+        dd[N - 1] = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
+        x[N - 1] = bi;
+        // back substitution in place
+        x[N - 1] = x[N - 1] * dd[N - 1];
+        if (N > 1) x[N - 2] = (x[N - 2] - du[N - 2] * x[N - 1]) * dd[N - 2];
+        for (int i = N - 3; i >= 0; --i)
+          x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) * dd[i];
+      }
+      __syncthreads();
+      if (wave == 0) {
+        for (int vb = 0; vb < kb; ++vb) {
+          const int v = v0b + vb;
+          double* x = iib + (int64_t)vb * pstr + 3 * N;
+          // against earlier close values (finished ones are in the work buffer)
+          for (int u = 0; u < v; ++u) {
+            if (fabs(sig[u] - sig[v]) >= ortol) continue;
+            const double* y = u >= v0b ? iib + (int64_t)(u - v0b) * pstr + 3 * N
+                                       : pv + (int64_t)u * svt_stride(m, n);
+            double s = 0.0;
+            for (int i = lane; i < N; i += 64) s += y[i] * x[i];
+            s = wave_sum64(s);
+            for (int i = lane; i < N; i += 64) x[i] -= s * y[i];
+          }
+          double s = 0.0;
+          for (int i = lane; i < N; i += 64) s += x[i] * x[i];
+          s = wave_sum64(s);
+          const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+          for (int i = lane; i < N; i += 64) x[i] *= inv;
+        }
+      }
+      __syncthreads();
+    }
+    // keep the batch's eigenvectors in the work buffer
+    for (int e = tid; e < kb * N; e += SVT_THREADS) {
+      const int vb = e / N, i = e % N;
+      pv[(int64_t)(v0b + vb) * svt_stride(m, n) + i] = iib[(int64_t)vb * pstr + 3 * N + i];
+    }
+    __syncthreads();
+  }
+  // ---- 4. U = Q_L D_L u, one wave per value; lane l holds rows l, l+64, l+128
+  const double floor2 = 1e-30 * fro2_s;
+  for (int v = wave; v < k; v += NW) {
+    const double* z = pv + (int64_t)v * svt_stride(m, n);
+    const bool zero = sig[v] * sig[v] <= floor2;
+    double s = 0.0;
+    for (int i = lane; i < n; i += 64) s += z[2 * i + 1] * z[2 * i + 1];
+    s = wave_sum64(s);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    cplx uc[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int i = lane + 64 * t;
+      uc[t] = cplx{0.0, 0.0};
+      if (i < n && !zero) uc[t] = cplx{pL[i].re * z[2 * i + 1] * inv, pL[i].im * z[2 * i + 1] * inv};
+    }
+    for (int j = n - 1; j >= 0; --j) {
+      const double tau = tauL[j];
+      if (tau == 0.0) continue;
+      const cplx* vj = W + (int64_t)j * mp;
+      cplx a[3];
+      double wr = 0.0, wi = 0.0;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int i = lane + 64 * t;
+        a[t] = (i >= j && i < m) ? vj[i] : cplx{0.0, 0.0};
+        wr += a[t].re * uc[t].re + a[t].im * uc[t].im;
+        wi += a[t].re * uc[t].im - a[t].im * uc[t].re;
+      }
+      wr = wave_sum64(wr);
+      wi = wave_sum64(wi);
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        uc[t].re -= tau * (a[t].re * wr - a[t].im * wi);
+        uc[t].im -= tau * (a[t].re * wi + a[t].im * wr);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int i = lane + 64 * t;
+      if (i < m) dsc.U[(int64_t)i * k + v] = uc[t];
+    }
+    if (lane == 0) dsc.sigma[v] = zero ? 0.0 : sig[v];
+  }
+}
+
+
 __global__ __launch_bounds__(256) void k_colphase(const ColPhaseDesc* __restrict__ descs) {
   const ColPhaseDesc d = descs[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

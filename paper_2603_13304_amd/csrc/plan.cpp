@@ -38,6 +38,9 @@ namespace {
 // largest fully merged in-leg run (complex elements) before the swallow
 // switches to the progressive contraction order
 constexpr int64_t kMergedPeakElems = int64_t(1) << 25;
+// narrowest truncated SVD block that goes through bidiagonalisation instead
+// of one-sided Jacobi (measured crossover on 144-row blocks)
+constexpr int64_t kSvdTopMinCols = 112;
 
 uint64_t mix_out0(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
@@ -161,8 +164,13 @@ struct Compiler::Lane {
     if (cols > rows || cols > kJacobiMaxCols) { err = "Jacobi SVD needs cols <= rows"; return; }
     Op op;
     op.type = OPK_JACOBI;
-    op.a = A; op.b = scratch(jacobi_work_elems(rows, cols)); op.c = U; op.d = sig;
+    // wide blocks with a truncated rank go through bidiagonalisation: its
+    // cost grows with cols, the Jacobi sweeps' with cols^2 times a sweep count
+    const bool top = keep < cols && cols >= kSvdTopMinCols;
+    op.a = A; op.c = U; op.d = sig;
+    op.b = scratch(top ? svd_top_work_elems(rows, cols, keep) : jacobi_work_elems(rows, cols));
     op.i[0] = rows; op.i[1] = cols; op.i[2] = lda; op.i[3] = conjT; op.i[4] = keep;
+    op.i[5] = top ? 1 : 0;
     push(op);
   }
   void omega(Ref dst, int64_t n, int64_t k, uint64_t prefix, bool sweep_tag) {
