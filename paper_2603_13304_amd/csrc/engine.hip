@@ -461,8 +461,10 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r) 
         hipLaunchKernelGGL(k_qr, r.grid, blk, r.lds, stream, (const QrDesc*)d);
       break;
     case OPK_JACOBI:
-      if (r.variant == 2)
+      if (r.variant == 2) {
+        hipLaunchKernelGGL(k_svt_bidiag, r.grid, dim3(SVB_THREADS), 0, stream, (const JacobiDesc*)d);
         hipLaunchKernelGGL(k_svd_top, r.grid, dim3(SVT_THREADS), 0, stream, (const JacobiDesc*)d);
+      }
       else if (r.variant)
         hipLaunchKernelGGL(k_jacobi<true>, r.grid, dim3(JAC_THREADS), r.lds, stream,
                            (const JacobiDesc*)d);

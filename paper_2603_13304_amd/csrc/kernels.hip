@@ -930,28 +930,18 @@ template __global__ void k_jacobi<true>(const JacobiDesc*);
 //      entries of the eigenvector are the left singular vector u of B';
 //   4. U = Q_L D_L u through the stored reflectors.
 // Singular values at or below 1e-15 ||A||_F give zero columns, as k_jacobi.
-// The working copy is column-major with rows padded to 16-row slices (zero
-// rows), so the passes over a column or a row issue all their loads at once.
+// Step 1 is its own kernel (k_svt_bidiag, the matrix held on chip); steps 2-4
+// run in k_svd_top on what it leaves in the work buffer.
 constexpr int SVT_THREADS = 1024;
 constexpr int SVT_MAXN = 144;          // rows and cols limit, as k_jacobi
 constexpr int SVT_ITERS = 3;           // inverse iteration steps
-constexpr int SVT_BATCH = 12;          // values per inverse-iteration batch (LDS)
+constexpr int SVT_BATCH = 16;          // values per inverse-iteration batch (LDS)
 
-// work buffer: the padded matrix, then per value the eigenvector of T (2n
+// work buffer: the left reflectors (rows padded to 16, column-major), the
+// bidiagonal (3 cols + 2 complex), then per value the eigenvector of T (2n
 // doubles) and the complex output vector (rows)
 __host__ __device__ inline int64_t svt_stride(int64_t rows, int64_t cols) {
   return 2 * cols + 2 * rows;
-}
-
-__device__ __forceinline__ double svt_block_sum(double v, double* sh) {
-  v = wave_sum64(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) sh[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < SVT_THREADS / 64; ++w) s += sh[w];
-  return s;
 }
 
 // 1/q from the hardware estimate and two Newton steps (full precision for
@@ -976,208 +966,375 @@ __device__ int svt_count(const double* b2, int N, double x, double pivmin) {
   return cnt;
 }
 
-#define SVT_QP 2
-// Up to SVT_QP trailing columns of the left reflector, a -= tau v (v^H a),
-// with all loads in flight together; lane gl of the 16-lane group holds rows
-// gl + 16 t.  Columns c0 + 64 q (q < SVT_QP, c < n).  Kept out of line with the row
-// pass so that the two register sets are not live together.
-__device__ __noinline__ void svt_left_cols(cplx* W, int mp, int c0, int n, const cplx* vL, double tau,
-                                           int nt, int gl) {
-  cplx a[SVT_QP][9];
+// sum over lanes l, l ^ 16, l ^ 32, l ^ 48 (the four 16-lane rows of the
+// wave), every lane active
+__device__ __forceinline__ double rows4_sum(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  v = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  lo = __double2loint(v);
+  hi = __double2hiint(v);
+  a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+
+// sum over the 64 lanes (16-lane DPP sums, then the four rows); every lane
+// must be active
+__device__ __forceinline__ double wave_sum_all(double v) { return rows4_sum(group16_sum(v)); }
+
+// Householder reflector H = I - tau v v^H with H x = alpha e_0 for the
+// vector x of norm^2 nx2 and head x0: alpha = -phase(x0) |x|, v = x - alpha
+// e_0 (only the head changes); returns the head of v
+__device__ __forceinline__ cplx svt_house(cplx x0, double nx2, double* tau, cplx* alpha) {
+  const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
+  *tau = 0.0;
+  *alpha = cplx{0.0, 0.0};
+  if (!(nx > 0.0)) return x0;
+  const double r = ax0 > 0.0 ? nx / ax0 : 0.0;
+  *alpha = ax0 > 0.0 ? cplx{-x0.re * r, -x0.im * r} : cplx{-nx, 0.0};
+  const cplx v0 = {x0.re - alpha->re, x0.im - alpha->im};
+  const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
+  *tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
+  return v0;
+}
+
+// Stage 1 (k_svt_bidiag, 512 threads): the matrix stays on chip.  Thread
+// (r, g) = (tid % 16, tid / 16) holds rows r + 16 a (a < 9) of five column
+// slots: columns g (slot 0, in LDS: finished after 32 steps), g + 32, g + 64,
+// g + 96 (slots 1-3, registers) and, for g < 16, g + 128 (slot 4, LDS until it
+// moves into registers).  A column reduction is a 16-lane DPP sum; a row
+// reduction sums the four 16-lane rows of a wave (lane swaps), then the 8
+// waves (LDS).  Writes the left reflectors (column j, rows j.., head at row j)
+// and, after them, the bidiagonal: d_j, conj(e_j), tau_j (real part) and
+// ||A||_F^2.
+constexpr int SVB_THREADS = 512;
+__host__ __device__ inline int64_t svt_bd_off(int64_t rows, int64_t cols) {
+  return (rows + 15) / 16 * 16 * cols;
+}
+__host__ __device__ inline int64_t svt_pv_off(int64_t rows, int64_t cols) {
+  return svt_bd_off(rows, cols) + 3 * cols + 2;
+}
+
+__global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __restrict__ descs) {
+  const JacobiDesc dsc = descs[blockIdx.x];
+  const int m = dsc.rows, n = dsc.cols, k = dsc.keep;
+  if (n > SVT_MAXN || m > SVT_MAXN || n > m || k > n || n < 1) return;   // excluded by the plan
+  const int nt = (m + 15) / 16, mp = nt * 16;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rl = tid & 15, cg = tid >> 4, q4 = (tid >> 4) & 3;
+  constexpr int NW = SVB_THREADS / 64, NS = 5;
+  constexpr int NR = SVT_MAXN + 16 * 8;  // row index range of the shifted slots
+  static_assert(NW == 8 && SVT_MAXN == 144, "thread layout");
+  __shared__ cplx xl[32 * SVT_MAXN];     // slot 0: [g][row], column g
+  __shared__ cplx xa[16 * SVT_MAXN];     // slot 4 before it moves: [g][row], column g + 128
+  __shared__ cplx xp[NW * NR];           // [wave][row]: partial row sums
+  __shared__ cplx uL[NR], yR[SVT_MAXN], xs[NR];
+  __shared__ double red[NW], tau_s;
+  cplx* W = dsc.work;
+  cplx* bd = dsc.work + svt_bd_off(m, n);
+  if (tid == 0) bd[2 * n - 1] = cplx{0.0, 0.0};   // e_{n-1} does not exist
+  for (int i = tid; i < NR; i += SVB_THREADS) uL[i] = xs[i] = cplx{0.0, 0.0};
+  const bool has4 = wave < 4;                      // column g + 128 exists (g < 16)
+  // Register slot A[a][q] (slot q + 1) holds row rl + 16 (a + r) of column
+  // cg + 32 (q + 1 + t), after r row shifts and t column shifts: every 16
+  // steps the finished row slot drops off the front (a zero row slot enters
+  // at the back); from step 64 on, every 32 steps the finished register
+  // column slot does, column g + 128 entering from LDS at the first of them.
+  // So row j is always row slot 0 and, from step 32 on, column j is register
+  // slot 0 (before, LDS slot 0).  Rows past the matrix stay exactly zero (their
+  // u and x are zero): every pass runs all 9 row slots without a test.  A is
+  // only indexed with constants, so it stays in registers.
+  cplx A[9][3];
+  double f = 0.0;
 #pragma unroll
-  for (int q = 0; q < SVT_QP; ++q) {
-    const int c = c0 + 64 * q;
+  for (int a = 0; a < 9; ++a) {
+    const int i = rl + 16 * a;
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
-      if (c < n && t < nt) a[q][t] = W[(int64_t)c * mp + gl + 16 * t];
+    for (int b = 0; b < NS; ++b) {
+      if (b == 4 && !has4) continue;
+      const int c = cg + 32 * b;
+      const bool ok = i < m && c < n;
+      const int64_t o = !ok ? 0 : dsc.conjT ? (int64_t)c * dsc.lda + i : (int64_t)i * dsc.lda + c;
+      cplx v = dsc.A[o];
+      if (dsc.conjT) v.im = -v.im;
+      if (!ok) v = cplx{0.0, 0.0};
+      f += v.re * v.re + v.im * v.im;
+      if (b == 0) xl[cg * SVT_MAXN + i] = v;
+      else if (b < 4) A[a][b - 1] = v;
+      else xa[cg * SVT_MAXN + i] = v;
+    }
   }
+  f = wave_sum_all(f);
+  if (lane == 0) red[wave] = f;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[w];
+    bd[3 * n] = cplx{t, 0.0};
+  }
+  for (int j0 = 0, r = 0; j0 < n; j0 += 16, ++r) {
+    const int s = r >> 1;                          // 32-column blocks done
+    const int t = s > 1 ? s - 1 : 0;               // register column shifts
+    const int rb = rl + 16 * r;                    // row of row slot a: rb + 16 a
+    // slot b: 0 = LDS columns g, 1..3 = A[.][b-1], 4 = LDS columns g + 128
+    auto col = [&](int b) { return b == 0 ? cg : b < 4 ? cg + 32 * (b + t) : cg + 128; };
+    auto live = [&](int b) {
+      return b == 0 ? s == 0 : b < 4 ? (b + t <= 3 || (b + t == 4 && has4)) : (t == 0 && has4);
+    };
+    // LDS element of row slot a (index clamped in range for every lane;
+    // padded row slots read 0)
+    auto lds_at = [&](const cplx* base, int gmask, int a) -> cplx {
+      cplx x = base[(cg & gmask) * SVT_MAXN + (a + r < 9 ? rb + 16 * a : 0)];
+      if (a + r >= 9) x = cplx{0.0, 0.0};
+      return x;
+    };
+    auto get = [&](int a, int b) -> cplx {
+      if (b == 0) return lds_at(xl, 31, a);
+      if (b == 4) return lds_at(xa, 15, a);
+      cplx x = A[a][0];
+      if (b == 2) x = A[a][1];
+      if (b == 3) x = A[a][2];
+      return x;
+    };
+    auto put = [&](int a, int b, cplx x) {
+      if (b == 0) { if (a + r < 9) xl[cg * SVT_MAXN + rb + 16 * a] = x; }
+      else if (b == 4) { if (a + r < 9) xa[cg * SVT_MAXN + rb + 16 * a] = x; }
+      else if (b == 1) A[a][0] = x;
+      else if (b == 2) A[a][1] = x;
+      else A[a][2] = x;
+    };
+    const int jend = j0 + 16 < n ? j0 + 16 : n;
+    for (int j = j0; j < jend; ++j) {
+      const int jj = j - j0;                       // row j: row slot 0 of lane rl == jj
+      const int bj = s == 0 ? 0 : 1;               // column slot of column j
+      // ---- left reflector from column j (lanes cg == j % 32), rows j..m-1
+      if (cg == (j & 31)) {
+        double part = 0.0;
+        cplx head = {0.0, 0.0};
 #pragma unroll
-  for (int q = 0; q < SVT_QP; ++q) {
-    const int c = c0 + 64 * q;
-    if (c >= n) break;
-    double wr = 0.0, wi = 0.0;
-#pragma unroll
-    for (int t = 0; t < 9; ++t)
-      if (t < nt) {
-        const cplx v = vL[gl + 16 * t];
-        wr += v.re * a[q][t].re + v.im * a[q][t].im;
-        wi += v.re * a[q][t].im - v.im * a[q][t].re;
+        for (int a = 0; a < 9; ++a) {
+          const int i = rb + 16 * a;
+          cplx v = bj == 0 ? lds_at(xl, 31, a) : A[a][0];
+          if (a == 0) head = v;
+          if (i < j || i >= m) v = cplx{0.0, 0.0};
+          uL[i] = v;
+          if (i > j && i < m) W[(int64_t)j * mp + i] = v;
+          part = fma(v.re, v.re, fma(v.im, v.im, part));
+        }
+        const double nx2 = group16_sum(part);
+        const int src = (lane & 48) | jj;
+        const cplx x0 = {__shfl(head.re, src), __shfl(head.im, src)};
+        double tau;
+        cplx alpha;
+        const cplx v0 = svt_house(x0, nx2, &tau, &alpha);
+        if (rl == jj) {
+          uL[j] = v0;
+          W[(int64_t)j * mp + j] = v0;
+        }
+        if (rl == 0) {
+          tau_s = tau;
+          bd[j] = alpha;
+          bd[2 * n + j] = cplx{tau, 0.0};
+        }
       }
-    wr = group16_sum(wr);
-    wi = group16_sum(wi);
+      __syncthreads();
+      // ---- trailing columns c > j: a -= tau u (u^H a)
+      const double tau = tau_s;
+      if (tau != 0.0) {
+        cplx u[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
-      if (t < nt) {
-        const cplx v = vL[gl + 16 * t];
-        a[q][t].re -= tau * (v.re * wr - v.im * wi);
-        a[q][t].im -= tau * (v.re * wi + v.im * wr);
-        W[(int64_t)c * mp + gl + 16 * t] = a[q][t];
+        for (int a = 0; a < 9; ++a) u[a] = uL[rb + 16 * a];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          if (!live(b)) continue;                  // scalar
+          cplx x[9];
+          double wr = 0.0, wi = 0.0;
+#pragma unroll
+          for (int a = 0; a < 9; ++a) {
+            x[a] = get(a, b);
+            wr = fma(u[a].re, x[a].re, fma(u[a].im, x[a].im, wr));
+            wi = fma(u[a].re, x[a].im, fma(-u[a].im, x[a].re, wi));
+          }
+          wr = group16_sum(wr);
+          wi = group16_sum(wi);
+          const bool cl = col(b) > j;              // this lane's column is trailing
+          wr = cl ? tau * wr : 0.0;
+          wi = cl ? tau * wi : 0.0;
+#pragma unroll
+          for (int a = 0; a < 9; ++a) {
+            x[a].re = fma(-u[a].re, wr, fma(u[a].im, wi, x[a].re));
+            x[a].im = fma(-u[a].re, wi, fma(-u[a].im, wr, x[a].im));
+            put(a, b, x[a]);
+          }
+        }
       }
+      if (j == n - 1) break;
+      // ---- right reflector from row j (row slot 0 of lane rl == jj), columns
+      // j+1..: y = conj(row) into yR, its norm summed per wave
+      {
+        double part = 0.0;
+        if (rl == jj) {
+#pragma unroll
+          for (int b = 0; b < NS; ++b) {
+            if (!live(b)) continue;
+            const int c = col(b);
+            const cplx x = get(0, b);
+            cplx y = {0.0, 0.0};
+            if (c > j && c < n) y = cplx{x.re, -x.im};
+            yR[c] = y;
+            part = fma(y.re, y.re, fma(y.im, y.im, part));
+          }
+        }
+        part = rows4_sum(part);
+        if (lane == jj) red[wave] = part;
+      }
+      __syncthreads();
+      const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
+      double tau2;
+      cplx beta;
+      const cplx u0 = svt_house(yR[j + 1], ny2, &tau2, &beta);
+      if (tid == 0) bd[n + j] = cplx{beta.re, -beta.im};
+      // ---- rows i > j: a -= tau2 (a . v2) conj(v2)
+      cplx v2[NS];
+      if (tau2 != 0.0) {
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          const int c = col(b);
+          v2[b] = cplx{0.0, 0.0};
+          if (live(b) && c > j + 1) v2[b] = yR[c];
+          if (c == j + 1) v2[b] = u0;
+        }
+        double xr[9], xi[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) xr[a] = xi[a] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          if (!live(b)) continue;                  // scalar
+#pragma unroll
+          for (int a = 0; a < 9; ++a) {
+            const cplx x = get(a, b);
+            xr[a] = fma(x.re, v2[b].re, fma(-x.im, v2[b].im, xr[a]));
+            xi[a] = fma(x.re, v2[b].im, fma(x.im, v2[b].re, xi[a]));
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+          const double sr = rows4_sum(xr[a]), si = rows4_sum(xi[a]);
+          if (q4 == 0) xp[wave * NR + rb + 16 * a] = cplx{sr, si};
+        }
+      }
+      __syncthreads();
+      if (tau2 != 0.0 && tid < mp && tid > j) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const cplx p = xp[w * NR + tid];
+          sr += p.re;
+          si += p.im;
+        }
+        xs[tid] = cplx{tau2 * sr, tau2 * si};
+      }
+      __syncthreads();
+      if (tau2 != 0.0) {
+        cplx x[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+          const int i = rb + 16 * a;
+          x[a] = xs[i];
+          if (i <= j || i >= mp) x[a] = cplx{0.0, 0.0};
+        }
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          if (!live(b)) continue;
+#pragma unroll
+          for (int a = 0; a < 9; ++a) {
+            cplx y = get(a, b);
+            y.re = fma(-x[a].re, v2[b].re, fma(-x[a].im, v2[b].im, y.re));   // x conj(v2)
+            y.im = fma(-x[a].im, v2[b].re, fma(x[a].re, v2[b].im, y.im));
+            put(a, b, y);
+          }
+        }
+      }
+    }
+    if (j0 + 16 >= n) break;
+    // drop the finished row slot; from the block at step 64 on, every other
+    // block also the finished register column slot (column g + 128 moving in
+    // from LDS the first time)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+      for (int a = 0; a < 8; ++a) A[a][q] = A[a + 1][q];
+      A[8][q] = cplx{0.0, 0.0};
+    }
+    const int s1 = (r + 1) >> 1;
+    if (s1 != s && s1 >= 2) {
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        A[a][0] = A[a][1];
+        A[a][1] = A[a][2];
+        const int ra = a + r + 1;                  // row slot index after the row shift
+        const cplx x = xa[(cg & 15) * SVT_MAXN + (ra < 9 ? rl + 16 * ra : 0)];
+        A[a][2] = (s1 == 2 && has4 && ra < 9) ? x : cplx{0.0, 0.0};
+      }
+    }
   }
 }
 
-// Up to SVT_QP rows of the right reflector, a -= tau2 (a . v2) conj(v2), all
-// loads in flight together; rows r0 + 64 q (< m), columns j1 + c for
-// c = gl + 16 t < nr.
-__device__ __noinline__ void svt_right_rows(cplx* W, int mp, int j1, int r0, int m, const cplx* vR,
-                                            double tau2, int nr, int gl) {
-  cplx a[SVT_QP][9];
-#pragma unroll
-  for (int q = 0; q < SVT_QP; ++q) {
-    const int r = r0 + 64 * q;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int c = gl + 16 * t;
-      if (r < m && c < nr) a[q][t] = W[(int64_t)(j1 + c) * mp + r];
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < SVT_QP; ++q) {
-    const int r = r0 + 64 * q;
-    if (r >= m) break;
-    double wr = 0.0, wi = 0.0;
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int c = gl + 16 * t;
-      if (c < nr) {
-        const cplx v = vR[c];
-        wr += a[q][t].re * v.re - a[q][t].im * v.im;
-        wi += a[q][t].re * v.im + a[q][t].im * v.re;
-      }
-    }
-    wr = group16_sum(wr);
-    wi = group16_sum(wi);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int c = gl + 16 * t;
-      if (c < nr) {
-        const cplx v = vR[c];
-        a[q][t].re -= tau2 * (wr * v.re + wi * v.im);   // w conj(v)
-        a[q][t].im -= tau2 * (wi * v.re - wr * v.im);
-        W[(int64_t)(j1 + c) * mp + r] = a[q][t];
-      }
-    }
-  }
-}
-
+// Stages 2-4 on the bidiagonal and reflectors written by k_svt_bidiag.
 __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __restrict__ descs) {
   const JacobiDesc dsc = descs[blockIdx.x];
   const int m = dsc.rows, n = dsc.cols, k = dsc.keep, N = 2 * n;
   const int nt = (m + 15) / 16, mp = nt * 16;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, grp = tid >> 4, gl = tid & 15;
-  constexpr int NW = SVT_THREADS / 64, NG = SVT_THREADS / 16;
-  __shared__ double red[NW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = SVT_THREADS / 64;
   __shared__ double tauL[SVT_MAXN];
   __shared__ cplx dcx[SVT_MAXN], ecx[SVT_MAXN], pL[SVT_MAXN];
   __shared__ double off[2 * SVT_MAXN], b2[2 * SVT_MAXN], sig[SVT_MAXN];
-  __shared__ cplx vL[SVT_MAXN], vR[SVT_MAXN];
   __shared__ double fro2_s;
   // inverse iteration: dd, du, du2, x per value; the odd stride keeps the
   // values' arrays in different LDS banks
   __shared__ double iib[SVT_BATCH * (4 * 2 * SVT_MAXN + 1)];
-  if (n > SVT_MAXN || m > SVT_MAXN || n > m || k > n) return;   // excluded by the plan compiler
-  cplx* W = dsc.work;                                  // mp x n column-major
-  double* pv = reinterpret_cast<double*>(dsc.work + (int64_t)mp * n);
-  double f = 0.0;
-  for (int e = tid; e < mp * n; e += SVT_THREADS) {
-    const int c = e / mp, i = e % mp;
-    cplx v = {0.0, 0.0};
-    if (i < m) {
-      if (dsc.conjT) { v = dsc.A[(int64_t)c * dsc.lda + i]; v.im = -v.im; }
-      else v = dsc.A[(int64_t)i * dsc.lda + c];
-    }
-    W[e] = v;
-    f += v.re * v.re + v.im * v.im;
+  if (n > SVT_MAXN || m > SVT_MAXN || n > m || k > n || n < 1) return;   // excluded by the plan
+  const cplx* W = dsc.work;                            // reflectors, mp x n column-major
+  const cplx* bd = dsc.work + svt_bd_off(m, n);
+  double* pv = reinterpret_cast<double*>(dsc.work + svt_pv_off(m, n));
+  for (int j = tid; j < n; j += SVT_THREADS) {
+    dcx[j] = bd[j];
+    ecx[j] = bd[n + j];
+    tauL[j] = bd[2 * n + j].re;
   }
-  f = svt_block_sum(f, red);
-  if (tid == 0) fro2_s = f;
-  // ---- 1. bidiagonalisation
-  for (int j = 0; j < n; ++j) {
-    // left reflector from column j, rows j..m-1 (copied to vL, zero elsewhere)
-    const cplx* xj = W + (int64_t)j * mp;
-    double part = 0.0;
-    for (int i = tid; i < SVT_MAXN; i += SVT_THREADS) {
-      const cplx x = (i >= j && i < m) ? xj[i] : cplx{0.0, 0.0};
-      vL[i] = x;
-      part += x.re * x.re + x.im * x.im;
+  if (tid == 0) fro2_s = bd[3 * n].re;
+  __syncthreads();
+  // ---- real bidiagonal: B = D_L B' D_R^H.  |d_j| and |e_j| need no phases;
+  // with the unit phases ph(d_j), ph(e_j) (1 for zero), the running phase is
+  // p_j = ph(d_j) q_j, q_{j+1} = p_j conj(ph(e_j)), q_0 = 1
+  for (int j = tid; j < n; j += SVT_THREADS) {
+    const cplx d = dcx[j];
+    const double ad = sqrt(d.re * d.re + d.im * d.im);
+    off[2 * j] = ad;
+    pL[j] = ad > 0.0 ? cplx{d.re / ad, d.im / ad} : cplx{1.0, 0.0};
+    if (j < n - 1) {
+      const cplx e = ecx[j];
+      const double ae = sqrt(e.re * e.re + e.im * e.im);
+      off[2 * j + 1] = ae;
+      ecx[j] = ae > 0.0 ? cplx{e.re / ae, e.im / ae} : cplx{1.0, 0.0};
     }
-    const double nx2 = svt_block_sum(part, red);   // (barrier: vL complete)
-    const cplx x0 = vL[j];
-    const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
-    double tau = 0.0;
-    cplx alpha = {0.0, 0.0}, v0 = x0;
-    if (nx > 0.0) {
-      const cplx ph = ax0 > 0.0 ? cplx{x0.re / ax0, x0.im / ax0} : cplx{1.0, 0.0};
-      alpha = cplx{-ph.re * nx, -ph.im * nx};
-      v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
-      const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
-      tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      vL[j] = v0;
-      tauL[j] = tau;
-      dcx[j] = alpha;
-    }
-    __syncthreads();
-    // trailing columns: a -= tau v (v^H a), one 16-lane group per column
-    if (tau != 0.0)
-      for (int c = j + 1 + grp; c < n; c += SVT_QP * NG) svt_left_cols(W, mp, c, n, vL, tau, nt, gl);
-    // the reflector (head v0) is stored in column j, rows j..
-    if (tid == 0 && tau != 0.0) W[(int64_t)j * mp + j] = v0;
-    __syncthreads();
-    if (j == n - 1) break;
-    // right reflector from row j, columns j+1..n-1: x = conj(W[j, j+1:])
-    const int nr = n - j - 1;
-    double p2 = 0.0;
-    for (int c = tid; c < SVT_MAXN; c += SVT_THREADS) {
-      cplx y = {0.0, 0.0};
-      if (c < nr) {
-        const cplx a = W[(int64_t)(j + 1 + c) * mp + j];
-        y = cplx{a.re, -a.im};
-      }
-      vR[c] = y;
-      p2 += y.re * y.re + y.im * y.im;
-    }
-    const double ny2 = svt_block_sum(p2, red);
-    const cplx y0 = vR[0];
-    const double ay0 = sqrt(y0.re * y0.re + y0.im * y0.im), ny = sqrt(ny2);
-    double tau2 = 0.0;
-    cplx beta = {0.0, 0.0}, u0 = y0;
-    if (ny > 0.0) {
-      const cplx ph = ay0 > 0.0 ? cplx{y0.re / ay0, y0.im / ay0} : cplx{1.0, 0.0};
-      beta = cplx{-ph.re * ny, -ph.im * ny};
-      u0 = cplx{y0.re - beta.re, y0.im - beta.im};
-      const double nv2 = ny2 - ay0 * ay0 + u0.re * u0.re + u0.im * u0.im;
-      tau2 = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      vR[0] = u0;
-      ecx[j] = cplx{beta.re, -beta.im};
-    }
-    __syncthreads();
-    // rows j+1..m-1: W[r, c] -= tau2 (sum_c' W[r, c'] v2[c']) conj(v2[c]),
-    // one 16-lane group per row, lanes over columns
-    if (tau2 != 0.0)
-      for (int r = j + 1 + grp; r < m; r += SVT_QP * NG) svt_right_rows(W, mp, j + 1, r, m, vR, tau2, nr, gl);
-    __syncthreads();
   }
-  // ---- real bidiagonal: B = D_L B' D_R^H
+  __syncthreads();
   if (tid == 0) {
     cplx q = {1.0, 0.0};
     for (int j = 0; j < n; ++j) {
-      const cplx z = {dcx[j].re * q.re - dcx[j].im * q.im, dcx[j].re * q.im + dcx[j].im * q.re};
-      const double a = sqrt(z.re * z.re + z.im * z.im);
-      pL[j] = a > 0.0 ? cplx{z.re / a, z.im / a} : cplx{1.0, 0.0};
-      off[2 * j] = a;
+      const cplx d = pL[j];
+      const cplx p = off[2 * j] > 0.0 ? cplx{d.re * q.re - d.im * q.im, d.re * q.im + d.im * q.re}
+                                      : cplx{1.0, 0.0};
+      pL[j] = p;
       if (j < n - 1) {
-        // w = conj(p_j) e_j ; q_{j+1} = conj(w/|w|)
-        const cplx p = pL[j], e = ecx[j];
-        const cplx w = {p.re * e.re + p.im * e.im, p.re * e.im - p.im * e.re};
-        const double aw = sqrt(w.re * w.re + w.im * w.im);
-        q = aw > 0.0 ? cplx{w.re / aw, -w.im / aw} : cplx{1.0, 0.0};
-        off[2 * j + 1] = aw;
+        const cplx e = ecx[j];
+        q = off[2 * j + 1] > 0.0 ? cplx{p.re * e.re + p.im * e.im, p.im * e.re - p.re * e.im}
+                                 : cplx{1.0, 0.0};
       }
     }
   }
@@ -1191,25 +1348,35 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   }
   bound = bound * (1.0 + 1e-14) + 1e-300;
   const double pivmin = fmax(2.2250738585072014e-308, 1e-300 * bound * bound);
-  // ---- 2. multisection: one wave per value
-  for (int v = wave; v < k; v += NW) {
-    const int target = N - 1 - v;   // ascending index of the v-th largest eigenvalue
-    double lo = 0.0, hi = bound;
-    for (int it = 0; it < 64; ++it) {
-      const double x = lo + (hi - lo) * double(lane + 1) / 65.0;
-      const int c = svt_count(b2, N, x, pivmin);
-      const unsigned long long above = __ballot(c > target);
-      const int first = above ? __ffsll((long long)above) - 1 : 64;
-      const double nlo = first == 0 ? lo : __shfl(x, first - 1);
-      const double nhi = first == 64 ? hi : __shfl(x, first);
-      // relative precision, or below 1e-18 ||T|| (values under the noise
-      // floor of 1e-15 ||A||_F are returned as zero anyway)
-      const bool done = (nhi - nlo) <= 2.2e-16 * fmax(fabs(nlo), fabs(nhi)) + 1e-18 * bound;
-      lo = nlo;
-      hi = nhi;
-      if (done) break;
+  // ---- 2. multisection: 16 shifts (lanes) per value, 4 values per wave on
+  // waves 0..3 (one per SIMD: each count is a dependent chain)
+  {
+    const int g16 = lane >> 4, gl = lane & 15;
+    for (int v0 = 0; v0 < k; v0 += 16) {
+      if (wave < 4 && v0 + 4 * wave < k) {
+        const int v = v0 + 4 * wave + g16;
+        const int target = N - 1 - (v < k ? v : k - 1);   // ascending index of the value
+        double lo = 0.0, hi = bound;
+        for (int it = 0; it < 96; ++it) {
+          const double x = lo + (hi - lo) * double(gl + 1) / 17.0;
+          const int c = svt_count(b2, N, x, pivmin);
+          const unsigned long long above = __ballot(c > target);
+          const unsigned ag = unsigned(above >> (16 * g16)) & 0xFFFFu;
+          const int first = ag ? __ffs(ag) - 1 : 16;
+          const double nlo = __shfl(x, 16 * g16 + (first > 0 ? first - 1 : 0));
+          const double nhi = __shfl(x, 16 * g16 + (first < 16 ? first : 15));
+          lo = first == 0 ? lo : nlo;
+          hi = first == 16 ? hi : nhi;
+          // a bracket of at most two ulps (its midpoint is within one ulp; one
+          // ulp can exceed 2.2e-16 |x| just above a power of two, so a 1-ulp
+          // test would never end there), or below 1e-18 ||T|| (values under
+          // the noise floor of 1e-15 ||A||_F are returned as zero anyway)
+          const bool done = (hi - lo) <= 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-18 * bound;
+          if (__ballot(!done) == 0) break;
+        }
+        if (gl == 0 && v < k) sig[v] = 0.5 * (lo + hi);
+      }
     }
-    if (lane == 0) sig[v] = 0.5 * (lo + hi);
   }
   __syncthreads();
   // ---- 3. inverse iteration: one thread per value solves (T - sigma I) x = b
@@ -1237,38 +1404,48 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           }
         }
         // eliminate row i+1 below the pivot row, carrying the right side x;
-        // dd keeps the reciprocal pivots for the back substitution
+        // dd keeps the reciprocal pivots for the back substitution.  The
+        // loads of step i+1 are issued during step i.
         double di = -lam, ui = N > 1 ? off[0] : 0.0, bi = x[0];
+        double li_n = off[0], un_n = N > 2 ? off[1] : 0.0, bn_n = N > 1 ? x[1] : 0.0;
         for (int i = 0; i < N - 1; ++i) {
-          const double li = off[i];                       // sub-diagonal (row i+1, col i)
+          const double li = li_n;                          // sub-diagonal (row i+1, col i)
           const double dn = -lam;                          // diagonal of row i+1
-          const double un = i + 1 < N - 1 ? off[i + 1] : 0.0;
-          const double bn = x[i + 1];
-          if (fabs(di) >= fabs(li)) {
-            const double piv = fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di;
-            const double rp = svt_rcp(piv);
-            const double fct = li * rp;
-            dd[i] = rp; du[i] = ui; du2[i] = 0.0; x[i] = bi;
-            di = dn - fct * ui;
-            ui = un;
-            bi = bn - fct * bi;
-          } else {
-            const double piv = fabs(li) < tiny ? (li < 0.0 ? -tiny : tiny) : li;
-            const double rp = svt_rcp(piv);
-            const double fct = di * rp;
-            dd[i] = rp; du[i] = dn; du2[i] = un; x[i] = bn;
-            di = ui - fct * dn;
-            ui = -fct * un;
-            bi = bi - fct * bn;
-          }
+          const double un = un_n;
+          const double bn = bn_n;
+          li_n = off[i + 1];
+          un_n = i + 2 < N - 1 ? off[i + 2] : 0.0;
+          bn_n = i + 2 < N ? x[i + 2] : 0.0;
+          // pivot row (p, r1, r2 | rb) and the row it eliminates (o, o1, o2 | ob):
+          // rows i, i+1 as they are, or swapped when |l_i| > |d_i|
+          const bool sw = fabs(di) < fabs(li);
+          const double p = sw ? li : di, o = sw ? di : li;
+          const double r1 = sw ? dn : ui, r2 = sw ? un : 0.0, rb = sw ? bn : bi;
+          const double o1 = sw ? ui : dn, o2 = sw ? 0.0 : un, ob = sw ? bi : bn;
+          const double rp = svt_rcp(fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p);
+          const double fct = o * rp;
+          dd[i] = rp; du[i] = r1; du2[i] = r2; x[i] = rb;
+          di = o1 - fct * r1;
+          ui = o2 - fct * r2;
+          bi = ob - fct * rb;
         }
         dd[N - 1] = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
         x[N - 1] = bi;
-        // back substitution in place
-        x[N - 1] = x[N - 1] * dd[N - 1];
-        if (N > 1) x[N - 2] = (x[N - 2] - du[N - 2] * x[N - 1]) * dd[N - 2];
-        for (int i = N - 3; i >= 0; --i)
-          x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) * dd[i];
+        // back substitution in place, the last two values in registers
+        double x1 = bi * dd[N - 1], x2 = 0.0;
+        x[N - 1] = x1;
+        if (N > 1) {
+          x2 = x1;
+          x1 = (x[N - 2] - du[N - 2] * x2) * dd[N - 2];
+          x[N - 2] = x1;
+        }
+#pragma unroll 4
+        for (int i = N - 3; i >= 0; --i) {
+          const double xi = (x[i] - du[i] * x1 - du2[i] * x2) * dd[i];
+          x[i] = xi;
+          x2 = x1;
+          x1 = xi;
+        }
       }
       __syncthreads();
       if (wave == 0) {
@@ -1282,12 +1459,12 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
                                        : pv + (int64_t)u * svt_stride(m, n);
             double s = 0.0;
             for (int i = lane; i < N; i += 64) s += y[i] * x[i];
-            s = wave_sum64(s);
+            s = wave_sum_all(s);
             for (int i = lane; i < N; i += 64) x[i] -= s * y[i];
           }
           double s = 0.0;
           for (int i = lane; i < N; i += 64) s += x[i] * x[i];
-          s = wave_sum64(s);
+          s = wave_sum_all(s);
           const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
           for (int i = lane; i < N; i += 64) x[i] *= inv;
         }
@@ -1301,49 +1478,70 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
     }
     __syncthreads();
   }
-  // ---- 4. U = Q_L D_L u, one wave per value; lane l holds rows l, l+64, l+128
+  // ---- 4. U = Q_L D_L u, one wave per value (lane l holds rows l, l+64,
+  // l+128); the reflectors are staged through LDS in chunks shared by all waves
   const double floor2 = 1e-30 * fro2_s;
-  for (int v = wave; v < k; v += NW) {
-    const double* z = pv + (int64_t)v * svt_stride(m, n);
-    const bool zero = sig[v] * sig[v] <= floor2;
-    double s = 0.0;
-    for (int i = lane; i < n; i += 64) s += z[2 * i + 1] * z[2 * i + 1];
-    s = wave_sum64(s);
-    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    cplx uc[3];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int i = lane + 64 * t;
-      uc[t] = cplx{0.0, 0.0};
-      if (i < n && !zero) uc[t] = cplx{pL[i].re * z[2 * i + 1] * inv, pL[i].im * z[2 * i + 1] * inv};
-    }
-    for (int j = n - 1; j >= 0; --j) {
-      const double tau = tauL[j];
-      if (tau == 0.0) continue;
-      const cplx* vj = W + (int64_t)j * mp;
-      cplx a[3];
-      double wr = 0.0, wi = 0.0;
+  constexpr int CH = 32;                                // reflectors per chunk
+  static_assert(CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 1), "chunk fits");
+  cplx* chunk = reinterpret_cast<cplx*>(iib);           // [c][row], rows 0..mp-1
+  for (int vb = 0; vb < k; vb += NW) {
+    const int v = vb + wave;
+    const bool act = v < k;                             // wave-uniform
+    bool zero = true;
+    cplx uc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    if (act) {
+      const double* z = pv + (int64_t)v * svt_stride(m, n);
+      zero = sig[v] * sig[v] <= floor2;
+      double s = 0.0;
+      for (int i = lane; i < n; i += 64) s += z[2 * i + 1] * z[2 * i + 1];
+      s = wave_sum_all(s);
+      const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const int i = lane + 64 * t;
-        a[t] = (i >= j && i < m) ? vj[i] : cplx{0.0, 0.0};
-        wr += a[t].re * uc[t].re + a[t].im * uc[t].im;
-        wi += a[t].re * uc[t].im - a[t].im * uc[t].re;
+        if (i < n && !zero) uc[t] = cplx{pL[i].re * z[2 * i + 1] * inv, pL[i].im * z[2 * i + 1] * inv};
       }
-      wr = wave_sum64(wr);
-      wi = wave_sum64(wi);
+    }
+    for (int j1 = n; j1 > 0; j1 -= CH) {
+      const int j0 = j1 > CH ? j1 - CH : 0;
+      __syncthreads();                                  // the previous chunk is consumed
+      for (int e = tid; e < (j1 - j0) * mp; e += SVT_THREADS) {
+        const int c = e / mp, i = e - c * mp, j = j0 + c;
+        chunk[e] = (i >= j && i < m) ? W[(int64_t)j * mp + i] : cplx{0.0, 0.0};
+      }
+      __syncthreads();
+      if (act) {
+        for (int j = j1 - 1; j >= j0; --j) {
+          const double tau = tauL[j];
+          if (tau == 0.0) continue;
+          const cplx* vj = chunk + (j - j0) * mp;
+          cplx a[3];
+          double wr = 0.0, wi = 0.0;
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            const int i = lane + 64 * t;
+            a[t] = i < mp ? vj[i] : cplx{0.0, 0.0};
+            wr += a[t].re * uc[t].re + a[t].im * uc[t].im;
+            wi += a[t].re * uc[t].im - a[t].im * uc[t].re;
+          }
+          wr = wave_sum_all(wr);
+          wi = wave_sum_all(wi);
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            uc[t].re -= tau * (a[t].re * wr - a[t].im * wi);
+            uc[t].im -= tau * (a[t].re * wi + a[t].im * wr);
+          }
+        }
+      }
+    }
+    if (act) {
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        uc[t].re -= tau * (a[t].re * wr - a[t].im * wi);
-        uc[t].im -= tau * (a[t].re * wi + a[t].im * wr);
+        const int i = lane + 64 * t;
+        if (i < m) dsc.U[(int64_t)i * k + v] = uc[t];
       }
+      if (lane == 0) dsc.sigma[v] = zero ? 0.0 : sig[v];
     }
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const int i = lane + 64 * t;
-      if (i < m) dsc.U[(int64_t)i * k + v] = uc[t];
-    }
-    if (lane == 0) dsc.sigma[v] = zero ? 0.0 : sig[v];
   }
 }
 

@@ -68,13 +68,13 @@ struct JacobiDesc {
   double* sigma;
   int rows, cols, lda, conjT, keep;
 };
-// k_svd_top takes the same descriptor and writes the same outputs for
-// keep <= cols <= rows <= 144 through Householder bidiagonalisation,
-// bisection on the Golub-Kahan tridiagonal and inverse iteration, with the
-// larger scratch below (the padded working copy, then per value 2 cols + 2
-// rows doubles).
+// k_svt_bidiag followed by k_svd_top take the same descriptor and write the
+// same outputs for keep <= cols <= rows <= 144 through Householder
+// bidiagonalisation, bisection on the Golub-Kahan tridiagonal and inverse
+// iteration, with the larger scratch below (the left reflectors, rows padded
+// to 16; the bidiagonal, 3 cols + 2; per value 2 cols + 2 rows doubles).
 inline int64_t svd_top_work_elems(int64_t rows, int64_t cols, int64_t keep) {
-  return (rows + 15) / 16 * 16 * cols + ((2 * cols + 2 * rows) * keep + 1) / 2 + 16;
+  return (rows + 15) / 16 * 16 * cols + 3 * cols + 2 + ((2 * cols + 2 * rows) * keep + 1) / 2 + 16;
 }
 
 // Random sign sketch: out[i, j] = (+-1 +- 1j)/sqrt(2) from SplitMix64 output
