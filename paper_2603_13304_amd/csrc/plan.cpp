@@ -40,7 +40,7 @@ namespace {
 constexpr int64_t kMergedPeakElems = int64_t(1) << 25;
 // narrowest truncated SVD block that goes through bidiagonalisation instead
 // of one-sided Jacobi (measured crossover on 144-row blocks)
-constexpr int64_t kSvdTopMinCols = 112;
+constexpr int64_t kSvdTopMinCols = 72;
 
 uint64_t mix_out0(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
