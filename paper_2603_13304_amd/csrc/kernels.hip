@@ -1294,9 +1294,10 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   __shared__ cplx dcx[SVT_MAXN], ecx[SVT_MAXN], pL[SVT_MAXN];
   __shared__ double off[2 * SVT_MAXN], b2[2 * SVT_MAXN], sig[SVT_MAXN];
   __shared__ double fro2_s;
-  // inverse iteration: dd, du, du2, x per value; the odd stride keeps the
-  // values' arrays in different LDS banks
-  __shared__ double iib[SVT_BATCH * (4 * 2 * SVT_MAXN + 1)];
+  // inverse iteration: per value and step i the record (1/pivot, u1, u2, x)
+  // at iib[v * pstr + 4 i]; pstr = 4 N + 2 keeps the records 16-byte aligned
+  // and the 16 values' records in different LDS banks
+  __shared__ __align__(16) double iib[SVT_BATCH * (4 * 2 * SVT_MAXN + 2)];
   if (n > SVT_MAXN || m > SVT_MAXN || n > m || k > n || n < 1) return;   // excluded by the plan
   const cplx* W = dsc.work;                            // reflectors, mp x n column-major
   const cplx* bd = dsc.work + svt_bd_off(m, n);
@@ -1326,6 +1327,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   __syncthreads();
   if (tid == 0) {
     cplx q = {1.0, 0.0};
+#pragma unroll 8
     for (int j = 0; j < n; ++j) {
       const cplx d = pL[j];
       const cplx p = off[2 * j] > 0.0 ? cplx{d.re * q.re - d.im * q.im, d.re * q.im + d.im * q.re}
@@ -1385,37 +1387,39 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   const double eps = 2.220446049250313e-16;
   const double tiny = eps * bound;
   const double ortol = 1e-3 * bound;
-  const int pstr = 4 * N + 1;
+  const int pstr = 4 * N + 2;
   for (int v0b = 0; v0b < k; v0b += SVT_BATCH) {
     const int kb = k - v0b < SVT_BATCH ? k - v0b : SVT_BATCH;
     for (int it = 0; it < SVT_ITERS; ++it) {
       if (tid < kb) {
         const int v = v0b + tid;
-        double* dd = iib + (int64_t)tid * pstr;
-        double* du = dd + N;
-        double* du2 = du + N;
-        double* x = du2 + N;
+        double* rec = iib + (int64_t)tid * pstr;
         const double lam = sig[v];
         if (it == 0) {
           // deterministic start vector (golden-ratio sequence)
           for (int i = 0; i < N; ++i) {
             const double fr = double(i + 1) * 0.6180339887498949 + 0.1 * v;
-            x[i] = 0.5 + (fr - floor(fr));
+            rec[4 * i + 3] = 0.5 + (fr - floor(fr));
           }
         }
         // eliminate row i+1 below the pivot row, carrying the right side x;
-        // dd keeps the reciprocal pivots for the back substitution.  The
-        // loads of step i+1 are issued during step i.
-        double di = -lam, ui = N > 1 ? off[0] : 0.0, bi = x[0];
-        double li_n = off[0], un_n = N > 2 ? off[1] : 0.0, bn_n = N > 1 ? x[1] : 0.0;
+        // the record keeps the reciprocal pivot for the back substitution.
+        // The loads of step i+1 are issued during step i (indexes clamped in
+        // range, values past the matrix masked).
+        const int lastoff = 2 * SVT_MAXN - 1;
+        double di = -lam, ui = N > 1 ? off[0] : 0.0, bi = rec[3];
+        double li_n = off[0], un_n = off[1 < lastoff ? 1 : lastoff];
+        double bn_n = rec[4 * (N > 1 ? 1 : 0) + 3];
+#pragma unroll 2
         for (int i = 0; i < N - 1; ++i) {
           const double li = li_n;                          // sub-diagonal (row i+1, col i)
           const double dn = -lam;                          // diagonal of row i+1
-          const double un = un_n;
+          const double un = i + 1 < N - 1 ? un_n : 0.0;
           const double bn = bn_n;
+          const int i2 = i + 2 < N ? i + 2 : N - 1;
           li_n = off[i + 1];
-          un_n = i + 2 < N - 1 ? off[i + 2] : 0.0;
-          bn_n = i + 2 < N ? x[i + 2] : 0.0;
+          un_n = off[i2 < lastoff ? i2 : lastoff];
+          bn_n = rec[4 * i2 + 3];
           // pivot row (p, r1, r2 | rb) and the row it eliminates (o, o1, o2 | ob):
           // rows i, i+1 as they are, or swapped when |l_i| > |d_i|
           const bool sw = fabs(di) < fabs(li);
@@ -1424,25 +1428,22 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           const double o1 = sw ? ui : dn, o2 = sw ? 0.0 : un, ob = sw ? bi : bn;
           const double rp = svt_rcp(fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p);
           const double fct = o * rp;
-          dd[i] = rp; du[i] = r1; du2[i] = r2; x[i] = rb;
+          reinterpret_cast<d2v*>(rec + 4 * i)[0] = d2v{rp, r1};
+          reinterpret_cast<d2v*>(rec + 4 * i)[1] = d2v{r2, rb};
           di = o1 - fct * r1;
           ui = o2 - fct * r2;
           bi = ob - fct * rb;
         }
-        dd[N - 1] = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
-        x[N - 1] = bi;
+        const double rpl = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
         // back substitution in place, the last two values in registers
-        double x1 = bi * dd[N - 1], x2 = 0.0;
-        x[N - 1] = x1;
-        if (N > 1) {
-          x2 = x1;
-          x1 = (x[N - 2] - du[N - 2] * x2) * dd[N - 2];
-          x[N - 2] = x1;
-        }
+        double x1 = bi * rpl, x2 = 0.0;
+        rec[4 * (N - 1) + 3] = x1;
 #pragma unroll 4
-        for (int i = N - 3; i >= 0; --i) {
-          const double xi = (x[i] - du[i] * x1 - du2[i] * x2) * dd[i];
-          x[i] = xi;
+        for (int i = N - 2; i >= 0; --i) {
+          const d2v a = reinterpret_cast<const d2v*>(rec + 4 * i)[0];
+          const d2v b = reinterpret_cast<const d2v*>(rec + 4 * i)[1];
+          const double xi = (b[1] - a[1] * x1 - b[0] * x2) * a[0];
+          rec[4 * i + 3] = xi;
           x2 = x1;
           x1 = xi;
         }
@@ -1451,22 +1452,28 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
       if (wave == 0) {
         for (int vb = 0; vb < kb; ++vb) {
           const int v = v0b + vb;
-          double* x = iib + (int64_t)vb * pstr + 3 * N;
+          double* x = iib + (int64_t)vb * pstr + 3;       // x_i = x[4 i]
           // against earlier close values (finished ones are in the work buffer)
           for (int u = 0; u < v; ++u) {
             if (fabs(sig[u] - sig[v]) >= ortol) continue;
-            const double* y = u >= v0b ? iib + (int64_t)(u - v0b) * pstr + 3 * N
-                                       : pv + (int64_t)u * svt_stride(m, n);
             double s = 0.0;
-            for (int i = lane; i < N; i += 64) s += y[i] * x[i];
-            s = wave_sum_all(s);
-            for (int i = lane; i < N; i += 64) x[i] -= s * y[i];
+            if (u >= v0b) {
+              const double* y = iib + (int64_t)(u - v0b) * pstr + 3;
+              for (int i = lane; i < N; i += 64) s += y[4 * i] * x[4 * i];
+              s = wave_sum_all(s);
+              for (int i = lane; i < N; i += 64) x[4 * i] -= s * y[4 * i];
+            } else {
+              const double* y = pv + (int64_t)u * svt_stride(m, n);
+              for (int i = lane; i < N; i += 64) s += y[i] * x[4 * i];
+              s = wave_sum_all(s);
+              for (int i = lane; i < N; i += 64) x[4 * i] -= s * y[i];
+            }
           }
           double s = 0.0;
-          for (int i = lane; i < N; i += 64) s += x[i] * x[i];
+          for (int i = lane; i < N; i += 64) s += x[4 * i] * x[4 * i];
           s = wave_sum_all(s);
           const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-          for (int i = lane; i < N; i += 64) x[i] *= inv;
+          for (int i = lane; i < N; i += 64) x[4 * i] *= inv;
         }
       }
       __syncthreads();
@@ -1474,7 +1481,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
     // keep the batch's eigenvectors in the work buffer
     for (int e = tid; e < kb * N; e += SVT_THREADS) {
       const int vb = e / N, i = e % N;
-      pv[(int64_t)(v0b + vb) * svt_stride(m, n) + i] = iib[(int64_t)vb * pstr + 3 * N + i];
+      pv[(int64_t)(v0b + vb) * svt_stride(m, n) + i] = iib[(int64_t)vb * pstr + 4 * i + 3];
     }
     __syncthreads();
   }
@@ -1482,7 +1489,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   // l+128); the reflectors are staged through LDS in chunks shared by all waves
   const double floor2 = 1e-30 * fro2_s;
   constexpr int CH = 32;                                // reflectors per chunk
-  static_assert(CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 1), "chunk fits");
+  static_assert(CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 2), "chunk fits");
   cplx* chunk = reinterpret_cast<cplx*>(iib);           // [c][row], rows 0..mp-1
   for (int vb = 0; vb < k; vb += NW) {
     const int v = vb + wave;
