@@ -355,6 +355,8 @@ def profile_sweeps(net, n_sweeps):
         if nl[k]:
             kind, prec = PROFILE_KINDS[k // 3], k % 3
             name = f"{kind}_{PREC_NAMES[prec]}" if kind == "gemm" else kind
+            if kind == "jacobi" and prec == 1:
+                name = "svd_bidiag"
             if kind == "jacobi" and prec == 2:
                 name = "svd_top"
             out[name] = (float(ms[k]), int(nl[k]), float(fl[k]), float(by[k]))

@@ -52,7 +52,8 @@ struct LaunchRec {
   dim3 grid;
   size_t lds = 0;
   int variant = 0;       // kernel variant (QR: 1 = blocked tall kernel; Jacobi: 1 = rows
-                         // split between LDS and the work buffer)
+                         // split between LDS and the work buffer, 2 = top-k SVD through
+                         // bidiagonalisation: k_svt_bidiag then k_svd_top)
   double gemm_flops = 0.0, contraction_flops = 0.0;
   double flops = 0.0;    // algorithmic flops of the launch (8 per complex MAC)
   double bytes = 0.0;    // algorithmic bytes moved (operands read once, results written once)
@@ -438,7 +439,9 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
   }
 }
 
-hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r) {
+// part: -1 every kernel of the record; 0 / 1 only the first / second kernel
+// of a two-kernel record (the top-k SVD), for per-kernel timing
+hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, int part = -1) {
   const void* d = desc_dev + r.desc_off;
   dim3 blk(256);
   switch (r.type) {
@@ -462,8 +465,10 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r) 
       break;
     case OPK_JACOBI:
       if (r.variant == 2) {
-        hipLaunchKernelGGL(k_svt_bidiag, r.grid, dim3(SVB_THREADS), 0, stream, (const JacobiDesc*)d);
-        hipLaunchKernelGGL(k_svd_top, r.grid, dim3(SVT_THREADS), 0, stream, (const JacobiDesc*)d);
+        if (part != 1)
+          hipLaunchKernelGGL(k_svt_bidiag, r.grid, dim3(SVB_THREADS), 0, stream, (const JacobiDesc*)d);
+        if (part != 0)
+          hipLaunchKernelGGL(k_svd_top, r.grid, dim3(SVT_THREADS), 0, stream, (const JacobiDesc*)d);
       }
       else if (r.variant)
         hipLaunchKernelGGL(k_jacobi<true>, r.grid, dim3(JAC_THREADS), r.lds, stream,
@@ -1086,24 +1091,42 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
   std::vector<int64_t> tl(nk, 0);
   for (int s = 0; s < n_sweeps; ++s) {
     Compiled& c = h->sweep[h->parity];
-    std::vector<hipEvent_t> ev(2 * c.launches.size());
+    // three events per record: a two-kernel record (top-k SVD) is timed per
+    // kernel, the bidiagonalisation in slot 10 and the rest in slot 11
+    std::vector<hipEvent_t> ev(3 * c.launches.size());
     for (auto& e : ev) PN_HIP(hipEventCreate(&e));
     h->pinned[0] = double(h->sweeps_total);
     PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
                           hipMemcpyHostToDevice, h->stream));
     for (size_t i = 0; i < c.launches.size(); ++i) {
-      PN_HIP(hipEventRecord(ev[2 * i], h->stream));
-      hipError_t e = launch(h->desc_dev, h->stream, c.launches[i]);
+      const LaunchRec& r = c.launches[i];
+      const bool two = r.type == OPK_JACOBI && r.variant == 2;
+      PN_HIP(hipEventRecord(ev[3 * i], h->stream));
+      hipError_t e = launch(h->desc_dev, h->stream, r, two ? 0 : -1);
       if (e != hipSuccess) return fail(BBP_EDEVICE, hipGetErrorString(e));
-      PN_HIP(hipEventRecord(ev[2 * i + 1], h->stream));
+      PN_HIP(hipEventRecord(ev[3 * i + 1], h->stream));
+      if (two) {
+        e = launch(h->desc_dev, h->stream, r, 1);
+        if (e != hipSuccess) return fail(BBP_EDEVICE, hipGetErrorString(e));
+      }
+      PN_HIP(hipEventRecord(ev[3 * i + 2], h->stream));
     }
     PN_HIP(hipStreamSynchronize(h->stream));
     for (size_t i = 0; i < c.launches.size(); ++i) {
-      float x = 0.0f;
-      PN_HIP(hipEventElapsedTime(&x, ev[2 * i], ev[2 * i + 1]));
+      float x = 0.0f, y = 0.0f;
+      PN_HIP(hipEventElapsedTime(&x, ev[3 * i], ev[3 * i + 1]));
+      PN_HIP(hipEventElapsedTime(&y, ev[3 * i + 1], ev[3 * i + 2]));
       const LaunchRec& r = c.launches[i];
-      int slot = r.type * 3 + (r.type == OPK_GEMM ? r.prec : 0);
-      if (r.type == OPK_JACOBI && r.variant == 2) slot += 2;
+      if (r.type == OPK_JACOBI && r.variant == 2) {
+        tms[10] += x;
+        tl[10] += 1;
+        tfl[10] += r.flops;
+        tby[10] += r.bytes;
+        tms[11] += y;
+        tl[11] += 1;
+        continue;
+      }
+      const int slot = r.type * 3 + (r.type == OPK_GEMM ? r.prec : 0);
       tms[slot] += x;
       tl[slot] += 1;
       tfl[slot] += r.flops;

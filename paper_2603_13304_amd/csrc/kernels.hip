@@ -261,6 +261,15 @@ __device__ __forceinline__ double group16_sum(double v) {
   return v;
 }
 
+// Householder columns whose squared norm is positive but below 1e-200 are
+// rescaled by this power of two (exact) before the reflector is formed:
+// tau = 2 / ||v||^2 would otherwise overflow once ||x||^2 nears the bottom of
+// the double range.  Returns 1 when no rescaling is needed.
+__device__ __forceinline__ double house_rescale(double nx2) {
+  if (!(nx2 > 0.0 && nx2 < 1e-200)) return 1.0;
+  return ldexp(1.0, -ilogb(sqrt(nx2)));
+}
+
 // W and Qt point into LDS (INLDS) or into the work buffer; keeping the two
 // cases apart lets the compiler use ds_read/ds_write for LDS data.
 template <bool INLDS>
@@ -285,7 +294,18 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, doub
     part = wave_sum(part);
     if (lane == 0) part_s[j & 1][wave] = part;
     __syncthreads();
-    const double nx2 = part_s[j & 1][0] + part_s[j & 1][1] + part_s[j & 1][2] + part_s[j & 1][3];
+    double nx2 = part_s[j & 1][0] + part_s[j & 1][1] + part_s[j & 1][2] + part_s[j & 1][3];
+    const double sc = house_rescale(nx2);   // uniform
+    if (sc != 1.0) {
+      for (int i = j + tid; i < m; i += 256) wj[i] = cplx{wj[i].re * sc, wj[i].im * sc};
+      __syncthreads();                        // also: every thread has read nx2
+      part = 0.0;
+      for (int i = j + tid; i < m; i += 256) part += wj[i].re * wj[i].re + wj[i].im * wj[i].im;
+      part = wave_sum(part);
+      if (lane == 0) part_s[j & 1][wave] = part;
+      __syncthreads();
+      nx2 = part_s[j & 1][0] + part_s[j & 1][1] + part_s[j & 1][2] + part_s[j & 1][3];
+    }
     const cplx x0 = wj[j];
     const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
     double tau = 0.0;
@@ -321,7 +341,7 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, doub
     if (tid == 0) {
       double a = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
       phs[j] = a > 0.0 ? cplx{alpha.re / a, alpha.im / a} : cplx{1.0, 0.0};
-      alpha_s[j] = cplx{a, 0.0};
+      alpha_s[j] = cplx{a / sc, 0.0};
     }
     __syncthreads();
     // the reflector's head replaces x0 only after every column used x0
@@ -561,7 +581,15 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qr_tall(const QrDesc* __restric
       cplx* xj = P + j * ldp;
       double part = 0.0;
       for (int i = j + tid; i < mr; i += QRT_THREADS) part += xj[i].re * xj[i].re + xj[i].im * xj[i].im;
-      const double nx2 = qrt_block_sum(part, red);
+      double nx2 = qrt_block_sum(part, red);
+      const double sc = house_rescale(nx2);   // uniform
+      if (sc != 1.0) {
+        for (int i = j + tid; i < mr; i += QRT_THREADS) xj[i] = cplx{xj[i].re * sc, xj[i].im * sc};
+        __syncthreads();
+        part = 0.0;
+        for (int i = j + tid; i < mr; i += QRT_THREADS) part += xj[i].re * xj[i].re + xj[i].im * xj[i].im;
+        nx2 = qrt_block_sum(part, red);
+      }
       const cplx x0 = xj[j];
       const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
       double tau = 0.0;
@@ -596,7 +624,7 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qr_tall(const QrDesc* __restric
         tau_s[p0 + j] = tau;
         const double a = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
         phs[p0 + j] = a > 0.0 ? cplx{alpha.re / a, alpha.im / a} : cplx{1.0, 0.0};
-        alpha_s[p0 + j] = a;
+        alpha_s[p0 + j] = a / sc;
       }
       __syncthreads();
       // the reflector head replaces x0 once every column used x0
@@ -986,12 +1014,15 @@ __device__ __forceinline__ double wave_sum_all(double v) { return rows4_sum(grou
 
 // Householder reflector H = I - tau v v^H with H x = alpha e_0 for the
 // vector x of norm^2 nx2 and head x0: alpha = -phase(x0) |x|, v = x - alpha
-// e_0 (only the head changes); returns the head of v
-__device__ __forceinline__ cplx svt_house(cplx x0, double nx2, double* tau, cplx* alpha) {
+// e_0 (only the head changes); returns the head of v.  A vector with
+// nx2 <= thr is left alone (tau = 0, alpha = x0): its tail is far below the
+// rounding of the factorisation, and 2 / ||v||^2 could overflow.
+__device__ __forceinline__ cplx svt_house(cplx x0, double nx2, double thr, double* tau,
+                                          cplx* alpha) {
   const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
   *tau = 0.0;
-  *alpha = cplx{0.0, 0.0};
-  if (!(nx > 0.0)) return x0;
+  *alpha = x0;
+  if (!(nx2 > thr) || !(nx > 0.0)) return x0;
   const double r = ax0 > 0.0 ? nx / ax0 : 0.0;
   *alpha = ax0 > 0.0 ? cplx{-x0.re * r, -x0.im * r} : cplx{-nx, 0.0};
   const cplx v0 = {x0.re - alpha->re, x0.im - alpha->im};
@@ -1070,11 +1101,11 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
   f = wave_sum_all(f);
   if (lane == 0) red[wave] = f;
   __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < NW; ++w) t += red[w];
-    bd[3 * n] = cplx{t, 0.0};
-  }
+  double fro2 = 0.0;
+  for (int w = 0; w < NW; ++w) fro2 += red[w];
+  if (tid == 0) bd[3 * n] = cplx{fro2, 0.0};
+  // columns and rows below 1e-100 ||A||_F get no reflector
+  const double hthr = 1e-200 * fro2;
   for (int j0 = 0, r = 0; j0 < n; j0 += 16, ++r) {
     const int s = r >> 1;                          // 32-column blocks done
     const int t = s > 1 ? s - 1 : 0;               // register column shifts
@@ -1129,7 +1160,7 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
         const cplx x0 = {__shfl(head.re, src), __shfl(head.im, src)};
         double tau;
         cplx alpha;
-        const cplx v0 = svt_house(x0, nx2, &tau, &alpha);
+        const cplx v0 = svt_house(x0, nx2, hthr, &tau, &alpha);
         if (rl == jj) {
           uL[j] = v0;
           W[(int64_t)j * mp + j] = v0;
@@ -1195,7 +1226,7 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
       const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
       double tau2;
       cplx beta;
-      const cplx u0 = svt_house(yR[j + 1], ny2, &tau2, &beta);
+      const cplx u0 = svt_house(yR[j + 1], ny2, hthr, &tau2, &beta);
       if (tid == 0) bd[n + j] = cplx{beta.re, -beta.im};
       // ---- rows i > j: a -= tau2 (a . v2) conj(v2)
       cplx v2[NS];
@@ -1388,6 +1419,9 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   const double tiny = eps * bound;
   const double ortol = 1e-3 * bound;
   const int pstr = 4 * N + 2;
+  // values at or below the noise floor get zero columns: no vector is solved
+  // for them (their cluster makes the solve singular)
+  const double floor2 = 1e-30 * fro2_s;
   for (int v0b = 0; v0b < k; v0b += SVT_BATCH) {
     const int kb = k - v0b < SVT_BATCH ? k - v0b : SVT_BATCH;
     for (int it = 0; it < SVT_ITERS; ++it) {
@@ -1395,13 +1429,16 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
         const int v = v0b + tid;
         double* rec = iib + (int64_t)tid * pstr;
         const double lam = sig[v];
+        const bool zv = lam * lam <= floor2;
         if (it == 0) {
-          // deterministic start vector (golden-ratio sequence)
+          // deterministic start vector (golden-ratio sequence); zero for a
+          // value under the floor, which then stays zero
           for (int i = 0; i < N; ++i) {
             const double fr = double(i + 1) * 0.6180339887498949 + 0.1 * v;
-            rec[4 * i + 3] = 0.5 + (fr - floor(fr));
+            rec[4 * i + 3] = zv ? 0.0 : 0.5 + (fr - floor(fr));
           }
         }
+        if (!zv) {
         // eliminate row i+1 below the pivot row, carrying the right side x;
         // the record keeps the reciprocal pivot for the back substitution.
         // The loads of step i+1 are issued during step i (indexes clamped in
@@ -1435,17 +1472,27 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           bi = ob - fct * rb;
         }
         const double rpl = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
-        // back substitution in place, the last two values in registers
-        double x1 = bi * rpl, x2 = 0.0;
+        // back substitution in place, the last two values in registers.  Each
+        // tiny pivot multiplies the solution by up to 1/eps: when an entry
+        // passes 1e150 the solution so far is scaled by 1e-150 and the rest
+        // of the right side (sc) with it, so that it cannot overflow
+        double x1 = bi * rpl, x2 = 0.0, sc = 1.0;
         rec[4 * (N - 1) + 3] = x1;
 #pragma unroll 4
         for (int i = N - 2; i >= 0; --i) {
           const d2v a = reinterpret_cast<const d2v*>(rec + 4 * i)[0];
           const d2v b = reinterpret_cast<const d2v*>(rec + 4 * i)[1];
-          const double xi = (b[1] - a[1] * x1 - b[0] * x2) * a[0];
+          double xi = (b[1] * sc - a[1] * x1 - b[0] * x2) * a[0];
+          if (fabs(xi) > 1e150) {
+            for (int q = i + 1; q < N; ++q) rec[4 * q + 3] *= 1e-150;
+            xi *= 1e-150;
+            x1 *= 1e-150;
+            sc *= 1e-150;
+          }
           rec[4 * i + 3] = xi;
           x2 = x1;
           x1 = xi;
+        }
         }
       }
       __syncthreads();
@@ -1487,7 +1534,6 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   }
   // ---- 4. U = Q_L D_L u, one wave per value (lane l holds rows l, l+64,
   // l+128); the reflectors are staged through LDS in chunks shared by all waves
-  const double floor2 = 1e-30 * fro2_s;
   constexpr int CH = 32;                                // reflectors per chunk
   static_assert(CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 2), "chunk fits");
   cplx* chunk = reinterpret_cast<cplx*>(iib);           // [c][row], rows 0..mp-1

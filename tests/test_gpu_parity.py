@@ -95,6 +95,27 @@ def test_hex_n3_cfg2_shape_t1_fp64():
     assert message_diff(g, O, P) < 1e-10
 
 
+def test_hex_n2_t2_chi64_wide_sketch_fp64():
+    """Randomized truncation at chi=64 (sketch width 72, D=3): the 72x72
+    splits keeping 64 values go through the top-k SVD.  One sweep from a
+    seeded generic start (full-rank splits) against the oracle.  From the
+    identity start the splits are rank-deficient: the kept set holds values
+    at the rounding floor, whose free basis a later sketch sees, so those
+    results are not unique and are only required to stay finite (tiny
+    trailing columns once drove the tall QR's reflectors to overflow)."""
+    ts = [t / np.linalg.norm(t) for t in syn.random_unit_cell(3, seed=100)]
+    P, g, O = _run("infinite", ts, 1, randmsg=14, N=2, D=3, chi=64, trunc=1, q=2, p=8, seed=7)
+    assert not bb.GAUGE_AMBIGUOUS
+    assert message_diff(g, O, P) < 1e-10
+    _, desc = problem("infinite", N=2, D=3, chi=64, trunc=1, q=2, p=8, seed=7)
+    g2 = pn.PepsNet(desc, ts)
+    done, err, _ = g2.blockbp_sweep(3, 0.0)
+    assert done == 3 and np.isfinite(err)
+    for msg in g2.get_messages():
+        for a in msg:
+            assert np.all(np.isfinite(a))
+
+
 def test_graph_replay_equals_direct_launches():
     ts = syn.random_unit_cell(2, seed=4)
     P, desc = problem("infinite", N=2, D=2, chi=8)
