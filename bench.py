@@ -298,7 +298,7 @@ def main():
         peak = {"gemm_fp64": PEAKS["fp64_tflops"], "gemm_fp32": PEAKS["fp32_tflops"],
                 "gemm_bf16x3": PEAKS["bf16_tflops"]}[name]
         achieved = kfl / nl / avg_s / 1e12
-    elif name in ("qr", "jacobi", "svd_bidiag", "svd_top"):
+    elif name in ("qr", "qr_tall", "jacobi", "svd_bidiag", "svd_top"):
         bound, unit, peak = "alu", "TFLOP/s", PEAKS["fp64_tflops"]
         achieved = kfl / nl / avg_s / 1e12
     else:

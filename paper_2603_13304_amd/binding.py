@@ -355,6 +355,8 @@ def profile_sweeps(net, n_sweeps):
         if nl[k]:
             kind, prec = PROFILE_KINDS[k // 3], k % 3
             name = f"{kind}_{PREC_NAMES[prec]}" if kind == "gemm" else kind
+            if kind == "qr" and prec == 1:
+                name = "qr_tall"
             if kind == "jacobi" and prec == 1:
                 name = "svd_bidiag"
             if kind == "jacobi" and prec == 2:

@@ -1126,7 +1126,8 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
         tl[11] += 1;
         continue;
       }
-      const int slot = r.type * 3 + (r.type == OPK_GEMM ? r.prec : 0);
+      int slot = r.type * 3 + (r.type == OPK_GEMM ? r.prec : 0);
+      if (r.type == OPK_QR && r.variant) slot += 1;   // blocked tall QR
       tms[slot] += x;
       tl[slot] += 1;
       tfl[slot] += r.flops;

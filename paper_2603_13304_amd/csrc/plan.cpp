@@ -41,6 +41,7 @@ constexpr int64_t kMergedPeakElems = int64_t(1) << 25;
 // narrowest truncated SVD block that goes through bidiagonalisation instead
 // of one-sided Jacobi (measured crossover on 144-row blocks)
 constexpr int64_t kSvdTopMinCols = 72;
+constexpr int64_t kSvdTopWideCols = 112;   // from here also when most columns are kept
 
 uint64_t mix_out0(uint64_t x) {
   uint64_t z = x + 0x9E3779B97F4A7C15ull;
@@ -165,8 +166,11 @@ struct Compiler::Lane {
     Op op;
     op.type = OPK_JACOBI;
     // wide blocks with a truncated rank go through bidiagonalisation: its
-    // cost grows with cols, the Jacobi sweeps' with cols^2 times a sweep count
-    const bool top = keep < cols && cols >= kSvdTopMinCols;
+    // cost grows like cols^3 once plus cols^2 per kept value, the Jacobi
+    // sweeps' like cols^3 per sweep; below 112 columns Jacobi stays ahead
+    // when most columns are kept (72x72 keeping 64: 1.8 against 2.1 ms)
+    const bool top = keep < cols && cols >= kSvdTopMinCols &&
+                     (2 * keep <= cols || cols >= kSvdTopWideCols);
     op.a = A; op.c = U; op.d = sig;
     op.b = scratch(top ? svd_top_work_elems(rows, cols, keep) : jacobi_work_elems(rows, cols));
     op.i[0] = rows; op.i[1] = cols; op.i[2] = lda; op.i[3] = conjT; op.i[4] = keep;

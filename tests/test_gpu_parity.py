@@ -96,13 +96,13 @@ def test_hex_n3_cfg2_shape_t1_fp64():
 
 
 def test_hex_n2_t2_chi64_wide_sketch_fp64():
-    """Randomized truncation at chi=64 (sketch width 72, D=3): the 72x72
-    splits keeping 64 values go through the top-k SVD.  One sweep from a
-    seeded generic start (full-rank splits) against the oracle.  From the
-    identity start the splits are rank-deficient: the kept set holds values
-    at the rounding floor, whose free basis a later sketch sees, so those
-    results are not unique and are only required to stay finite (tiny
-    trailing columns once drove the tall QR's reflectors to overflow)."""
+    """Randomized truncation at chi=64 (sketch width 72, D=3; the 72x72
+    splits keep 64 values).  One sweep from a seeded generic start
+    (full-rank splits) against the oracle.  From the identity start the
+    splits are rank-deficient: the kept set holds values at the rounding
+    floor, whose free basis a later sketch sees, so those results are not
+    unique and are only required to stay finite (columns near 1e-139 once
+    drove the tall QR's reflectors to overflow)."""
     ts = [t / np.linalg.norm(t) for t in syn.random_unit_cell(3, seed=100)]
     P, g, O = _run("infinite", ts, 1, randmsg=14, N=2, D=3, chi=64, trunc=1, q=2, p=8, seed=7)
     assert not bb.GAUGE_AMBIGUOUS
@@ -114,6 +114,16 @@ def test_hex_n2_t2_chi64_wide_sketch_fp64():
     for msg in g2.get_messages():
         for a in msg:
             assert np.all(np.isfinite(a))
+
+
+def test_hex_n3_d2_chi36_t1_many_kept_fp64():
+    """T1 at chi=36 (D=2, simple-update tensors): the 144x144 splits keeping
+    36 values go through the top-k SVD with several inverse-iteration
+    batches and back-transformation passes; one sweep from a seeded generic
+    start."""
+    ts = syn.simple_update_cell(2, seed=2)
+    P, g, O = _run("infinite", ts, 1, randmsg=15, N=3, D=2, chi=36)
+    assert message_diff(g, O, P) < 1e-10
 
 
 def test_graph_replay_equals_direct_launches():
