@@ -51,7 +51,7 @@ struct LaunchRec {
   int count = 0;
   dim3 grid;
   size_t lds = 0;
-  int variant = 0;       // kernel variant (QR: 1 = blocked tall kernel; Jacobi: 1 = rows
+  int variant = 0;       // kernel variant (QR: 1 = blocked tall kernel, 2 = k_qr_small; Jacobi: 1 = rows
                          // split between LDS and the work buffer, 2 = top-k SVD through
                          // bidiagonalisation: k_svt_bidiag then k_svd_top)
   double gemm_flops = 0.0, contraction_flops = 0.0;
@@ -179,6 +179,7 @@ size_t push_descs(std::vector<char>* blob, const std::vector<T>& v) {
 int op_variant(const Op& op) {
   if (op.type == OPK_QR) {
     const int64_t m = op.i[0], n = op.i[1], k = std::min(m, n);
+    if (m <= QRS_MAXM && n <= QRS_MAXN) return 2;   // k_qr_small
     return m * (n + (op.c.valid() ? k : 0)) <= QR_LDS_MAX ? 0 : 1;
   }
   if (op.type == OPK_JACOBI) {
@@ -303,8 +304,10 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
           }
           rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(v.size()));
-          // blocked kernel (panel in LDS) for working copies that overflow LDS
-          rec.lds = rec.variant ? size_t(QRT_LDS) * sizeof(cplx) : size_t(lds_elems) * sizeof(cplx);
+          // blocked kernel (panel in LDS) for working copies that overflow LDS;
+          // k_qr_small uses static LDS only
+          rec.lds = rec.variant == 1 ? size_t(QRT_LDS) * sizeof(cplx)
+                  : rec.variant == 2 ? 0 : size_t(lds_elems) * sizeof(cplx);
           break;
         }
         case OPK_JACOBI: {
@@ -457,7 +460,9 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
       hipLaunchKernelGGL(k_permute, r.grid, blk, 0, stream, (const PermDesc*)d);
       break;
     case OPK_QR:
-      if (r.variant)
+      if (r.variant == 2)
+        hipLaunchKernelGGL(k_qr_small, r.grid, dim3(256), 0, stream, (const QrDesc*)d);
+      else if (r.variant)
         hipLaunchKernelGGL(k_qr_tall, r.grid, dim3(QRT_THREADS), r.lds, stream,
                            (const QrDesc*)d);
       else
@@ -1127,7 +1132,7 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
         continue;
       }
       int slot = r.type * 3 + (r.type == OPK_GEMM ? r.prec : 0);
-      if (r.type == OPK_QR && r.variant) slot += 1;   // blocked tall QR
+      if (r.type == OPK_QR && r.variant == 1) slot += 1;   // blocked tall QR
       tms[slot] += x;
       tl[slot] += 1;
       tfl[slot] += r.flops;

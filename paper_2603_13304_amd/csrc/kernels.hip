@@ -410,6 +410,147 @@ __global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
     qr_body<false>(d, d.work, d.work + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
 }
 
+// QR of a block with n <= 16 columns and m <= 144 rows (the reflectors,
+// phases and outputs of k_qr): 16-lane group g holds column g in registers
+// (rows lane + 16 t).  Step j: group j forms the reflector with DPP sums and
+// stores it in LDS, one barrier, every later group applies it to its column
+// with a 16-lane DPP dot product.  The reflectors stay in LDS, so forming Q
+// (group c applies H_{k-1} .. H_0 to e_c) needs no barrier at all.
+constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
+__global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ descs) {
+  const QrDesc d = descs[blockIdx.x];
+  const int m = d.m, n = d.n, k = m < n ? m : n;
+  if (m > QRS_MAXM || n > QRS_MAXN) return;            // excluded by the plan compiler
+  const int tid = threadIdx.x, g = tid >> 4, gl = tid & 15, lane = tid & 63;
+  __shared__ cplx V[QRS_MAXN][QRS_MAXM];
+  __shared__ double tau_s[QRS_MAXN];
+  __shared__ cplx phs[QRS_MAXN], alpha_s[QRS_MAXN];
+  cplx a[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int r = gl + 16 * t;
+    const bool ok = r < m && g < n;
+    const int64_t o = !ok ? 0 : d.conjT ? (int64_t)g * d.lda + r : (int64_t)r * d.lda + g;
+    cplx v = d.A[o];
+    if (d.conjT) v.im = -v.im;
+    a[t] = ok ? v : cplx{0.0, 0.0};
+  }
+  for (int j = 0; j < k; ++j) {
+    if (g == j) {
+      double part = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t)
+        if (gl + 16 * t >= j) part += a[t].re * a[t].re + a[t].im * a[t].im;
+      double nx2 = group16_sum(part);
+      const double sc = house_rescale(nx2);          // uniform within the group
+      if (sc != 1.0) {
+        part = 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+          if (gl + 16 * t >= j) {
+            a[t] = cplx{a[t].re * sc, a[t].im * sc};
+            part += a[t].re * a[t].re + a[t].im * a[t].im;
+          }
+        nx2 = group16_sum(part);
+      }
+      cplx mine = a[0];
+#pragma unroll
+      for (int t = 1; t < 9; ++t)
+        if (t == (j >> 4)) mine = a[t];
+      const int src = (lane & 48) | (j & 15);
+      const cplx x0 = {__shfl(mine.re, src), __shfl(mine.im, src)};
+      const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
+      double tau = 0.0;
+      cplx alpha = {0.0, 0.0}, v0 = x0;
+      if (nx > 0.0) {
+        const cplx ph = ax0 > 0.0 ? cplx{x0.re / ax0, x0.im / ax0} : cplx{1.0, 0.0};
+        alpha = cplx{-ph.re * nx, -ph.im * nx};
+        v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
+        const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
+        tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int r = gl + 16 * t;
+        if (r < QRS_MAXM) V[j][r] = r < j ? cplx{0.0, 0.0} : r == j ? v0 : a[t];
+      }
+      if (gl == 0) {
+        tau_s[j] = tau;
+        const double aa = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
+        phs[j] = aa > 0.0 ? cplx{alpha.re / aa, alpha.im / aa} : cplx{1.0, 0.0};
+        alpha_s[j] = cplx{aa / sc, 0.0};
+      }
+    }
+    __syncthreads();
+    const double tau = tau_s[j];
+    if (g > j && g < n && tau != 0.0) {
+      double wr = 0.0, wi = 0.0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const cplx v = V[j][gl + 16 * t];                   // zero above row j
+        wr += v.re * a[t].re + v.im * a[t].im;
+        wi += v.re * a[t].im - v.im * a[t].re;
+      }
+      wr = group16_sum(wr);
+      wi = group16_sum(wi);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const cplx v = V[j][gl + 16 * t];
+        a[t].re -= tau * (v.re * wr - v.im * wi);
+        a[t].im -= tau * (v.re * wi + v.im * wr);
+      }
+    }
+  }
+  __syncthreads();
+  // R (k x n) with the canonical gauge: diag real non-negative, row r times
+  // conj(phase_r); group g writes column g
+  if (g < n) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int r = gl + 16 * t;
+      if (r >= k) continue;
+      cplx x = {0.0, 0.0};
+      if (r == g) {
+        x = alpha_s[r];
+      } else if (r < g) {
+        const cplx ph = phs[r];
+        x = cplx{a[t].re * ph.re + a[t].im * ph.im, a[t].im * ph.re - a[t].re * ph.im};
+      }
+      d.R[(int64_t)r * n + g] = x;
+    }
+  }
+  if (d.Q == nullptr || g >= k) return;
+  // Q = H_0 ... H_{k-1} [I; 0] times the phases, column g
+  cplx q[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) q[t] = cplx{gl + 16 * t == g ? 1.0 : 0.0, 0.0};
+  for (int j = g; j >= 0; --j) {
+    const double tau = tau_s[j];
+    if (tau == 0.0) continue;
+    double wr = 0.0, wi = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const cplx v = V[j][gl + 16 * t];
+      wr += v.re * q[t].re + v.im * q[t].im;
+      wi += v.re * q[t].im - v.im * q[t].re;
+    }
+    wr = group16_sum(wr);
+    wi = group16_sum(wi);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const cplx v = V[j][gl + 16 * t];
+      q[t].re -= tau * (v.re * wr - v.im * wi);
+      q[t].im -= tau * (v.re * wi + v.im * wr);
+    }
+  }
+  const cplx ph = phs[g];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int r = gl + 16 * t;
+    if (r < m) d.Q[(int64_t)r * k + g] = cplx{q[t].re * ph.re - q[t].im * ph.im, q[t].re * ph.im + q[t].im * ph.re};
+  }
+}
+
 // --------------------------------------------------------------- tall QR
 // Blocked Householder QR for matrices whose working copy does not fit in LDS
 // (same reflectors, phases and outputs as k_qr).  Panels of pb <= 8 columns
