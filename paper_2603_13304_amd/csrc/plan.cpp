@@ -77,6 +77,11 @@ struct Compiler::Lane {
   LaneOps* out;
   int64_t chain_top = 0, scratch_top = 0, scratch_max = 0;
   int stage = 0, step = 0, phase = 0, counter = 0;
+  // launch keys: within a stage the lanes are independent, so each lane's
+  // ops are keyed by (stage, SVDs emitted so far in the stage, index since
+  // the last SVD) and every SVD by (stage, its index): the k-th truncated
+  // SVDs of all lanes share one launch, whatever their swallow schedules
+  int key_stage = -1, svd_seq = 0, seg_idx = 0;
   std::string err;
 
   Lane(Compiler* c, int lane, LaneOps* o) : C(c), id(lane), out(o) {}
@@ -100,8 +105,19 @@ struct Compiler::Lane {
     stage = st; step = sp; phase = ph;
   }
   void push(const Op& op) {
+    if (stage != key_stage) {
+      key_stage = stage;
+      svd_seq = 0;
+      seg_idx = 0;
+    }
     WaveKey k;
-    k.k = {stage, step, phase, counter++};
+    if (op.type == OPK_JACOBI) {
+      k.k = {stage, svd_seq++, 1 << 30};
+      seg_idx = 0;
+    } else {
+      k.k = {stage, svd_seq, seg_idx++};
+    }
+    ++counter;
     out->ops.push_back({k, op});
   }
 

@@ -3,8 +3,11 @@
 // complete sweep -- canonical moves, merges, double-layer absorption,
 // truncated splits, normalisation, message finalisation and the convergence
 // distance -- is compiled once into lists of device operations.  Independent
-// message updates ("lanes") are interleaved in lockstep "waves" so that one
-// kernel launch serves every lane at the same stage.
+// message updates ("lanes") are interleaved in "waves" so that one kernel
+// launch serves the same operation of every lane: the k-th truncated SVD of
+// each lane (the costly, latency-bound step) shares a launch with the k-th of
+// every other lane, and the operations between two SVDs are matched by their
+// position since the last one.
 #pragma once
 #include <cstdint>
 #include <map>
