@@ -1189,6 +1189,221 @@ __host__ __device__ inline int64_t svt_pv_off(int64_t rows, int64_t cols) {
   return svt_bd_off(rows, cols) + 3 * cols + 2;
 }
 
+// One block of 16 bidiagonalisation steps (steps j0 .. j0+15) after r row
+// shifts, with NA = nt - r live row slots: every row-slot loop has a
+// compile-time bound (the slots past the matrix are zero and skipped).
+struct SvbCtx {
+  cplx *W, *bd, *xl, *xa, *xp, *uL, *yR, *xs;
+  double *red, *tau_s;
+  int m, n, mp, tid, lane, wave, rl, cg, q4;
+  bool has4;
+  double hthr;
+};
+constexpr int SVB_NW = SVB_THREADS / 64, SVB_NS = 5;
+constexpr int SVB_NR = SVT_MAXN + 16 * 8;   // row index range of the shifted slots
+
+template <int NA>
+__device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int j0, int r) {
+  constexpr int NW = SVB_NW, NS = SVB_NS, NR = SVB_NR;
+  cplx* const W = c.W;
+  cplx* const bd = c.bd;
+  cplx* const xl = c.xl;
+  cplx* const xa = c.xa;
+  cplx* const xp = c.xp;
+  cplx* const uL = c.uL;
+  cplx* const yR = c.yR;
+  cplx* const xs = c.xs;
+  double* const red = c.red;
+  double* const tau_s = c.tau_s;
+  const int m = c.m, n = c.n, mp = c.mp, tid = c.tid, lane = c.lane, wave = c.wave;
+  const int rl = c.rl, cg = c.cg, q4 = c.q4;
+  const bool has4 = c.has4;
+  const double hthr = c.hthr;
+    const int s = r >> 1;                          // 32-column blocks done
+    const int t = s > 1 ? s - 1 : 0;               // register column shifts
+    const int rb = rl + 16 * r;                    // row of row slot a: rb + 16 a
+    // slot b: 0 = LDS columns g, 1..3 = A[.][b-1], 4 = LDS columns g + 128
+    auto col = [&](int b) { return b == 0 ? cg : b < 4 ? cg + 32 * (b + t) : cg + 128; };
+    auto live = [&](int b) {
+      return b == 0 ? s == 0 : b < 4 ? (b + t <= 3 || (b + t == 4 && has4)) : (t == 0 && has4);
+    };
+    // LDS element of row slot a (index clamped in range for every lane;
+    // padded row slots read 0)
+    auto lds_at = [&](const cplx* base, int gmask, int a) -> cplx {
+      cplx x = base[(cg & gmask) * SVT_MAXN + (a + r < 9 ? rb + 16 * a : 0)];
+      if (a + r >= 9) x = cplx{0.0, 0.0};
+      return x;
+    };
+    auto get = [&](int a, int b) -> cplx {
+      if (b == 0) return lds_at(xl, 31, a);
+      if (b == 4) return lds_at(xa, 15, a);
+      cplx x = A[a][0];
+      if (b == 2) x = A[a][1];
+      if (b == 3) x = A[a][2];
+      return x;
+    };
+    auto put = [&](int a, int b, cplx x) {
+      if (b == 0) { if (a + r < 9) xl[cg * SVT_MAXN + rb + 16 * a] = x; }
+      else if (b == 4) { if (a + r < 9) xa[cg * SVT_MAXN + rb + 16 * a] = x; }
+      else if (b == 1) A[a][0] = x;
+      else if (b == 2) A[a][1] = x;
+      else A[a][2] = x;
+    };
+    const int jend = j0 + 16 < n ? j0 + 16 : n;
+    for (int j = j0; j < jend; ++j) {
+      const int jj = j - j0;                       // row j: row slot 0 of lane rl == jj
+      const int bj = s == 0 ? 0 : 1;               // column slot of column j
+      // ---- left reflector from column j (lanes cg == j % 32), rows j..m-1
+      if (cg == (j & 31)) {
+        double part = 0.0;
+        cplx head = {0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const int i = rb + 16 * a;
+          cplx v = bj == 0 ? lds_at(xl, 31, a) : A[a][0];
+          if (a == 0) head = v;
+          if (i < j || i >= m) v = cplx{0.0, 0.0};
+          uL[i] = v;
+          if (i > j && i < m) W[(int64_t)j * mp + i] = v;
+          part = fma(v.re, v.re, fma(v.im, v.im, part));
+        }
+        const double nx2 = group16_sum(part);
+        const int src = (lane & 48) | jj;
+        const cplx x0 = {__shfl(head.re, src), __shfl(head.im, src)};
+        double tau;
+        cplx alpha;
+        const cplx v0 = svt_house(x0, nx2, hthr, &tau, &alpha);
+        if (rl == jj) {
+          uL[j] = v0;
+          W[(int64_t)j * mp + j] = v0;
+        }
+        if (rl == 0) {
+          *tau_s = tau;
+          bd[j] = alpha;
+          bd[2 * n + j] = cplx{tau, 0.0};
+        }
+      }
+      __syncthreads();
+      // ---- trailing columns c > j: a -= tau u (u^H a)
+      const double tau = *tau_s;
+      if (tau != 0.0) {
+        cplx u[9];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) u[a] = uL[rb + 16 * a];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          if (!live(b)) continue;                  // scalar
+          cplx x[9];
+          double wr = 0.0, wi = 0.0;
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            x[a] = get(a, b);
+            wr = fma(u[a].re, x[a].re, fma(u[a].im, x[a].im, wr));
+            wi = fma(u[a].re, x[a].im, fma(-u[a].im, x[a].re, wi));
+          }
+          wr = group16_sum(wr);
+          wi = group16_sum(wi);
+          const bool cl = col(b) > j;              // this lane's column is trailing
+          wr = cl ? tau * wr : 0.0;
+          wi = cl ? tau * wi : 0.0;
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            x[a].re = fma(-u[a].re, wr, fma(u[a].im, wi, x[a].re));
+            x[a].im = fma(-u[a].re, wi, fma(-u[a].im, wr, x[a].im));
+            put(a, b, x[a]);
+          }
+        }
+      }
+      if (j == n - 1) break;
+      // ---- right reflector from row j (row slot 0 of lane rl == jj), columns
+      // j+1..: y = conj(row) into yR, its norm summed per wave
+      {
+        double part = 0.0;
+        if (rl == jj) {
+#pragma unroll
+          for (int b = 0; b < NS; ++b) {
+            if (!live(b)) continue;
+            const int c = col(b);
+            const cplx x = get(0, b);
+            cplx y = {0.0, 0.0};
+            if (c > j && c < n) y = cplx{x.re, -x.im};
+            yR[c] = y;
+            part = fma(y.re, y.re, fma(y.im, y.im, part));
+          }
+        }
+        part = rows4_sum(part);
+        if (lane == jj) red[wave] = part;
+      }
+      __syncthreads();
+      const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
+      double tau2;
+      cplx beta;
+      const cplx u0 = svt_house(yR[j + 1], ny2, hthr, &tau2, &beta);
+      if (tid == 0) bd[n + j] = cplx{beta.re, -beta.im};
+      // ---- rows i > j: a -= tau2 (a . v2) conj(v2)
+      cplx v2[NS];
+      if (tau2 != 0.0) {
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          const int c = col(b);
+          v2[b] = cplx{0.0, 0.0};
+          if (live(b) && c > j + 1) v2[b] = yR[c];
+          if (c == j + 1) v2[b] = u0;
+        }
+        double xr[9], xi[9];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) xr[a] = xi[a] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          if (!live(b)) continue;                  // scalar
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            const cplx x = get(a, b);
+            xr[a] = fma(x.re, v2[b].re, fma(-x.im, v2[b].im, xr[a]));
+            xi[a] = fma(x.re, v2[b].im, fma(x.im, v2[b].re, xi[a]));
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const double sr = rows4_sum(xr[a]), si = rows4_sum(xi[a]);
+          if (q4 == 0) xp[wave * NR + rb + 16 * a] = cplx{sr, si};
+        }
+      }
+      __syncthreads();
+      if (tau2 != 0.0 && tid < mp && tid > j) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const cplx p = xp[w * NR + tid];
+          sr += p.re;
+          si += p.im;
+        }
+        xs[tid] = cplx{tau2 * sr, tau2 * si};
+      }
+      __syncthreads();
+      if (tau2 != 0.0) {
+        cplx x[9];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const int i = rb + 16 * a;
+          x[a] = xs[i];
+          if (i <= j || i >= mp) x[a] = cplx{0.0, 0.0};
+        }
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          if (!live(b)) continue;
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            cplx y = get(a, b);
+            y.re = fma(-x[a].re, v2[b].re, fma(-x[a].im, v2[b].im, y.re));   // x conj(v2)
+            y.im = fma(-x[a].im, v2[b].re, fma(x[a].re, v2[b].im, y.im));
+            put(a, b, y);
+          }
+        }
+      }
+    }
+}
+
 __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __restrict__ descs) {
   const JacobiDesc dsc = descs[blockIdx.x];
   const int m = dsc.rows, n = dsc.cols, k = dsc.keep;
@@ -1247,191 +1462,13 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
   if (tid == 0) bd[3 * n] = cplx{fro2, 0.0};
   // columns and rows below 1e-100 ||A||_F get no reflector
   const double hthr = 1e-200 * fro2;
-  for (int j0 = 0, r = 0; j0 < n; j0 += 16, ++r) {
-    const int s = r >> 1;                          // 32-column blocks done
-    const int t = s > 1 ? s - 1 : 0;               // register column shifts
-    const int rb = rl + 16 * r;                    // row of row slot a: rb + 16 a
-    // slot b: 0 = LDS columns g, 1..3 = A[.][b-1], 4 = LDS columns g + 128
-    auto col = [&](int b) { return b == 0 ? cg : b < 4 ? cg + 32 * (b + t) : cg + 128; };
-    auto live = [&](int b) {
-      return b == 0 ? s == 0 : b < 4 ? (b + t <= 3 || (b + t == 4 && has4)) : (t == 0 && has4);
-    };
-    // LDS element of row slot a (index clamped in range for every lane;
-    // padded row slots read 0)
-    auto lds_at = [&](const cplx* base, int gmask, int a) -> cplx {
-      cplx x = base[(cg & gmask) * SVT_MAXN + (a + r < 9 ? rb + 16 * a : 0)];
-      if (a + r >= 9) x = cplx{0.0, 0.0};
-      return x;
-    };
-    auto get = [&](int a, int b) -> cplx {
-      if (b == 0) return lds_at(xl, 31, a);
-      if (b == 4) return lds_at(xa, 15, a);
-      cplx x = A[a][0];
-      if (b == 2) x = A[a][1];
-      if (b == 3) x = A[a][2];
-      return x;
-    };
-    auto put = [&](int a, int b, cplx x) {
-      if (b == 0) { if (a + r < 9) xl[cg * SVT_MAXN + rb + 16 * a] = x; }
-      else if (b == 4) { if (a + r < 9) xa[cg * SVT_MAXN + rb + 16 * a] = x; }
-      else if (b == 1) A[a][0] = x;
-      else if (b == 2) A[a][1] = x;
-      else A[a][2] = x;
-    };
-    const int jend = j0 + 16 < n ? j0 + 16 : n;
-    for (int j = j0; j < jend; ++j) {
-      const int jj = j - j0;                       // row j: row slot 0 of lane rl == jj
-      const int bj = s == 0 ? 0 : 1;               // column slot of column j
-      // ---- left reflector from column j (lanes cg == j % 32), rows j..m-1
-      if (cg == (j & 31)) {
-        double part = 0.0;
-        cplx head = {0.0, 0.0};
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-          const int i = rb + 16 * a;
-          cplx v = bj == 0 ? lds_at(xl, 31, a) : A[a][0];
-          if (a == 0) head = v;
-          if (i < j || i >= m) v = cplx{0.0, 0.0};
-          uL[i] = v;
-          if (i > j && i < m) W[(int64_t)j * mp + i] = v;
-          part = fma(v.re, v.re, fma(v.im, v.im, part));
-        }
-        const double nx2 = group16_sum(part);
-        const int src = (lane & 48) | jj;
-        const cplx x0 = {__shfl(head.re, src), __shfl(head.im, src)};
-        double tau;
-        cplx alpha;
-        const cplx v0 = svt_house(x0, nx2, hthr, &tau, &alpha);
-        if (rl == jj) {
-          uL[j] = v0;
-          W[(int64_t)j * mp + j] = v0;
-        }
-        if (rl == 0) {
-          tau_s = tau;
-          bd[j] = alpha;
-          bd[2 * n + j] = cplx{tau, 0.0};
-        }
-      }
-      __syncthreads();
-      // ---- trailing columns c > j: a -= tau u (u^H a)
-      const double tau = tau_s;
-      if (tau != 0.0) {
-        cplx u[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) u[a] = uL[rb + 16 * a];
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-          if (!live(b)) continue;                  // scalar
-          cplx x[9];
-          double wr = 0.0, wi = 0.0;
-#pragma unroll
-          for (int a = 0; a < 9; ++a) {
-            x[a] = get(a, b);
-            wr = fma(u[a].re, x[a].re, fma(u[a].im, x[a].im, wr));
-            wi = fma(u[a].re, x[a].im, fma(-u[a].im, x[a].re, wi));
-          }
-          wr = group16_sum(wr);
-          wi = group16_sum(wi);
-          const bool cl = col(b) > j;              // this lane's column is trailing
-          wr = cl ? tau * wr : 0.0;
-          wi = cl ? tau * wi : 0.0;
-#pragma unroll
-          for (int a = 0; a < 9; ++a) {
-            x[a].re = fma(-u[a].re, wr, fma(u[a].im, wi, x[a].re));
-            x[a].im = fma(-u[a].re, wi, fma(-u[a].im, wr, x[a].im));
-            put(a, b, x[a]);
-          }
-        }
-      }
-      if (j == n - 1) break;
-      // ---- right reflector from row j (row slot 0 of lane rl == jj), columns
-      // j+1..: y = conj(row) into yR, its norm summed per wave
-      {
-        double part = 0.0;
-        if (rl == jj) {
-#pragma unroll
-          for (int b = 0; b < NS; ++b) {
-            if (!live(b)) continue;
-            const int c = col(b);
-            const cplx x = get(0, b);
-            cplx y = {0.0, 0.0};
-            if (c > j && c < n) y = cplx{x.re, -x.im};
-            yR[c] = y;
-            part = fma(y.re, y.re, fma(y.im, y.im, part));
-          }
-        }
-        part = rows4_sum(part);
-        if (lane == jj) red[wave] = part;
-      }
-      __syncthreads();
-      const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
-      double tau2;
-      cplx beta;
-      const cplx u0 = svt_house(yR[j + 1], ny2, hthr, &tau2, &beta);
-      if (tid == 0) bd[n + j] = cplx{beta.re, -beta.im};
-      // ---- rows i > j: a -= tau2 (a . v2) conj(v2)
-      cplx v2[NS];
-      if (tau2 != 0.0) {
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-          const int c = col(b);
-          v2[b] = cplx{0.0, 0.0};
-          if (live(b) && c > j + 1) v2[b] = yR[c];
-          if (c == j + 1) v2[b] = u0;
-        }
-        double xr[9], xi[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) xr[a] = xi[a] = 0.0;
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-          if (!live(b)) continue;                  // scalar
-#pragma unroll
-          for (int a = 0; a < 9; ++a) {
-            const cplx x = get(a, b);
-            xr[a] = fma(x.re, v2[b].re, fma(-x.im, v2[b].im, xr[a]));
-            xi[a] = fma(x.re, v2[b].im, fma(x.im, v2[b].re, xi[a]));
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-          const double sr = rows4_sum(xr[a]), si = rows4_sum(xi[a]);
-          if (q4 == 0) xp[wave * NR + rb + 16 * a] = cplx{sr, si};
-        }
-      }
-      __syncthreads();
-      if (tau2 != 0.0 && tid < mp && tid > j) {
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const cplx p = xp[w * NR + tid];
-          sr += p.re;
-          si += p.im;
-        }
-        xs[tid] = cplx{tau2 * sr, tau2 * si};
-      }
-      __syncthreads();
-      if (tau2 != 0.0) {
-        cplx x[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) {
-          const int i = rb + 16 * a;
-          x[a] = xs[i];
-          if (i <= j || i >= mp) x[a] = cplx{0.0, 0.0};
-        }
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-          if (!live(b)) continue;
-#pragma unroll
-          for (int a = 0; a < 9; ++a) {
-            cplx y = get(a, b);
-            y.re = fma(-x[a].re, v2[b].re, fma(-x[a].im, v2[b].im, y.re));   // x conj(v2)
-            y.im = fma(-x[a].im, v2[b].re, fma(x[a].re, v2[b].im, y.im));
-            put(a, b, y);
-          }
-        }
-      }
-    }
-    if (j0 + 16 >= n) break;
+  const SvbCtx ctx{W, bd, xl, xa, xp, uL, yR, xs, red, &tau_s, m, n, mp, tid, lane, wave,
+                   rl, cg, q4, has4, hthr};
+  // blocks of 16 steps with nt, nt-1, .. 1 live row slots, in sequence (a
+  // loop or a switch over the templates would merge the register tile from
+  // many paths); a block's templates for more slots than nt are skipped
+  int j0 = 0, r = 0;
+  auto block_shift = [&]() {
     // drop the finished row slot; from the block at step 64 on, every other
     // block also the finished register column slot (column g + 128 moving in
     // from LDS the first time)
@@ -1441,18 +1478,28 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
       for (int a = 0; a < 8; ++a) A[a][q] = A[a + 1][q];
       A[8][q] = cplx{0.0, 0.0};
     }
-    const int s1 = (r + 1) >> 1;
+    const int s = r >> 1, s1 = (r + 1) >> 1;
     if (s1 != s && s1 >= 2) {
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
         A[a][0] = A[a][1];
         A[a][1] = A[a][2];
-        const int ra = a + r + 1;                  // row slot index after the row shift
+        const int ra = a + r + 1;                    // row slot index after the row shift
         const cplx x = xa[(cg & 15) * SVT_MAXN + (ra < 9 ? rl + 16 * ra : 0)];
         A[a][2] = (s1 == 2 && has4 && ra < 9) ? x : cplx{0.0, 0.0};
       }
     }
+  };
+#define SVB_BLOCK(NAV)                                  \
+  if (nt >= NAV && j0 < n) {                            \
+    svb_block<NAV>(A, ctx, j0, r);                      \
+    if (j0 + 16 < n) block_shift();                     \
+    j0 += 16;                                           \
+    ++r;                                                \
   }
+  SVB_BLOCK(9) SVB_BLOCK(8) SVB_BLOCK(7) SVB_BLOCK(6) SVB_BLOCK(5)
+  SVB_BLOCK(4) SVB_BLOCK(3) SVB_BLOCK(2) SVB_BLOCK(1)
+#undef SVB_BLOCK
 }
 
 // Stages 2-4 on the bidiagonal and reflectors written by k_svt_bidiag.
