@@ -1512,7 +1512,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   __shared__ double tauL[SVT_MAXN];
   __shared__ cplx dcx[SVT_MAXN], ecx[SVT_MAXN], pL[SVT_MAXN];
   __shared__ double off[2 * SVT_MAXN], b2[2 * SVT_MAXN], sig[SVT_MAXN];
-  __shared__ double fro2_s;
+  __shared__ double fro2_s, bmax[NW];
   // inverse iteration: per value and step i the record (1/pivot, u1, u2, x)
   // at iib[v * pstr + 4 i]; pstr = 4 N + 2 keeps the records 16-byte aligned
   // and the 16 values' records in different LDS banks
@@ -1544,29 +1544,65 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    cplx q = {1.0, 0.0};
-#pragma unroll 8
-    for (int j = 0; j < n; ++j) {
-      const cplx d = pL[j];
-      const cplx p = off[2 * j] > 0.0 ? cplx{d.re * q.re - d.im * q.im, d.re * q.im + d.im * q.re}
-                                      : cplx{1.0, 0.0};
+  // the running phases by a scan over one wave: step j maps q_j to q_{j+1} =
+  // A_j q_j + B_j with A = ph(d_j) conj(ph(e_j)), B = 0 when both are nonzero,
+  // A = 0, B = conj(ph(e_j)) when d_j = 0, and A = 0, B = 1 when e_j = 0;
+  // lane l composes steps 3l .. 3l+2, the lanes' maps are scanned, and each
+  // lane then walks its own steps from q_{3l}
+  if (wave == 0) {
+    auto mul = [](cplx a, cplx b) { return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; };
+    cplx A = {1.0, 0.0}, B = {0.0, 0.0};
+    for (int t = 0; t < 3; ++t) {
+      const int j = 3 * lane + t;
+      if (j >= n - 1) break;
+      const cplx pe = {ecx[j].re, -ecx[j].im};
+      cplx a = {0.0, 0.0}, b = {1.0, 0.0};
+      if (off[2 * j + 1] > 0.0) {
+        if (off[2 * j] > 0.0) {
+          a = mul(pL[j], pe);
+          b = cplx{0.0, 0.0};
+        } else {
+          b = pe;
+        }
+      }
+      const cplx aB = mul(a, B);
+      B = cplx{aB.re + b.re, aB.im + b.im};
+      A = mul(a, A);
+    }
+    for (int o = 1; o < 64; o <<= 1) {   // inclusive scan, later lanes applied last
+      const cplx Ao = {__shfl_up(A.re, o), __shfl_up(A.im, o)};
+      const cplx Bo = {__shfl_up(B.re, o), __shfl_up(B.im, o)};
+      if (lane >= o) {
+        const cplx aB = mul(A, Bo);
+        B = cplx{aB.re + B.re, aB.im + B.im};
+        A = mul(A, Ao);
+      }
+    }
+    cplx q = {__shfl_up(A.re, 1) + __shfl_up(B.re, 1), __shfl_up(A.im, 1) + __shfl_up(B.im, 1)};
+    if (lane == 0) q = cplx{1.0, 0.0};
+    for (int t = 0; t < 3; ++t) {
+      const int j = 3 * lane + t;
+      if (j >= n) break;
+      const cplx p = off[2 * j] > 0.0 ? mul(pL[j], q) : cplx{1.0, 0.0};
       pL[j] = p;
       if (j < n - 1) {
-        const cplx e = ecx[j];
-        q = off[2 * j + 1] > 0.0 ? cplx{p.re * e.re + p.im * e.im, p.im * e.re - p.re * e.im}
-                                 : cplx{1.0, 0.0};
+        const cplx pe = {ecx[j].re, -ecx[j].im};
+        q = off[2 * j + 1] > 0.0 ? mul(p, pe) : cplx{1.0, 0.0};
       }
     }
   }
-  __syncthreads();
-  for (int i = tid; i < N - 1; i += SVT_THREADS) b2[i] = off[i] * off[i];
+  // squared off-diagonal and the Gershgorin bound max_i (off_{i-1} + off_i)
+  double bl = 0.0;
+  for (int i = tid; i < N; i += SVT_THREADS) {
+    if (i < N - 1) b2[i] = off[i] * off[i];
+    const double l = i > 0 ? off[i - 1] : 0.0, r = i < N - 1 ? off[i] : 0.0;
+    bl = fmax(bl, l + r);
+  }
+  for (int o = 32; o > 0; o >>= 1) bl = fmax(bl, __shfl_xor(bl, o));
+  if (lane == 0) bmax[wave] = bl;
   __syncthreads();
   double bound = 0.0;
-  for (int i = 0; i < N; ++i) {
-    const double l = i > 0 ? off[i - 1] : 0.0, r = i < N - 1 ? off[i] : 0.0;
-    bound = fmax(bound, l + r);
-  }
+  for (int w = 0; w < NW; ++w) bound = fmax(bound, bmax[w]);
   bound = bound * (1.0 + 1e-14) + 1e-300;
   const double pivmin = fmax(2.2250738585072014e-308, 1e-300 * bound * bound);
   // ---- 2. multisection: 16 shifts (lanes) per value, 4 values per wave on
