@@ -1092,11 +1092,12 @@ template __global__ void k_jacobi<true>(const JacobiDesc*);
 //   2. the singular values of B' are the positive eigenvalues of the
 //      Golub-Kahan tridiagonal T (zero diagonal, off-diagonal d_0, e_0,
 //      d_1, ...): each of the k largest is found by multisection on Sturm
-//      counts, 64 shifts per step (one per lane of a wave);
+//      counts, 16 shifts per step (one per lane of a 16-lane group);
 //   3. inverse iteration on T - sigma I (Gaussian elimination with partial
-//      pivoting fused with the forward solve, tiny pivots raised to
-//      eps ||T||), eigenvectors of close values re-orthogonalised; the odd
-//      entries of the eigenvector are the left singular vector u of B';
+//      pivoting, once; tiny pivots raised to eps ||T||; then a forward and a
+//      back substitution per step), eigenvectors of close values
+//      re-orthogonalised; the odd entries of the eigenvector are the left
+//      singular vector u of B';
 //   4. U = Q_L D_L u through the stored reflectors.
 // Singular values at or below 1e-15 ||A||_F give zero columns, as k_jacobi.
 // Step 1 is its own kernel (k_svt_bidiag, the matrix held on chip); steps 2-4
@@ -1114,7 +1115,8 @@ __host__ __device__ inline int64_t svt_stride(int64_t rows, int64_t cols) {
 }
 
 // 1/q from the hardware estimate and two Newton steps (full precision for
-// |q| >= pivmin; cheaper than the IEEE division in the recurrences below)
+// the pivots of the scaled matrix, |q| >= eps; cheaper than the IEEE
+// division in the elimination below)
 __device__ __forceinline__ double svt_rcp(double q) {
   double r = __builtin_amdgcn_rcp(q);
   r = fma(r, fma(-q, r, 1.0), r);
@@ -1122,15 +1124,44 @@ __device__ __forceinline__ double svt_rcp(double q) {
   return r;
 }
 
-// number of eigenvalues below x of the symmetric tridiagonal with zero
-// diagonal and squared off-diagonal b2[0 .. N-2]
-__device__ int svt_count(const double* b2, int N, double x, double pivmin) {
-  double q = -x;
-  int cnt = q < 0.0;
-  for (int i = 0; i < N - 1; ++i) {
-    if (fabs(q) < pivmin) q = -pivmin;
-    q = -x - b2[i] * svt_rcp(q);
-    cnt += q < 0.0;
+// number of eigenvalues below x of the symmetric tridiagonal T with zero
+// diagonal and squared off-diagonal c2[0 .. N-2], scaled by a power of two so
+// that ||T|| < 2, with c2 >= 2^-300 and x >= 2^-64 (changes far below the
+// noise floor).  Sturm: the leading minors p_i of T - x I (p_0 = 1, p_1 = -x,
+// p_{i+2} = -x p_{i+1} - c2[i] p_i) change sign once per eigenvalue below x.
+// A step rounds as the pivot recurrence q_{i+1} = p_{i+1} / p_i does (one
+// relative error on c2[i] q_i^-1 and one on the sum), without its division;
+// a zero minor counts by its sign bit and the next step settles the pair.
+// Every four steps both minors are scaled by the power of two that brings the
+// newer one into [1/2, 1) (the older one when the newer is zero): no sign or
+// rounding changes, and over four steps the magnitudes stay within 2^+-500.
+__device__ __forceinline__ int svt_count(const double* c2, int N, double x) {
+  double P = 1.0, Q = -x;
+  int cnt = 1;
+  auto step = [&](double c) {
+    const double R = fma(-x, Q, -(c * P));
+    cnt += int((unsigned(__double2hiint(R)) ^ unsigned(__double2hiint(Q))) >> 31);
+    P = Q;
+    Q = R;
+  };
+  int i = 0;
+  for (const int r = (N - 1) & 3; i < r; ++i) step(c2[i]);
+  // the next group's coefficients are loaded during the current group
+  double a0 = c2[i], a1 = c2[i + 1], a2 = c2[i + 2], a3 = c2[i + 3];
+  for (; i < N - 1; i += 4) {
+    const int nx = i + 4 < N - 1 ? i + 4 : i;
+    const double n0 = c2[nx], n1 = c2[nx + 1], n2 = c2[nx + 2], n3 = c2[nx + 3];
+    step(a0);
+    step(a1);
+    step(a2);
+    step(a3);
+    const int e = __builtin_amdgcn_frexp_exp(Q != 0.0 ? Q : P);
+    Q = ldexp(Q, -e);
+    P = ldexp(P, -e);
+    a0 = n0;
+    a1 = n1;
+    a2 = n2;
+    a3 = n3;
   }
   return cnt;
 }
@@ -1591,10 +1622,11 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
       }
     }
   }
-  // squared off-diagonal and the Gershgorin bound max_i (off_{i-1} + off_i)
+  // the Gershgorin bound max_i (off_{i-1} + off_i); then off is scaled in
+  // place by the power of two 2^-bexp that brings the bound into [1, 2)
+  // (exact: counts and eigenvectors are those of the unscaled matrix)
   double bl = 0.0;
   for (int i = tid; i < N; i += SVT_THREADS) {
-    if (i < N - 1) b2[i] = off[i] * off[i];
     const double l = i > 0 ? off[i - 1] : 0.0, r = i < N - 1 ? off[i] : 0.0;
     bl = fmax(bl, l + r);
   }
@@ -1604,7 +1636,14 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   double bound = 0.0;
   for (int w = 0; w < NW; ++w) bound = fmax(bound, bmax[w]);
   bound = bound * (1.0 + 1e-14) + 1e-300;
-  const double pivmin = fmax(2.2250738585072014e-308, 1e-300 * bound * bound);
+  const int bexp = ilogb(bound);
+  const double bs = ldexp(bound, -bexp);
+  for (int i = tid; i < N; i += SVT_THREADS) {
+    const double o = i < N - 1 ? ldexp(off[i], -bexp) : 0.0;   // off[N-1] = 0 pads
+    off[i] = o;
+    b2[i] = fmax(o * o, 0x1p-300);
+  }
+  __syncthreads();
   // ---- 2. multisection: 16 shifts (lanes) per value, 4 values per wave on
   // waves 0..3 (one per SIMD: each count is a dependent chain)
   {
@@ -1613,10 +1652,10 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
       if (wave < 4 && v0 + 4 * wave < k) {
         const int v = v0 + 4 * wave + g16;
         const int target = N - 1 - (v < k ? v : k - 1);   // ascending index of the value
-        double lo = 0.0, hi = bound;
+        double lo = 0.0, hi = bs;
         for (int it = 0; it < 96; ++it) {
           const double x = lo + (hi - lo) * double(gl + 1) / 17.0;
-          const int c = svt_count(b2, N, x, pivmin);
+          const int c = svt_count(b2, N, fmax(x, 0x1p-64));
           const unsigned long long above = __ballot(c > target);
           const unsigned ag = unsigned(above >> (16 * g16)) & 0xFFFFu;
           const int first = ag ? __ffs(ag) - 1 : 16;
@@ -1628,19 +1667,21 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           // ulp can exceed 2.2e-16 |x| just above a power of two, so a 1-ulp
           // test would never end there), or below 1e-18 ||T|| (values under
           // the noise floor of 1e-15 ||A||_F are returned as zero anyway)
-          const bool done = (hi - lo) <= 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-18 * bound;
+          const bool done = (hi - lo) <= 4.5e-16 * fmax(fabs(lo), fabs(hi)) + 1e-18 * bs;
           if (__ballot(!done) == 0) break;
         }
-        if (gl == 0 && v < k) sig[v] = 0.5 * (lo + hi);
+        if (gl == 0 && v < k) sig[v] = ldexp(0.5 * (lo + hi), bexp);
       }
     }
   }
   __syncthreads();
-  // ---- 3. inverse iteration: one thread per value solves (T - sigma I) x = b
-  // in LDS (elimination with partial pivoting fused with the forward solve),
-  // then wave 0 normalises and re-orthogonalises close values in order
+  // ---- 3. inverse iteration on the scaled matrix, one thread per value:
+  // T - sigma I = P L U by elimination with partial pivoting (once), then per
+  // step a forward and a back substitution in LDS.  Wave w normalises value w
+  // of the batch; a value with a close predecessor is re-orthogonalised
+  // against the earlier close values in order (wave 0) and normalised there.
   const double eps = 2.220446049250313e-16;
-  const double tiny = eps * bound;
+  const double tiny = eps * bs;
   const double ortol = 1e-3 * bound;
   const int pstr = 4 * N + 2;
   // values at or below the noise floor get zero columns: no vector is solved
@@ -1648,82 +1689,121 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   const double floor2 = 1e-30 * fro2_s;
   for (int v0b = 0; v0b < k; v0b += SVT_BATCH) {
     const int kb = k - v0b < SVT_BATCH ? k - v0b : SVT_BATCH;
-    for (int it = 0; it < SVT_ITERS; ++it) {
-      if (tid < kb) {
-        const int v = v0b + tid;
-        double* rec = iib + (int64_t)tid * pstr;
-        const double lam = sig[v];
-        const bool zv = lam * lam <= floor2;
-        if (it == 0) {
-          // deterministic start vector (golden-ratio sequence); zero for a
-          // value under the floor, which then stays zero
-          for (int i = 0; i < N; ++i) {
-            const double fr = double(i + 1) * 0.6180339887498949 + 0.1 * v;
-            rec[4 * i + 3] = zv ? 0.0 : 0.5 + (fr - floor(fr));
-          }
-        }
-        if (!zv) {
-        // eliminate row i+1 below the pivot row, carrying the right side x;
-        // the record keeps the reciprocal pivot for the back substitution.
-        // The loads of step i+1 are issued during step i (indexes clamped in
-        // range, values past the matrix masked).
-        const int lastoff = 2 * SVT_MAXN - 1;
-        double di = -lam, ui = N > 1 ? off[0] : 0.0, bi = rec[3];
-        double li_n = off[0], un_n = off[1 < lastoff ? 1 : lastoff];
-        double bn_n = rec[4 * (N > 1 ? 1 : 0) + 3];
-#pragma unroll 2
+    bool zv = true;
+    if (tid < kb) {
+      const int v = v0b + tid;
+      double* rec = iib + (int64_t)tid * pstr;
+      const double lam = sig[v];
+      zv = lam * lam <= floor2;
+      // deterministic start vector (golden-ratio sequence); zero for a value
+      // under the floor, which then stays zero
+      for (int i = 0; i < N; ++i) {
+        const double fr = double(i + 1) * 0.6180339887498949 + 0.1 * v;
+        rec[4 * i + 3] = zv ? 0.0 : 0.5 + (fr - floor(fr));
+      }
+      if (!zv) {
+        // step i pivots on row i or i+1 (the larger entry in column i); record
+        // i keeps 1/pivot, the pivot row's entry in column i+1 (its entry in
+        // column i+2 is off[i+1] after a swap, else zero) and the multiplier,
+        // whose last bit is replaced by the swap flag (a change within its
+        // rounding, used in every solve)
+        const double ls = ldexp(lam, -bexp);
+        double di = -ls, ui = off[0], li = off[0];
+#pragma unroll 4
         for (int i = 0; i < N - 1; ++i) {
-          const double li = li_n;                          // sub-diagonal (row i+1, col i)
-          const double dn = -lam;                          // diagonal of row i+1
-          const double un = i + 1 < N - 1 ? un_n : 0.0;
-          const double bn = bn_n;
-          const int i2 = i + 2 < N ? i + 2 : N - 1;
-          li_n = off[i + 1];
-          un_n = off[i2 < lastoff ? i2 : lastoff];
-          bn_n = rec[4 * i2 + 3];
-          // pivot row (p, r1, r2 | rb) and the row it eliminates (o, o1, o2 | ob):
-          // rows i, i+1 as they are, or swapped when |l_i| > |d_i|
+          const double un = off[i + 1];                  // zero past the end
           const bool sw = fabs(di) < fabs(li);
           const double p = sw ? li : di, o = sw ? di : li;
-          const double r1 = sw ? dn : ui, r2 = sw ? un : 0.0, rb = sw ? bn : bi;
-          const double o1 = sw ? ui : dn, o2 = sw ? 0.0 : un, ob = sw ? bi : bn;
+          const double r1 = sw ? -ls : ui, o1 = sw ? ui : -ls;
           const double rp = svt_rcp(fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p);
-          const double fct = o * rp;
+          const double f0 = o * rp;
+          const double fct = __hiloint2double(__double2hiint(f0), (__double2loint(f0) & ~1) | int(sw));
           reinterpret_cast<d2v*>(rec + 4 * i)[0] = d2v{rp, r1};
-          reinterpret_cast<d2v*>(rec + 4 * i)[1] = d2v{r2, rb};
+          rec[4 * i + 2] = fct;
           di = o1 - fct * r1;
-          ui = o2 - fct * r2;
+          ui = sw ? -fct * un : un;
+          li = un;
+        }
+        rec[4 * (N - 1)] = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
+      }
+    }
+    for (int it = 0; it < SVT_ITERS; ++it) {
+      if (tid < kb && !zv) {
+        double* rec = iib + (int64_t)tid * pstr;
+        // forward: the right side (slot 3) through the swaps and multipliers
+        double bi = rec[3];
+#pragma unroll 4
+        for (int i = 0; i < N - 1; ++i) {
+          const double fct = rec[4 * i + 2];
+          const bool sw = __double2loint(fct) & 1;
+          const double bn = rec[4 * i + 7];
+          const double rb = sw ? bn : bi, ob = sw ? bi : bn;
+          rec[4 * i + 3] = rb;
           bi = ob - fct * rb;
         }
-        const double rpl = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
-        // back substitution in place, the last two values in registers.  Each
-        // tiny pivot multiplies the solution by up to 1/eps: when an entry
-        // passes 1e150 the solution so far is scaled by 1e-150 and the rest
-        // of the right side (sc) with it, so that it cannot overflow
-        double x1 = bi * rpl, x2 = 0.0, sc = 1.0;
+        // back substitution in place, the last two values in registers.  A
+        // tiny pivot can multiply the solution by up to 1/eps: after every
+        // block of steps (at most 8, far too few to overflow from 2^500) the
+        // solution so far and the rest of the right side (sc) are scaled by
+        // 2^-500 while the carried values exceed 2^500
+        double x1 = bi * rec[4 * (N - 1)], x2 = 0.0, sc = 1.0;
         rec[4 * (N - 1) + 3] = x1;
-#pragma unroll 4
-        for (int i = N - 2; i >= 0; --i) {
+        auto bstep = [&](int i) {
           const d2v a = reinterpret_cast<const d2v*>(rec + 4 * i)[0];
           const d2v b = reinterpret_cast<const d2v*>(rec + 4 * i)[1];
-          double xi = (b[1] * sc - a[1] * x1 - b[0] * x2) * a[0];
-          if (fabs(xi) > 1e150) {
-            for (int q = i + 1; q < N; ++q) rec[4 * q + 3] *= 1e-150;
-            xi *= 1e-150;
-            x1 *= 1e-150;
-            sc *= 1e-150;
-          }
+          const double o = off[i + 1];
+          const int msk = -(__double2loint(b[0]) & 1);   // all ones after a swap
+          const double r2 = __hiloint2double(__double2hiint(o) & msk, __double2loint(o) & msk);
+          const double xi = (b[1] * sc - a[1] * x1 - r2 * x2) * a[0];
           rec[4 * i + 3] = xi;
           x2 = x1;
           x1 = xi;
+        };
+        auto rescale = [&](int i0) {     // entries i0 .. N-1 are stored
+          for (int t = 0; t < 3 && (fabs(x1) > 0x1p500 || fabs(x2) > 0x1p500); ++t) {
+            for (int q = i0; q < N; ++q) rec[4 * q + 3] *= 0x1p-500;
+            x1 *= 0x1p-500;
+            x2 *= 0x1p-500;
+            sc *= 0x1p-500;
+          }
+        };
+        int i = N - 2;
+        for (const int r = (N - 1) & 7; i > N - 2 - r; --i) bstep(i);
+        rescale(i + 1);
+        for (; i >= 0; i -= 8) {
+          bstep(i);
+          bstep(i - 1);
+          bstep(i - 2);
+          bstep(i - 3);
+          bstep(i - 4);
+          bstep(i - 5);
+          bstep(i - 6);
+          bstep(i - 7);
+          rescale(i - 7);
         }
+      }
+      __syncthreads();
+      if (wave < kb) {
+        const int v = v0b + wave;
+        bool cl = false;
+        for (int u = lane; u < v; u += 64) cl |= fabs(sig[u] - sig[v]) < ortol;
+        if (__ballot(cl) == 0) {
+          double* x = iib + (int64_t)wave * pstr + 3;     // x_i = x[4 i]
+          double s = 0.0;
+          for (int i = lane; i < N; i += 64) s += x[4 * i] * x[4 * i];
+          s = wave_sum_all(s);
+          const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+          for (int i = lane; i < N; i += 64) x[4 * i] *= inv;
         }
       }
       __syncthreads();
       if (wave == 0) {
         for (int vb = 0; vb < kb; ++vb) {
           const int v = v0b + vb;
-          double* x = iib + (int64_t)vb * pstr + 3;       // x_i = x[4 i]
+          bool cl = false;
+          for (int u = lane; u < v; u += 64) cl |= fabs(sig[u] - sig[v]) < ortol;
+          if (__ballot(cl) == 0) continue;
+          double* x = iib + (int64_t)vb * pstr + 3;
           // against earlier close values (finished ones are in the work buffer)
           for (int u = 0; u < v; ++u) {
             if (fabs(sig[u] - sig[v]) >= ortol) continue;
@@ -1756,26 +1836,35 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
     }
     __syncthreads();
   }
-  // ---- 4. U = Q_L D_L u, one wave per value (lane l holds rows l, l+64,
-  // l+128); the reflectors are staged through LDS in chunks shared by all waves
+  // ---- 4. U = Q_L D_L u: 16 lanes per value (lane r of the group holds rows
+  // r + 16 t, t < nt), four values per wave; the reflectors are staged
+  // through LDS in chunks shared by all waves
   constexpr int CH = 32;                                // reflectors per chunk
   static_assert(CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 2), "chunk fits");
   cplx* chunk = reinterpret_cast<cplx*>(iib);           // [c][row], rows 0..mp-1
-  for (int vb = 0; vb < k; vb += NW) {
-    const int v = vb + wave;
-    const bool act = v < k;                             // wave-uniform
+  const int g16 = lane >> 4, rl = lane & 15;
+  for (int vb = 0; vb < k; vb += 4 * NW) {
+    const int v = vb + 4 * wave + g16;
+    const bool act = vb + 4 * wave < k;                 // wave-uniform
+    const bool mine = v < k;                            // uniform in the 16-lane group
     bool zero = true;
-    cplx uc[3] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
-    if (act) {
+    cplx uc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) uc[t] = cplx{0.0, 0.0};
+    if (act && mine) {
       const double* z = pv + (int64_t)v * svt_stride(m, n);
       zero = sig[v] * sig[v] <= floor2;
       double s = 0.0;
-      for (int i = lane; i < n; i += 64) s += z[2 * i + 1] * z[2 * i + 1];
-      s = wave_sum_all(s);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int i = rl + 16 * t;
+        if (i < n) s += z[2 * i + 1] * z[2 * i + 1];
+      }
+      s = group16_sum(s);
       const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int i = lane + 64 * t;
+      for (int t = 0; t < 9; ++t) {
+        const int i = rl + 16 * t;
         if (i < n && !zero) uc[t] = cplx{pL[i].re * z[2 * i + 1] * inv, pL[i].im * z[2 * i + 1] * inv};
       }
     }
@@ -1792,32 +1881,31 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           const double tau = tauL[j];
           if (tau == 0.0) continue;
           const cplx* vj = chunk + (j - j0) * mp;
-          cplx a[3];
+          cplx a[9];
           double wr = 0.0, wi = 0.0;
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            const int i = lane + 64 * t;
-            a[t] = i < mp ? vj[i] : cplx{0.0, 0.0};
+          for (int t = 0; t < 9; ++t) {
+            a[t] = t < nt ? vj[rl + 16 * t] : cplx{0.0, 0.0};
             wr += a[t].re * uc[t].re + a[t].im * uc[t].im;
             wi += a[t].re * uc[t].im - a[t].im * uc[t].re;
           }
-          wr = wave_sum_all(wr);
-          wi = wave_sum_all(wi);
+          wr = tau * group16_sum(wr);
+          wi = tau * group16_sum(wi);
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
-            uc[t].re -= tau * (a[t].re * wr - a[t].im * wi);
-            uc[t].im -= tau * (a[t].re * wi + a[t].im * wr);
+          for (int t = 0; t < 9; ++t) {
+            uc[t].re -= a[t].re * wr - a[t].im * wi;
+            uc[t].im -= a[t].re * wi + a[t].im * wr;
           }
         }
       }
     }
-    if (act) {
+    if (act && mine) {
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int i = lane + 64 * t;
+      for (int t = 0; t < 9; ++t) {
+        const int i = rl + 16 * t;
         if (i < m) dsc.U[(int64_t)i * k + v] = uc[t];
       }
-      if (lane == 0) dsc.sigma[v] = zero ? 0.0 : sig[v];
+      if (rl == 0) dsc.sigma[v] = zero ? 0.0 : sig[v];
     }
   }
 }
