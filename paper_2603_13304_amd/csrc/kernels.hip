@@ -245,11 +245,13 @@ constexpr int QR_LDS_MAX = 8192;   // complex elements (128 KB)
 
 // Sum over the 16 lanes of a DPP row, result in every lane: xor-1 and xor-2
 // quad permutations, then half-row and row mirrors (VALU moves, no LDS).
+// Every lane reads a valid source lane under these controls, so the moves
+// need no old value.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 
@@ -1730,34 +1732,44 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
     for (int it = 0; it < SVT_ITERS; ++it) {
       if (tid < kb && !zv) {
         double* rec = iib + (int64_t)tid * pstr;
+        // Both solves run in blocks of 8 steps: the block's records are read
+        // first, the dependent chain runs in registers, the results are
+        // stored last (LDS reads and writes complete in order, so a store
+        // between two reads would make the wait for the later read cover it).
         // forward: the right side (slot 3) through the swaps and multipliers
         double bi = rec[3];
-#pragma unroll 4
-        for (int i = 0; i < N - 1; ++i) {
-          const double fct = rec[4 * i + 2];
+        auto fstep = [&](double fct, double bn) {
           const bool sw = __double2loint(fct) & 1;
-          const double bn = rec[4 * i + 7];
           const double rb = sw ? bn : bi, ob = sw ? bi : bn;
-          rec[4 * i + 3] = rb;
           bi = ob - fct * rb;
+          return rb;
+        };
+        int i = 0;
+        for (const int r = (N - 1) & 7; i < r; ++i) rec[4 * i + 3] = fstep(rec[4 * i + 2], rec[4 * i + 7]);
+        for (; i < N - 1; i += 8) {
+          d2v fb[9];                                     // (multiplier, b) of steps i .. i+8
+#pragma unroll
+          for (int t = 0; t < 9; ++t) fb[t] = reinterpret_cast<const d2v*>(rec + 4 * (i + t) + 2)[0];
+          double rb[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) rb[t] = fstep(fb[t][0], fb[t + 1][1]);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) rec[4 * (i + t) + 3] = rb[t];
         }
         // back substitution in place, the last two values in registers.  A
         // tiny pivot can multiply the solution by up to 1/eps: after every
-        // block of steps (at most 8, far too few to overflow from 2^500) the
+        // block (at most 8 steps, far too few to overflow from 2^500) the
         // solution so far and the rest of the right side (sc) are scaled by
         // 2^-500 while the carried values exceed 2^500
         double x1 = bi * rec[4 * (N - 1)], x2 = 0.0, sc = 1.0;
         rec[4 * (N - 1) + 3] = x1;
-        auto bstep = [&](int i) {
-          const d2v a = reinterpret_cast<const d2v*>(rec + 4 * i)[0];
-          const d2v b = reinterpret_cast<const d2v*>(rec + 4 * i)[1];
-          const double o = off[i + 1];
+        auto bstep = [&](d2v a, d2v b, double o) {
           const int msk = -(__double2loint(b[0]) & 1);   // all ones after a swap
           const double r2 = __hiloint2double(__double2hiint(o) & msk, __double2loint(o) & msk);
           const double xi = (b[1] * sc - a[1] * x1 - r2 * x2) * a[0];
-          rec[4 * i + 3] = xi;
           x2 = x1;
           x1 = xi;
+          return xi;
         };
         auto rescale = [&](int i0) {     // entries i0 .. N-1 are stored
           for (int t = 0; t < 3 && (fabs(x1) > 0x1p500 || fabs(x2) > 0x1p500); ++t) {
@@ -1767,18 +1779,27 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
             sc *= 0x1p-500;
           }
         };
-        int i = N - 2;
-        for (const int r = (N - 1) & 7; i > N - 2 - r; --i) bstep(i);
+        i = N - 2;
+        for (const int r = (N - 1) & 7; i > N - 2 - r; --i) {
+          const d2v* ri = reinterpret_cast<const d2v*>(rec + 4 * i);
+          rec[4 * i + 3] = bstep(ri[0], ri[1], off[i + 1]);
+        }
         rescale(i + 1);
         for (; i >= 0; i -= 8) {
-          bstep(i);
-          bstep(i - 1);
-          bstep(i - 2);
-          bstep(i - 3);
-          bstep(i - 4);
-          bstep(i - 5);
-          bstep(i - 6);
-          bstep(i - 7);
+          d2v a[8], b[8];
+          double o[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const d2v* ri = reinterpret_cast<const d2v*>(rec + 4 * (i - t));
+            a[t] = ri[0];
+            b[t] = ri[1];
+            o[t] = off[i - t + 1];
+          }
+          double xs[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) xs[t] = bstep(a[t], b[t], o[t]);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) rec[4 * (i - t) + 3] = xs[t];
           rescale(i - 7);
         }
       }
@@ -1882,19 +1903,25 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           if (tau == 0.0) continue;
           const cplx* vj = chunk + (j - j0) * mp;
           cplx a[9];
-          double wr = 0.0, wi = 0.0;
+          double wr0 = 0.0, wi0 = 0.0, wr1 = 0.0, wi1 = 0.0;   // v^H u, even and odd slots
 #pragma unroll
           for (int t = 0; t < 9; ++t) {
             a[t] = t < nt ? vj[rl + 16 * t] : cplx{0.0, 0.0};
-            wr += a[t].re * uc[t].re + a[t].im * uc[t].im;
-            wi += a[t].re * uc[t].im - a[t].im * uc[t].re;
+            double& wr = t & 1 ? wr1 : wr0;
+            double& wi = t & 1 ? wi1 : wi0;
+            wr = fma(a[t].re, uc[t].re, wr);
+            wr = fma(a[t].im, uc[t].im, wr);
+            wi = fma(a[t].re, uc[t].im, wi);
+            wi = fma(-a[t].im, uc[t].re, wi);
           }
-          wr = tau * group16_sum(wr);
-          wi = tau * group16_sum(wi);
+          const double wr = tau * group16_sum(wr0 + wr1);
+          const double wi = tau * group16_sum(wi0 + wi1);
 #pragma unroll
           for (int t = 0; t < 9; ++t) {
-            uc[t].re -= a[t].re * wr - a[t].im * wi;
-            uc[t].im -= a[t].re * wi + a[t].im * wr;
+            uc[t].re = fma(-a[t].re, wr, uc[t].re);
+            uc[t].re = fma(a[t].im, wi, uc[t].re);
+            uc[t].im = fma(-a[t].re, wi, uc[t].im);
+            uc[t].im = fma(-a[t].im, wr, uc[t].im);
           }
         }
       }
