@@ -29,11 +29,29 @@
 
 namespace pn {
 
+// Descriptor pointers are generic, and accesses through generic pointers
+// compile to FLAT instructions, which count against the LDS wait counter as
+// well as the memory one: every wait for an LDS result would then also wait
+// for outstanding global loads and stores.  Kernels that mix the two convert
+// their device-memory pointers to global ones first.
+// (The host pass only parses device code; it keeps plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;
+#endif
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ cplx ld_op(const cplx* X, int ld, int op, int r, int c) {
+__device__ __forceinline__ cplx ld_op(gptr<const cplx> X, int ld, int op, int r, int c) {
   if (op == OP_N) return X[(int64_t)r * ld + c];
   cplx v = X[(int64_t)c * ld + r];
   if (op == OP_C) v.im = -v.im;
@@ -66,6 +84,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   const GemmDesc g = descs[blockIdx.z];
   const int n0 = blockIdx.x * GT_N;
   if (n0 >= g.N) return;
+  const gptr<const cplx> Ag = to_global(g.A), Bg = to_global(g.B);
+  const gptr<cplx> Cg = to_global(g.C);
   __shared__ T As_r[TK][GT_M + PAD], As_i[TK][GT_M + PAD];
   __shared__ T Bs_r[TK][GT_N + PAD], Bs_i[TK][GT_N + PAD];
   // M tiles are grid-strided (the grid's y extent is capped at 65535)
@@ -79,25 +99,51 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
       accr[i][j] = acc_t{0, 0, 0, 0};
       acci[i][j] = acc_t{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < g.K; k0 += TK) {
-    // stage op(A)[m0:m0+64, k0:k0+TK] and op(B)[k0:k0+TK, n0:n0+64]
-    for (int e = tid; e < GT_M * TK; e += 256) {
+  // op(A)[m0:m0+64, k0:k0+TK] and op(B)[k0:k0+TK, n0:n0+64] pass through
+  // registers: with 16-deep slices the next one is loaded while the current
+  // one is used (the 32-deep split-BF16 slices would need too many registers)
+  constexpr int EA = GT_M * TK / 256, EB = GT_N * TK / 256;
+  constexpr bool PF = TK == 16;
+  cplx pa[EA], pb[EB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
+      const int e = tid + 256 * q;
       int mm, kk;
       if (g.opA == OP_N) { mm = e / TK; kk = e % TK; } else { mm = e % GT_M; kk = e / GT_M; }
-      int r = m0 + mm, c = k0 + kk;
-      cplx v = {0.0, 0.0};
-      if (r < g.M && c < g.K) v = ld_op(g.A, g.lda, g.opA, r, c);
-      As_r[kk][mm] = (T)v.re;
-      As_i[kk][mm] = (T)v.im;
+      const int r = m0 + mm, c = k0 + kk;
+      pa[q] = (r < g.M && c < g.K) ? ld_op(Ag, g.lda, g.opA, r, c) : cplx{0.0, 0.0};
     }
-    for (int e = tid; e < GT_N * TK; e += 256) {
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      const int e = tid + 256 * q;
       int nn, kk;
       if (g.opB == OP_N) { nn = e % GT_N; kk = e / GT_N; } else { kk = e % TK; nn = e / TK; }
-      int r = k0 + kk, c = n0 + nn;
-      cplx v = {0.0, 0.0};
-      if (r < g.K && c < g.N) v = ld_op(g.B, g.ldb, g.opB, r, c);
-      Bs_r[kk][nn] = (T)v.re;
-      Bs_i[kk][nn] = (T)v.im;
+      const int r = k0 + kk, c = n0 + nn;
+      pb[q] = (r < g.K && c < g.N) ? ld_op(Bg, g.ldb, g.opB, r, c) : cplx{0.0, 0.0};
+    }
+  };
+  if constexpr (PF) fetch(0);
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    if constexpr (!PF) fetch(k0);
+#pragma unroll
+    for (int q = 0; q < EA; ++q) {
+      const int e = tid + 256 * q;
+      int mm, kk;
+      if (g.opA == OP_N) { mm = e / TK; kk = e % TK; } else { mm = e % GT_M; kk = e / GT_M; }
+      As_r[kk][mm] = (T)pa[q].re;
+      As_i[kk][mm] = (T)pa[q].im;
+    }
+#pragma unroll
+    for (int q = 0; q < EB; ++q) {
+      const int e = tid + 256 * q;
+      int nn, kk;
+      if (g.opB == OP_N) { nn = e % GT_N; kk = e / GT_N; } else { kk = e % TK; nn = e / TK; }
+      Bs_r[kk][nn] = (T)pb[q].re;
+      Bs_i[kk][nn] = (T)pb[q].im;
+    }
+    if constexpr (PF) {
+      if (k0 + TK < g.K) fetch(k0 + TK);
     }
     __syncthreads();
     if constexpr (P == PREC_FP64 || P == PREC_FP32) {
@@ -183,9 +229,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
           cplx out;
           out.re = g.alpha.re * vr - g.alpha.im * vi;
           out.im = g.alpha.re * vi + g.alpha.im * vr;
-          cplx* cp = g.C + (int64_t)r * g.ldc + c;
+          const gptr<cplx> cp = Cg + (int64_t)r * g.ldc + c;
           if (!beta0) {
-            cplx o = *cp;
+            const cplx o = *cp;
             out.re += g.beta.re * o.re - g.beta.im * o.im;
             out.im += g.beta.re * o.im + g.beta.im * o.re;
           }
@@ -274,22 +320,24 @@ __device__ __forceinline__ double house_rescale(double nx2) {
 
 // W and Qt point into LDS (INLDS) or into the work buffer; keeping the two
 // cases apart lets the compiler use ds_read/ds_write for LDS data.
-template <bool INLDS>
-__device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, double* tau_s,
+template <bool INLDS, class PW>
+__device__ __forceinline__ void qr_body(const QrDesc& d, PW W, PW Qt, double* tau_s,
                                         cplx* phs, cplx* alpha_s, double (*part_s)[4]) {
   const int m = d.m, n = d.n, k = m < n ? m : n;
+  const gptr<const cplx> Ain = to_global(d.A);
+  const gptr<cplx> Rout = to_global(d.R), Qout = to_global(d.Q);
   const int tid = threadIdx.x, grp = tid >> 4, gl = tid & 15;
   for (int64_t e = tid; e < (int64_t)m * n; e += 256) {
     int r = (int)(e / n), c = (int)(e % n);
     cplx v;
-    if (d.conjT) { v = d.A[(int64_t)c * d.lda + r]; v.im = -v.im; }
-    else v = d.A[(int64_t)r * d.lda + c];
+    if (d.conjT) { v = Ain[(int64_t)c * d.lda + r]; v.im = -v.im; }
+    else v = Ain[(int64_t)r * d.lda + c];
     W[(int64_t)c * m + r] = v;
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
   for (int j = 0; j < k; ++j) {
-    cplx* wj = W + (int64_t)j * m;
+    const PW wj = W + (int64_t)j * m;
     // column norm: wave sums, one barrier, every thread finishes the sum
     double part = 0.0;
     for (int i = j + tid; i < m; i += 256) part += wj[i].re * wj[i].re + wj[i].im * wj[i].im;
@@ -322,17 +370,17 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, doub
     if (tid == 0) tau_s[j] = tau;
     if (tau != 0.0) {
       for (int c = j + 1 + grp; c < n; c += 16) {
-        cplx* wc = W + (int64_t)c * m;
+        const PW wc = W + (int64_t)c * m;
         double wr = 0.0, wi = 0.0;
         for (int i = j + gl; i < m; i += 16) {
-          cplx v = (i == j) ? v0 : wj[i], a = wc[i];
+          const cplx v = (i == j) ? v0 : cplx(wj[i]), a = wc[i];
           wr += v.re * a.re + v.im * a.im;   // conj(v) * a
           wi += v.re * a.im - v.im * a.re;
         }
         wr = group16_sum(wr);
         wi = group16_sum(wi);
         for (int i = j + gl; i < m; i += 16) {
-          cplx v = (i == j) ? v0 : wj[i];
+          const cplx v = (i == j) ? v0 : cplx(wj[i]);
           wc[i].re -= tau * (v.re * wr - v.im * wi);
           wc[i].im -= tau * (v.re * wi + v.im * wr);
         }
@@ -359,7 +407,7 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, doub
       cplx w = W[(int64_t)c * m + j], ph = phs[j];
       x = cplx{w.re * ph.re + w.im * ph.im, w.im * ph.re - w.re * ph.im};
     }
-    d.R[e] = x;
+    Rout[e] = x;
   }
   if (d.Q == nullptr) return;
   // Q = H_0 ... H_{k-1} [I; 0], built backwards (column-major Qt)
@@ -371,9 +419,9 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, doub
   for (int j = k - 1; j >= 0; --j) {
     const double tau = tau_s[j];
     if (tau != 0.0) {
-      const cplx* wj = W + (int64_t)j * m;
+      const PW wj = W + (int64_t)j * m;
       for (int c = j + grp; c < k; c += 16) {
-        cplx* qc = Qt + (int64_t)c * m;
+        const PW qc = Qt + (int64_t)c * m;
         double wr = 0.0, wi = 0.0;
         for (int i = j + gl; i < m; i += 16) {
           cplx v = wj[i], a = qc[i];
@@ -394,7 +442,7 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, cplx* W, cplx* Qt, doub
   for (int64_t e = tid; e < (int64_t)m * k; e += 256) {
     int r = (int)(e / k), c = (int)(e % k);
     cplx ph = phs[c], x = Qt[(int64_t)c * m + r];
-    d.Q[e] = cplx{x.re * ph.re - x.im * ph.im, x.re * ph.im + x.im * ph.re};
+    Qout[e] = cplx{x.re * ph.re - x.im * ph.im, x.re * ph.im + x.im * ph.re};
   }
 }
 
@@ -409,7 +457,7 @@ __global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
   if ((int64_t)m * (n + (d.Q ? k : 0)) <= QR_LDS_MAX)
     qr_body<true>(d, qlds, qlds + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
   else
-    qr_body<false>(d, d.work, d.work + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
+    qr_body<false>(d, to_global(d.work), to_global(d.work) + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
 }
 
 // QR of a block with n <= 16 columns and m <= 144 rows (the reflectors,
@@ -424,6 +472,8 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
   const int m = d.m, n = d.n, k = m < n ? m : n;
   if (m > QRS_MAXM || n > QRS_MAXN) return;            // excluded by the plan compiler
   const int tid = threadIdx.x, g = tid >> 4, gl = tid & 15, lane = tid & 63;
+  const gptr<const cplx> Ain = to_global(d.A);
+  const gptr<cplx> Rout = to_global(d.R), Qout = to_global(d.Q);
   __shared__ cplx V[QRS_MAXN][QRS_MAXM];
   __shared__ double tau_s[QRS_MAXN];
   __shared__ cplx phs[QRS_MAXN], alpha_s[QRS_MAXN];
@@ -433,7 +483,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
     const int r = gl + 16 * t;
     const bool ok = r < m && g < n;
     const int64_t o = !ok ? 0 : d.conjT ? (int64_t)g * d.lda + r : (int64_t)r * d.lda + g;
-    cplx v = d.A[o];
+    cplx v = Ain[o];
     if (d.conjT) v.im = -v.im;
     a[t] = ok ? v : cplx{0.0, 0.0};
   }
@@ -518,7 +568,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
         const cplx ph = phs[r];
         x = cplx{a[t].re * ph.re + a[t].im * ph.im, a[t].im * ph.re - a[t].re * ph.im};
       }
-      d.R[(int64_t)r * n + g] = x;
+      Rout[(int64_t)r * n + g] = x;
     }
   }
   if (d.Q == nullptr || g >= k) return;
@@ -549,7 +599,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     const int r = gl + 16 * t;
-    if (r < m) d.Q[(int64_t)r * k + g] = cplx{q[t].re * ph.re - q[t].im * ph.im, q[t].re * ph.im + q[t].im * ph.re};
+    if (r < m) Qout[(int64_t)r * k + g] = cplx{q[t].re * ph.re - q[t].im * ph.im, q[t].re * ph.im + q[t].im * ph.re};
   }
 }
 
@@ -1226,7 +1276,8 @@ __host__ __device__ inline int64_t svt_pv_off(int64_t rows, int64_t cols) {
 // shifts, with NA = nt - r live row slots: every row-slot loop has a
 // compile-time bound (the slots past the matrix are zero and skipped).
 struct SvbCtx {
-  cplx *W, *bd, *xl, *xa, *xp, *uL, *yR, *xs;
+  gptr<cplx> W, bd;
+  cplx *xl, *xa, *xp, *uL, *yR, *xs;
   double *red, *tau_s;
   int m, n, mp, tid, lane, wave, rl, cg, q4;
   bool has4;
@@ -1238,8 +1289,8 @@ constexpr int SVB_NR = SVT_MAXN + 16 * 8;   // row index range of the shifted sl
 template <int NA>
 __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int j0, int r) {
   constexpr int NW = SVB_NW, NS = SVB_NS, NR = SVB_NR;
-  cplx* const W = c.W;
-  cplx* const bd = c.bd;
+  const gptr<cplx> W = c.W;
+  const gptr<cplx> bd = c.bd;
   cplx* const xl = c.xl;
   cplx* const xa = c.xa;
   cplx* const xp = c.xp;
@@ -1453,8 +1504,9 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
   __shared__ cplx xp[NW * NR];           // [wave][row]: partial row sums
   __shared__ cplx uL[NR], yR[SVT_MAXN], xs[NR];
   __shared__ double red[NW], tau_s;
-  cplx* W = dsc.work;
-  cplx* bd = dsc.work + svt_bd_off(m, n);
+  const gptr<cplx> W = to_global(dsc.work);
+  const gptr<cplx> bd = W + svt_bd_off(m, n);
+  const gptr<const cplx> Ain = to_global(dsc.A);
   if (tid == 0) bd[2 * n - 1] = cplx{0.0, 0.0};   // e_{n-1} does not exist
   for (int i = tid; i < NR; i += SVB_THREADS) uL[i] = xs[i] = cplx{0.0, 0.0};
   const bool has4 = wave < 4;                      // column g + 128 exists (g < 16)
@@ -1478,7 +1530,7 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
       const int c = cg + 32 * b;
       const bool ok = i < m && c < n;
       const int64_t o = !ok ? 0 : dsc.conjT ? (int64_t)c * dsc.lda + i : (int64_t)i * dsc.lda + c;
-      cplx v = dsc.A[o];
+      cplx v = Ain[o];
       if (dsc.conjT) v.im = -v.im;
       if (!ok) v = cplx{0.0, 0.0};
       f += v.re * v.re + v.im * v.im;
@@ -1551,9 +1603,11 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   // and the 16 values' records in different LDS banks
   __shared__ __align__(16) double iib[SVT_BATCH * (4 * 2 * SVT_MAXN + 2)];
   if (n > SVT_MAXN || m > SVT_MAXN || n > m || k > n || n < 1) return;   // excluded by the plan
-  const cplx* W = dsc.work;                            // reflectors, mp x n column-major
-  const cplx* bd = dsc.work + svt_bd_off(m, n);
-  double* pv = reinterpret_cast<double*>(dsc.work + svt_pv_off(m, n));
+  const gptr<const cplx> W = to_global(dsc.work);    // reflectors, mp x n column-major
+  const gptr<const cplx> bd = W + svt_bd_off(m, n);
+  const gptr<double> pv = to_global(reinterpret_cast<double*>(dsc.work + svt_pv_off(m, n)));
+  const gptr<cplx> Uout = to_global(dsc.U);
+  const gptr<double> sgout = to_global(dsc.sigma);
   for (int j = tid; j < n; j += SVT_THREADS) {
     dcx[j] = bd[j];
     ecx[j] = bd[n + j];
@@ -1835,7 +1889,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
               s = wave_sum_all(s);
               for (int i = lane; i < N; i += 64) x[4 * i] -= s * y[4 * i];
             } else {
-              const double* y = pv + (int64_t)u * svt_stride(m, n);
+              const gptr<const double> y = pv + (int64_t)u * svt_stride(m, n);
               for (int i = lane; i < N; i += 64) s += y[i] * x[4 * i];
               s = wave_sum_all(s);
               for (int i = lane; i < N; i += 64) x[4 * i] -= s * y[i];
@@ -1873,7 +1927,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
 #pragma unroll
     for (int t = 0; t < 9; ++t) uc[t] = cplx{0.0, 0.0};
     if (act && mine) {
-      const double* z = pv + (int64_t)v * svt_stride(m, n);
+      const gptr<const double> z = pv + (int64_t)v * svt_stride(m, n);
       zero = sig[v] * sig[v] <= floor2;
       double s = 0.0;
 #pragma unroll
@@ -1894,7 +1948,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
       __syncthreads();                                  // the previous chunk is consumed
       for (int e = tid; e < (j1 - j0) * mp; e += SVT_THREADS) {
         const int c = e / mp, i = e - c * mp, j = j0 + c;
-        chunk[e] = (i >= j && i < m) ? W[(int64_t)j * mp + i] : cplx{0.0, 0.0};
+        chunk[e] = (i >= j && i < m) ? cplx(W[(int64_t)j * mp + i]) : cplx{0.0, 0.0};
       }
       __syncthreads();
       if (act) {
@@ -1930,9 +1984,9 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int i = rl + 16 * t;
-        if (i < m) dsc.U[(int64_t)i * k + v] = uc[t];
+        if (i < m) Uout[(int64_t)i * k + v] = uc[t];
       }
-      if (rl == 0) dsc.sigma[v] = zero ? 0.0 : sig[v];
+      if (rl == 0) sgout[v] = zero ? 0.0 : sig[v];
     }
   }
 }
