@@ -263,9 +263,66 @@ __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ de
 }
 
 // ---------------------------------------------------------------- reductions
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+// Sum over the 16 lanes of a DPP row, result in every lane: xor-1 and xor-2
+// quad permutations, then half-row and row mirrors (VALU moves, no LDS).
+// Every lane reads a valid source lane under these controls, so the moves
+// need no old value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double group16_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);   // row_half_mirror
+  v += dpp_d<0x140>(v);   // row_mirror
   return v;
+}
+
+// sum over lanes l, l ^ 16, l ^ 32, l ^ 48 (the four 16-lane rows of the
+// wave), every lane active
+__device__ __forceinline__ double rows4_sum(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  v = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+  lo = __double2loint(v);
+  hi = __double2hiint(v);
+  a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+
+// sum over the 64 lanes (16-lane DPP sums, then the four rows); every lane
+// must be active
+__device__ __forceinline__ double wave_sum_all(double v) { return rows4_sum(group16_sum(v)); }
+
+// Reduce-scatter steps over the wave's 16-lane rows (r = lane / 16): p's sum
+// over rows r and r ^ 2 lands in rows 0-1, q's in rows 2-3 (swap32_sum); p's
+// sum over rows r and r ^ 1 in rows 0 and 2, q's in rows 1 and 3 (swap16_sum).
+// Every lane active.
+__device__ __forceinline__ double swap32_sum(double p, double q) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(p), __double2loint(q), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(p), __double2hiint(q), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double swap16_sum(double p, double q) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(p), __double2loint(q), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(p), __double2hiint(q), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+
+// sum over the wave, result in every lane (all lanes active)
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_all(v); }
+
+// v of lane l (l uniform over the wave)
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
 template <int NT>
@@ -288,26 +345,6 @@ __device__ double block_sum(double v, double* sh) {
 // (W) and a column-major staging area behind it (Qt).  Column operations use
 // one 16-lane group per column, 16 columns at a time.
 constexpr int QR_LDS_MAX = 8192;   // complex elements (128 KB)
-
-// Sum over the 16 lanes of a DPP row, result in every lane: xor-1 and xor-2
-// quad permutations, then half-row and row mirrors (VALU moves, no LDS).
-// Every lane reads a valid source lane under these controls, so the moves
-// need no old value.
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double group16_sum(double v) {
-  v += dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_d<0x141>(v);   // row_half_mirror
-  v += dpp_d<0x140>(v);   // row_mirror
-  return v;
-}
 
 // Householder columns whose squared norm is positive but below 1e-200 are
 // rescaled by this power of two (exact) before the reflector is formed:
@@ -509,13 +546,15 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
 #pragma unroll
       for (int t = 1; t < 9; ++t)
         if (t == (j >> 4)) mine = a[t];
-      const int src = (lane & 48) | (j & 15);
-      const cplx x0 = {__shfl(mine.re, src), __shfl(mine.im, src)};
+      // only group j is active here: its lanes share lane & 48
+      const int src = __builtin_amdgcn_readfirstlane(lane & 48) | (j & 15);
+      const cplx x0 = {readlane_d(mine.re, src), readlane_d(mine.im, src)};
       const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
       double tau = 0.0;
       cplx alpha = {0.0, 0.0}, v0 = x0;
       if (nx > 0.0) {
-        const cplx ph = ax0 > 0.0 ? cplx{x0.re / ax0, x0.im / ax0} : cplx{1.0, 0.0};
+        const double iax = ax0 > 0.0 ? 1.0 / ax0 : 0.0;
+        const cplx ph = ax0 > 0.0 ? cplx{x0.re * iax, x0.im * iax} : cplx{1.0, 0.0};
         alpha = cplx{-ph.re * nx, -ph.im * nx};
         v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
         const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
@@ -529,8 +568,9 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
       if (gl == 0) {
         tau_s[j] = tau;
         const double aa = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
-        phs[j] = aa > 0.0 ? cplx{alpha.re / aa, alpha.im / aa} : cplx{1.0, 0.0};
-        alpha_s[j] = cplx{aa / sc, 0.0};
+        const double iaa = aa > 0.0 ? 1.0 / aa : 0.0;
+        phs[j] = aa > 0.0 ? cplx{alpha.re * iaa, alpha.im * iaa} : cplx{1.0, 0.0};
+        alpha_s[j] = cplx{aa * (1.0 / sc), 0.0};            // sc is a power of two
       }
     }
     __syncthreads();
@@ -615,11 +655,8 @@ constexpr int QRT_THREADS = 1024;
 constexpr int QRT_PB = 8;
 constexpr int QRT_LDS = 9216;   // complex elements of the LDS panel (144 KB)
 
-// sum over the 64 lanes of a wave, result in every lane
-__device__ __forceinline__ double wave_sum64(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+// sum over the 64 lanes of a wave, result in every lane (all lanes active)
+__device__ __forceinline__ double wave_sum64(double v) { return wave_sum_all(v); }
 
 // sum over the workgroup (QRT_THREADS), result in every thread
 __device__ __forceinline__ double qrt_block_sum(double v, double* sh) {
@@ -1218,24 +1255,6 @@ __device__ __forceinline__ int svt_count(const double* c2, int N, double x) {
   return cnt;
 }
 
-// sum over lanes l, l ^ 16, l ^ 32, l ^ 48 (the four 16-lane rows of the
-// wave), every lane active
-__device__ __forceinline__ double rows4_sum(double v) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  v = __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
-  lo = __double2loint(v);
-  hi = __double2hiint(v);
-  a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-  b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-  return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
-}
-
-// sum over the 64 lanes (16-lane DPP sums, then the four rows); every lane
-// must be active
-__device__ __forceinline__ double wave_sum_all(double v) { return rows4_sum(group16_sum(v)); }
-
 // Householder reflector H = I - tau v v^H with H x = alpha e_0 for the
 // vector x of norm^2 nx2 and head x0: alpha = -phase(x0) |x|, v = x - alpha
 // e_0 (only the head changes); returns the head of v.  A vector with
@@ -1277,7 +1296,8 @@ __host__ __device__ inline int64_t svt_pv_off(int64_t rows, int64_t cols) {
 // compile-time bound (the slots past the matrix are zero and skipped).
 struct SvbCtx {
   gptr<cplx> W, bd;
-  cplx *xl, *xa, *xp, *uL, *yR, *xs;
+  cplx *xl, *xa, *uL, *yR, *xs;
+  double *xpr, *xpi;
   double *red, *tau_s;
   int m, n, mp, tid, lane, wave, rl, cg, q4;
   bool has4;
@@ -1293,7 +1313,8 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
   const gptr<cplx> bd = c.bd;
   cplx* const xl = c.xl;
   cplx* const xa = c.xa;
-  cplx* const xp = c.xp;
+  double* const xpr = c.xpr;
+  double* const xpi = c.xpi;
   cplx* const uL = c.uL;
   cplx* const yR = c.yR;
   cplx* const xs = c.xs;
@@ -1352,8 +1373,9 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
           part = fma(v.re, v.re, fma(v.im, v.im, part));
         }
         const double nx2 = group16_sum(part);
-        const int src = (lane & 48) | jj;
-        const cplx x0 = {__shfl(head.re, src), __shfl(head.im, src)};
+        // only the group of column j is active here: its lanes share lane & 48
+        const int src = __builtin_amdgcn_readfirstlane(lane & 48) | jj;
+        const cplx x0 = {readlane_d(head.re, src), readlane_d(head.im, src)};
         double tau;
         cplx alpha;
         const cplx v0 = svt_house(x0, nx2, hthr, &tau, &alpha);
@@ -1447,10 +1469,21 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
             xi[a] = fma(x.re, v2[b].im, fma(x.im, v2[b].re, xi[a]));
           }
         }
+        // sums over the wave's four 16-lane rows as a reduce-scatter: the
+        // first swaps leave re(a) in rows 0-1 and im(a) in rows 2-3, the
+        // second ones rows a < H in the even 16-lane rows and a >= H in the
+        // odd ones (an odd NA's last row is summed in every lane)
+        constexpr int H = NA / 2;
+        double s1[NA];
 #pragma unroll
-        for (int a = 0; a < NA; ++a) {
-          const double sr = rows4_sum(xr[a]), si = rows4_sum(xi[a]);
-          if (q4 == 0) xp[wave * NR + rb + 16 * a] = cplx{sr, si};
+        for (int a = 0; a < NA; ++a) s1[a] = swap32_sum(xr[a], xi[a]);
+        double* const xo = (q4 >= 2 ? xpi : xpr) + wave * NR + rb;
+        const int ah = (q4 & 1) ? H : 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) xo[16 * (i + ah)] = swap16_sum(s1[i], s1[i + H]);
+        if constexpr ((NA & 1) != 0) {
+          const double t = swap16_sum(s1[NA - 1], s1[NA - 1]);
+          if (!(q4 & 1)) xo[16 * (NA - 1)] = t;
         }
       }
       __syncthreads();
@@ -1458,9 +1491,8 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
         double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-          const cplx p = xp[w * NR + tid];
-          sr += p.re;
-          si += p.im;
+          sr += xpr[w * NR + tid];
+          si += xpi[w * NR + tid];
         }
         xs[tid] = cplx{tau2 * sr, tau2 * si};
       }
@@ -1501,7 +1533,7 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
   static_assert(NW == 8 && SVT_MAXN == 144, "thread layout");
   __shared__ cplx xl[32 * SVT_MAXN];     // slot 0: [g][row], column g
   __shared__ cplx xa[16 * SVT_MAXN];     // slot 4 before it moves: [g][row], column g + 128
-  __shared__ cplx xp[NW * NR];           // [wave][row]: partial row sums
+  __shared__ double xpr[NW * NR], xpi[NW * NR];   // [wave][row]: partial row sums
   __shared__ cplx uL[NR], yR[SVT_MAXN], xs[NR];
   __shared__ double red[NW], tau_s;
   const gptr<cplx> W = to_global(dsc.work);
@@ -1547,7 +1579,7 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
   if (tid == 0) bd[3 * n] = cplx{fro2, 0.0};
   // columns and rows below 1e-100 ||A||_F get no reflector
   const double hthr = 1e-200 * fro2;
-  const SvbCtx ctx{W, bd, xl, xa, xp, uL, yR, xs, red, &tau_s, m, n, mp, tid, lane, wave,
+  const SvbCtx ctx{W, bd, xl, xa, uL, yR, xs, xpr, xpi, red, &tau_s, m, n, mp, tid, lane, wave,
                    rl, cg, q4, has4, hthr};
   // blocks of 16 steps with nt, nt-1, .. 1 live row slots, in sequence (a
   // loop or a switch over the templates would merge the register tile from
