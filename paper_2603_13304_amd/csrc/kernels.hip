@@ -319,6 +319,17 @@ __device__ __forceinline__ double swap16_sum(double p, double q) {
 // sum over the wave, result in every lane (all lanes active)
 __device__ __forceinline__ double wave_sum(double v) { return wave_sum_all(v); }
 
+// 1/q from the hardware estimate and two Newton steps: full precision for
+// normal q well inside the double range (the pivots of the scaled
+// tridiagonal, |q| >= eps, and Householder norms), at a fraction of the cost
+// of the IEEE division sequence
+__device__ __forceinline__ double svt_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
 // v of lane l (l uniform over the wave)
 __device__ __forceinline__ double readlane_d(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
@@ -497,6 +508,29 @@ __global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
     qr_body<false>(d, to_global(d.work), to_global(d.work) + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
 }
 
+// x -= tau v (v^H x) for a vector held as rows gl + 16 t (t < 9) of a
+// 16-lane group; the dot product is a 16-lane DPP sum
+__device__ __forceinline__ void house_apply(cplx (&x)[9], const cplx (&v)[9], double tau) {
+  double wr0 = 0.0, wi0 = 0.0, wr1 = 0.0, wi1 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    double& wr = t & 1 ? wr1 : wr0;
+    double& wi = t & 1 ? wi1 : wi0;
+    wr = fma(v[t].re, x[t].re, wr);
+    wr = fma(v[t].im, x[t].im, wr);
+    wi = fma(v[t].re, x[t].im, wi);
+    wi = fma(-v[t].im, x[t].re, wi);
+  }
+  const double wr = tau * group16_sum(wr0 + wr1), wi = tau * group16_sum(wi0 + wi1);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    x[t].re = fma(-v[t].re, wr, x[t].re);
+    x[t].re = fma(v[t].im, wi, x[t].re);
+    x[t].im = fma(-v[t].re, wi, x[t].im);
+    x[t].im = fma(-v[t].im, wr, x[t].im);
+  }
+}
+
 // QR of a block with n <= 16 columns and m <= 144 rows (the reflectors,
 // phases and outputs of k_qr): 16-lane group g holds column g in registers
 // (rows lane + 16 t).  Step j: group j forms the reflector with DPP sums and
@@ -553,12 +587,12 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
       double tau = 0.0;
       cplx alpha = {0.0, 0.0}, v0 = x0;
       if (nx > 0.0) {
-        const double iax = ax0 > 0.0 ? 1.0 / ax0 : 0.0;
+        const double iax = ax0 > 0.0 ? svt_rcp(ax0) : 0.0;
         const cplx ph = ax0 > 0.0 ? cplx{x0.re * iax, x0.im * iax} : cplx{1.0, 0.0};
         alpha = cplx{-ph.re * nx, -ph.im * nx};
         v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
         const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
-        tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
+        tau = nv2 > 0.0 ? 2.0 * svt_rcp(nv2) : 0.0;
       }
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
@@ -568,7 +602,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
       if (gl == 0) {
         tau_s[j] = tau;
         const double aa = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
-        const double iaa = aa > 0.0 ? 1.0 / aa : 0.0;
+        const double iaa = aa > 0.0 ? svt_rcp(aa) : 0.0;
         phs[j] = aa > 0.0 ? cplx{alpha.re * iaa, alpha.im * iaa} : cplx{1.0, 0.0};
         alpha_s[j] = cplx{aa * (1.0 / sc), 0.0};            // sc is a power of two
       }
@@ -576,21 +610,10 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
     __syncthreads();
     const double tau = tau_s[j];
     if (g > j && g < n && tau != 0.0) {
-      double wr = 0.0, wi = 0.0;
+      cplx v[9];                                            // zero above row j
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const cplx v = V[j][gl + 16 * t];                   // zero above row j
-        wr += v.re * a[t].re + v.im * a[t].im;
-        wi += v.re * a[t].im - v.im * a[t].re;
-      }
-      wr = group16_sum(wr);
-      wi = group16_sum(wi);
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const cplx v = V[j][gl + 16 * t];
-        a[t].re -= tau * (v.re * wr - v.im * wi);
-        a[t].im -= tau * (v.re * wi + v.im * wr);
-      }
+      for (int t = 0; t < 9; ++t) v[t] = V[j][gl + 16 * t];
+      house_apply(a, v, tau);
     }
   }
   __syncthreads();
@@ -619,21 +642,10 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
   for (int j = g; j >= 0; --j) {
     const double tau = tau_s[j];
     if (tau == 0.0) continue;
-    double wr = 0.0, wi = 0.0;
+    cplx v[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const cplx v = V[j][gl + 16 * t];
-      wr += v.re * q[t].re + v.im * q[t].im;
-      wi += v.re * q[t].im - v.im * q[t].re;
-    }
-    wr = group16_sum(wr);
-    wi = group16_sum(wi);
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const cplx v = V[j][gl + 16 * t];
-      q[t].re -= tau * (v.re * wr - v.im * wi);
-      q[t].im -= tau * (v.re * wi + v.im * wr);
-    }
+    for (int t = 0; t < 9; ++t) v[t] = V[j][gl + 16 * t];
+    house_apply(q, v, tau);
   }
   const cplx ph = phs[g];
 #pragma unroll
@@ -1203,16 +1215,6 @@ __host__ __device__ inline int64_t svt_stride(int64_t rows, int64_t cols) {
   return 2 * cols + 2 * rows;
 }
 
-// 1/q from the hardware estimate and two Newton steps (full precision for
-// the pivots of the scaled matrix, |q| >= eps; cheaper than the IEEE
-// division in the elimination below)
-__device__ __forceinline__ double svt_rcp(double q) {
-  double r = __builtin_amdgcn_rcp(q);
-  r = fma(r, fma(-q, r, 1.0), r);
-  r = fma(r, fma(-q, r, 1.0), r);
-  return r;
-}
-
 // number of eigenvalues below x of the symmetric tridiagonal T with zero
 // diagonal and squared off-diagonal c2[0 .. N-2], scaled by a power of two so
 // that ||T|| < 2, with c2 >= 2^-300 and x >= 2^-64 (changes far below the
@@ -1775,6 +1777,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   // values at or below the noise floor get zero columns: no vector is solved
   // for them (their cluster makes the solve singular)
   const double floor2 = 1e-30 * fro2_s;
+  const double ctol = 1.0 / (sqrt(double(N)) * eps * bs);
   for (int v0b = 0; v0b < k; v0b += SVT_BATCH) {
     const int kb = k - v0b < SVT_BATCH ? k - v0b : SVT_BATCH;
     bool zv = true;
@@ -1816,6 +1819,12 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
       }
     }
     for (int it = 0; it < SVT_ITERS; ++it) {
+      // a solve from a unit right side whose solution reaches max |x_i| >=
+      // 1 / (sqrt(N) eps ||T||) has a residual at the rounding level already
+      // (the inverse-iteration stopping test of LAPACK's dstein, with its
+      // extra step): when every value of the batch passes it on the second
+      // solve, the third is skipped
+      bool conv = true;
       if (tid < kb && !zv) {
         double* rec = iib + (int64_t)tid * pstr;
         // Both solves run in blocks of 8 steps: the block's records are read
@@ -1849,12 +1858,14 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
         // 2^-500 while the carried values exceed 2^500
         double x1 = bi * rec[4 * (N - 1)], x2 = 0.0, sc = 1.0;
         rec[4 * (N - 1) + 3] = x1;
+        double mx = fabs(x1);
         auto bstep = [&](d2v a, d2v b, double o) {
           const int msk = -(__double2loint(b[0]) & 1);   // all ones after a swap
           const double r2 = __hiloint2double(__double2hiint(o) & msk, __double2loint(o) & msk);
           const double xi = (b[1] * sc - a[1] * x1 - r2 * x2) * a[0];
           x2 = x1;
           x1 = xi;
+          mx = fmax(mx, fabs(xi));
           return xi;
         };
         auto rescale = [&](int i0) {     // entries i0 .. N-1 are stored
@@ -1863,6 +1874,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
             x1 *= 0x1p-500;
             x2 *= 0x1p-500;
             sc *= 0x1p-500;
+            mx *= 0x1p-500;
           }
         };
         i = N - 2;
@@ -1888,8 +1900,9 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           for (int t = 0; t < 8; ++t) rec[4 * (i - t) + 3] = xs[t];
           rescale(i - 7);
         }
+        conv = sc < 1.0 || mx >= ctol;
       }
-      __syncthreads();
+      const bool all_conv = __syncthreads_and(conv) != 0;
       if (wave < kb) {
         const int v = v0b + wave;
         bool cl = false;
@@ -1935,6 +1948,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
         }
       }
       __syncthreads();
+      if (it >= 1 && all_conv) break;
     }
     // keep the batch's eigenvectors in the work buffer
     for (int e = tid; e < kb * N; e += SVT_THREADS) {
@@ -1989,26 +2003,9 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           if (tau == 0.0) continue;
           const cplx* vj = chunk + (j - j0) * mp;
           cplx a[9];
-          double wr0 = 0.0, wi0 = 0.0, wr1 = 0.0, wi1 = 0.0;   // v^H u, even and odd slots
 #pragma unroll
-          for (int t = 0; t < 9; ++t) {
-            a[t] = t < nt ? vj[rl + 16 * t] : cplx{0.0, 0.0};
-            double& wr = t & 1 ? wr1 : wr0;
-            double& wi = t & 1 ? wi1 : wi0;
-            wr = fma(a[t].re, uc[t].re, wr);
-            wr = fma(a[t].im, uc[t].im, wr);
-            wi = fma(a[t].re, uc[t].im, wi);
-            wi = fma(-a[t].im, uc[t].re, wi);
-          }
-          const double wr = tau * group16_sum(wr0 + wr1);
-          const double wi = tau * group16_sum(wi0 + wi1);
-#pragma unroll
-          for (int t = 0; t < 9; ++t) {
-            uc[t].re = fma(-a[t].re, wr, uc[t].re);
-            uc[t].re = fma(a[t].im, wi, uc[t].re);
-            uc[t].im = fma(-a[t].re, wi, uc[t].im);
-            uc[t].im = fma(-a[t].im, wr, uc[t].im);
-          }
+          for (int t = 0; t < 9; ++t) a[t] = t < nt ? vj[rl + 16 * t] : cplx{0.0, 0.0};
+          house_apply(uc, a, tau);
         }
       }
     }
