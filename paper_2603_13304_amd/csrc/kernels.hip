@@ -609,7 +609,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
     }
     __syncthreads();
     const double tau = tau_s[j];
-    if (g > j && g < n && tau != 0.0) {
+    if (g > j && g < n) {                                   // tau = 0 changes nothing
       cplx v[9];                                            // zero above row j
 #pragma unroll
       for (int t = 0; t < 9; ++t) v[t] = V[j][gl + 16 * t];
@@ -640,8 +640,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
 #pragma unroll
   for (int t = 0; t < 9; ++t) q[t] = cplx{gl + 16 * t == g ? 1.0 : 0.0, 0.0};
   for (int j = g; j >= 0; --j) {
-    const double tau = tau_s[j];
-    if (tau == 0.0) continue;
+    const double tau = tau_s[j];                            // tau = 0 changes nothing
     cplx v[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) v[t] = V[j][gl + 16 * t];
@@ -1958,16 +1957,19 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
     __syncthreads();
   }
   // ---- 4. U = Q_L D_L u: 16 lanes per value (lane r of the group holds rows
-  // r + 16 t, t < nt), four values per wave; the reflectors are staged
-  // through LDS in chunks shared by all waves
+  // r + 16 t, t < nt), four values per wave.  The reflectors pass through two
+  // LDS chunks of CH: while the waves holding values apply one chunk, the
+  // other waves load the next (with every wave busy, the chunks are loaded
+  // in turn)
   constexpr int CH = 32;                                // reflectors per chunk
-  static_assert(CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 2), "chunk fits");
-  cplx* chunk = reinterpret_cast<cplx*>(iib);           // [c][row], rows 0..mp-1
+  static_assert(2 * CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 2), "two chunks fit");
+  cplx* const chunk0 = reinterpret_cast<cplx*>(iib);    // [c][row], rows 0..mp-1
   const int g16 = lane >> 4, rl = lane & 15;
   for (int vb = 0; vb < k; vb += 4 * NW) {
     const int v = vb + 4 * wave + g16;
     const bool act = vb + 4 * wave < k;                 // wave-uniform
     const bool mine = v < k;                            // uniform in the 16-lane group
+    const int wa = (min(k - vb, 4 * NW) + 3) / 4;       // waves holding values
     bool zero = true;
     cplx uc[9];
 #pragma unroll
@@ -1989,25 +1991,40 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
         if (i < n && !zero) uc[t] = cplx{pL[i].re * z[2 * i + 1] * inv, pL[i].im * z[2 * i + 1] * inv};
       }
     }
+    // reflectors j0 .. j1-1 into chunk buffer bsel, by threads t0, t0 + dt, ..
+    auto stage = [&](int bsel, int j0, int j1, int t0, int dt) {
+      cplx* const ch = chunk0 + bsel * CH * SVT_MAXN;
+      for (int e = t0; e < (j1 - j0) * mp; e += dt) {
+        const int c = e / mp, i = e - c * mp, j = j0 + c;
+        ch[e] = (i >= j && i < m) ? cplx(W[(int64_t)j * mp + i]) : cplx{0.0, 0.0};
+      }
+    };
+    const bool split = wa < NW;                         // spare waves load ahead
+    __syncthreads();                                    // iib is free
+    stage(0, n > CH ? n - CH : 0, n, tid, SVT_THREADS);
+    __syncthreads();
+    int bsel = 0;
     for (int j1 = n; j1 > 0; j1 -= CH) {
       const int j0 = j1 > CH ? j1 - CH : 0;
-      __syncthreads();                                  // the previous chunk is consumed
-      for (int e = tid; e < (j1 - j0) * mp; e += SVT_THREADS) {
-        const int c = e / mp, i = e - c * mp, j = j0 + c;
-        chunk[e] = (i >= j && i < m) ? cplx(W[(int64_t)j * mp + i]) : cplx{0.0, 0.0};
-      }
-      __syncthreads();
+      const int n0 = j0 > CH ? j0 - CH : 0;             // next chunk n0 .. j0-1
+      if (split && wave >= wa && j0 > 0) stage(bsel ^ 1, n0, j0, tid - 64 * wa, SVT_THREADS - 64 * wa);
       if (act) {
+        const cplx* const ch = chunk0 + bsel * CH * SVT_MAXN;
         for (int j = j1 - 1; j >= j0; --j) {
-          const double tau = tauL[j];
-          if (tau == 0.0) continue;
-          const cplx* vj = chunk + (j - j0) * mp;
+          const double tau = tauL[j];                   // tau = 0 leaves uc exactly as it is
+          const cplx* vj = ch + (j - j0) * mp;
           cplx a[9];
 #pragma unroll
           for (int t = 0; t < 9; ++t) a[t] = t < nt ? vj[rl + 16 * t] : cplx{0.0, 0.0};
           house_apply(uc, a, tau);
         }
       }
+      __syncthreads();                                  // next chunk in, this one consumed
+      if (!split && j0 > 0) {
+        stage(bsel ^ 1, n0, j0, tid, SVT_THREADS);
+        __syncthreads();
+      }
+      bsel ^= 1;
     }
     if (act && mine) {
 #pragma unroll
