@@ -51,7 +51,8 @@ struct LaunchRec {
   int count = 0;
   dim3 grid;
   size_t lds = 0;
-  int variant = 0;       // kernel variant (QR: 1 = blocked tall kernel, 2 = k_qr_small; Jacobi: 1 = rows
+  int variant = 0;       // kernel variant (QR: 1 = blocked tall kernel, 2 = k_qr_small, 3 =
+                         // k_qr_mid (R only); Jacobi: 1 = rows
                          // split between LDS and the work buffer, 2 = top-k SVD through
                          // bidiagonalisation: k_svt_bidiag then k_svd_top)
   double gemm_flops = 0.0, contraction_flops = 0.0;
@@ -180,6 +181,7 @@ int op_variant(const Op& op) {
   if (op.type == OPK_QR) {
     const int64_t m = op.i[0], n = op.i[1], k = std::min(m, n);
     if (m <= QRS_MAXM && n <= QRS_MAXN) return 2;   // k_qr_small
+    if (!op.c.valid() && m <= QRS_MAXM && n <= QRM_MAXN) return 3;   // k_qr_mid, R only
     return m * (n + (op.c.valid() ? k : 0)) <= QR_LDS_MAX ? 0 : 1;
   }
   if (op.type == OPK_JACOBI) {
@@ -305,9 +307,9 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
           rec.desc_off = push_descs(blob, v);
           rec.grid = dim3(unsigned(v.size()));
           // blocked kernel (panel in LDS) for working copies that overflow LDS;
-          // k_qr_small uses static LDS only
+          // k_qr_small and k_qr_mid use static LDS only
           rec.lds = rec.variant == 1 ? size_t(QRT_LDS) * sizeof(cplx)
-                  : rec.variant == 2 ? 0 : size_t(lds_elems) * sizeof(cplx);
+                  : rec.variant >= 2 ? 0 : size_t(lds_elems) * sizeof(cplx);
           break;
         }
         case OPK_JACOBI: {
@@ -462,6 +464,8 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
     case OPK_QR:
       if (r.variant == 2)
         hipLaunchKernelGGL(k_qr_small, r.grid, dim3(256), 0, stream, (const QrDesc*)d);
+      else if (r.variant == 3)
+        hipLaunchKernelGGL(k_qr_mid, r.grid, dim3(QRM_THREADS), 0, stream, (const QrDesc*)d);
       else if (r.variant)
         hipLaunchKernelGGL(k_qr_tall, r.grid, dim3(QRT_THREADS), r.lds, stream,
                            (const QrDesc*)d);

@@ -531,13 +531,69 @@ __device__ __forceinline__ void house_apply(cplx (&x)[9], const cplx (&v)[9], do
   }
 }
 
+constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
+
+// Householder step j on a column held by one 16-lane group as rows gl + 16 t
+// (only that group active): the reflector (zero above row j, its head at row
+// j) goes to Vr[0 .. 143]; lane gl == 0 stores tau, the unit phase of alpha
+// and |alpha| (rescaled back when the column was tiny).  The column's rows
+// from j on may be left rescaled.
+__device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, int lane, cplx* Vr,
+                                                   double* tau_o, cplx* phs_o, cplx* alpha_o) {
+  double part = 0.0;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+    if (gl + 16 * t >= j) part += a[t].re * a[t].re + a[t].im * a[t].im;
+  double nx2 = group16_sum(part);
+  const double sc = house_rescale(nx2);          // uniform within the group
+  if (sc != 1.0) {
+    part = 0.0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+      if (gl + 16 * t >= j) {
+        a[t] = cplx{a[t].re * sc, a[t].im * sc};
+        part += a[t].re * a[t].re + a[t].im * a[t].im;
+      }
+    nx2 = group16_sum(part);
+  }
+  cplx mine = a[0];
+#pragma unroll
+  for (int t = 1; t < 9; ++t)
+    if (t == (j >> 4)) mine = a[t];
+  // only the owner group is active here: its lanes share lane & 48
+  const int src = __builtin_amdgcn_readfirstlane(lane & 48) | (j & 15);
+  const cplx x0 = {readlane_d(mine.re, src), readlane_d(mine.im, src)};
+  const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
+  double tau = 0.0;
+  cplx alpha = {0.0, 0.0}, v0 = x0;
+  if (nx > 0.0) {
+    const double iax = ax0 > 0.0 ? svt_rcp(ax0) : 0.0;
+    const cplx ph = ax0 > 0.0 ? cplx{x0.re * iax, x0.im * iax} : cplx{1.0, 0.0};
+    alpha = cplx{-ph.re * nx, -ph.im * nx};
+    v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
+    const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
+    tau = nv2 > 0.0 ? 2.0 * svt_rcp(nv2) : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int r = gl + 16 * t;
+    if (r < QRS_MAXM) Vr[r] = r < j ? cplx{0.0, 0.0} : r == j ? v0 : a[t];
+  }
+  if (gl == 0) {
+    *tau_o = tau;
+    const double aa = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
+    const double iaa = aa > 0.0 ? svt_rcp(aa) : 0.0;
+    *phs_o = aa > 0.0 ? cplx{alpha.re * iaa, alpha.im * iaa} : cplx{1.0, 0.0};
+    *alpha_o = cplx{aa * (1.0 / sc), 0.0};              // sc is a power of two
+  }
+}
+
 // QR of a block with n <= 16 columns and m <= 144 rows (the reflectors,
 // phases and outputs of k_qr): 16-lane group g holds column g in registers
 // (rows lane + 16 t).  Step j: group j forms the reflector with DPP sums and
 // stores it in LDS, one barrier, every later group applies it to its column
 // with a 16-lane DPP dot product.  The reflectors stay in LDS, so forming Q
 // (group c applies H_{k-1} .. H_0 to e_c) needs no barrier at all.
-constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
 __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ descs) {
   const QrDesc d = descs[blockIdx.x];
   const int m = d.m, n = d.n, k = m < n ? m : n;
@@ -559,54 +615,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
     a[t] = ok ? v : cplx{0.0, 0.0};
   }
   for (int j = 0; j < k; ++j) {
-    if (g == j) {
-      double part = 0.0;
-#pragma unroll
-      for (int t = 0; t < 9; ++t)
-        if (gl + 16 * t >= j) part += a[t].re * a[t].re + a[t].im * a[t].im;
-      double nx2 = group16_sum(part);
-      const double sc = house_rescale(nx2);          // uniform within the group
-      if (sc != 1.0) {
-        part = 0.0;
-#pragma unroll
-        for (int t = 0; t < 9; ++t)
-          if (gl + 16 * t >= j) {
-            a[t] = cplx{a[t].re * sc, a[t].im * sc};
-            part += a[t].re * a[t].re + a[t].im * a[t].im;
-          }
-        nx2 = group16_sum(part);
-      }
-      cplx mine = a[0];
-#pragma unroll
-      for (int t = 1; t < 9; ++t)
-        if (t == (j >> 4)) mine = a[t];
-      // only group j is active here: its lanes share lane & 48
-      const int src = __builtin_amdgcn_readfirstlane(lane & 48) | (j & 15);
-      const cplx x0 = {readlane_d(mine.re, src), readlane_d(mine.im, src)};
-      const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
-      double tau = 0.0;
-      cplx alpha = {0.0, 0.0}, v0 = x0;
-      if (nx > 0.0) {
-        const double iax = ax0 > 0.0 ? svt_rcp(ax0) : 0.0;
-        const cplx ph = ax0 > 0.0 ? cplx{x0.re * iax, x0.im * iax} : cplx{1.0, 0.0};
-        alpha = cplx{-ph.re * nx, -ph.im * nx};
-        v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
-        const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
-        tau = nv2 > 0.0 ? 2.0 * svt_rcp(nv2) : 0.0;
-      }
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int r = gl + 16 * t;
-        if (r < QRS_MAXM) V[j][r] = r < j ? cplx{0.0, 0.0} : r == j ? v0 : a[t];
-      }
-      if (gl == 0) {
-        tau_s[j] = tau;
-        const double aa = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
-        const double iaa = aa > 0.0 ? svt_rcp(aa) : 0.0;
-        phs[j] = aa > 0.0 ? cplx{alpha.re * iaa, alpha.im * iaa} : cplx{1.0, 0.0};
-        alpha_s[j] = cplx{aa * (1.0 / sc), 0.0};            // sc is a power of two
-      }
-    }
+    if (g == j) qr_group_reflector(a, j, gl, lane, V[j], tau_s + j, phs + j, alpha_s + j);
     __syncthreads();
     const double tau = tau_s[j];
     if (g > j && g < n) {                                   // tau = 0 changes nothing
@@ -651,6 +660,87 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
   for (int t = 0; t < 9; ++t) {
     const int r = gl + 16 * t;
     if (r < m) Qout[(int64_t)r * k + g] = cplx{q[t].re * ph.re - q[t].im * ph.im, q[t].re * ph.im + q[t].im * ph.re};
+  }
+}
+
+// R-only QR of a block with 16 < n <= 128 columns and m <= 144 rows (the same
+// R as k_qr): 16-lane group g of 32 holds columns g + 32 s (s < 4) in
+// registers (rows lane + 16 t).  Step j: the group holding column j forms the
+// reflector into one of two LDS buffers, one barrier, every later column
+// applies it with a 16-lane DPP dot product.  Step j + 1 writes the other
+// buffer, so one barrier per step is enough.
+constexpr int QRM_MAXN = 128, QRM_THREADS = 512;
+__global__ __launch_bounds__(QRM_THREADS) void k_qr_mid(const QrDesc* __restrict__ descs) {
+  const QrDesc d = descs[blockIdx.x];
+  const int m = d.m, n = d.n, k = m < n ? m : n;
+  if (m > QRS_MAXM || n > QRM_MAXN || d.Q != nullptr) return;   // excluded by the plan compiler
+  const int tid = threadIdx.x, g = tid >> 4, gl = tid & 15, lane = tid & 63;
+  const gptr<const cplx> Ain = to_global(d.A);
+  const gptr<cplx> Rout = to_global(d.R);
+  __shared__ cplx V[2][QRS_MAXM];
+  __shared__ double tau_s[QRM_MAXN];
+  __shared__ cplx phs[QRM_MAXN], alpha_s[QRM_MAXN];
+  cplx a[4][9];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = g + 32 * q;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int r = gl + 16 * t;
+      const bool ok = r < m && c < n;
+      const int64_t o = !ok ? 0 : d.conjT ? (int64_t)c * d.lda + r : (int64_t)r * d.lda + c;
+      cplx v = Ain[o];
+      if (d.conjT) v.im = -v.im;
+      a[q][t] = ok ? v : cplx{0.0, 0.0};
+    }
+  }
+  for (int j = 0; j < k; ++j) {
+    if (g == (j & 31)) {
+      const int so = j >> 5;                         // slot of column j
+      cplx col[9];
+#pragma unroll
+      for (int t = 0; t < 9; ++t) col[t] = a[0][t];
+#pragma unroll
+      for (int q = 1; q < 4; ++q)
+        if (q == so) {
+#pragma unroll
+          for (int t = 0; t < 9; ++t) col[t] = a[q][t];
+        }
+      // the finished column's rows from j on are not read again
+      qr_group_reflector(col, j, gl, lane, V[j & 1], tau_s + j, phs + j, alpha_s + j);
+    }
+    __syncthreads();
+    const double tau = tau_s[j];                     // tau = 0 changes nothing
+    if (g + 96 > j) {                                // some column of this group is trailing
+      cplx v[9];                                     // zero above row j
+#pragma unroll
+      for (int t = 0; t < 9; ++t) v[t] = V[j & 1][gl + 16 * t];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = g + 32 * q;
+        if (c > j && c < n) house_apply(a[q], v, tau);
+      }
+    }
+  }
+  __syncthreads();
+  // R (k x n) with the canonical gauge, as k_qr_small; group g writes its columns
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = g + 32 * q;
+    if (c >= n) continue;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int r = gl + 16 * t;
+      if (r >= k) continue;
+      cplx x = {0.0, 0.0};
+      if (r == c) {
+        x = alpha_s[r];
+      } else if (r < c) {
+        const cplx ph = phs[r];
+        x = cplx{a[q][t].re * ph.re + a[q][t].im * ph.im, a[q][t].im * ph.re - a[q][t].re * ph.im};
+      }
+      Rout[(int64_t)r * n + c] = x;
+    }
   }
 }
 
