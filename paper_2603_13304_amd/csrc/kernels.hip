@@ -1513,53 +1513,44 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
       }
       if (j == n - 1) break;
       // ---- right reflector from row j (row slot 0 of lane rl == jj), columns
-      // j+1..: y = conj(row) into yR, its norm summed per wave
+      // j+1..: y = conj(row j) into yR, its norm summed per wave.  The row
+      // sums the right update needs, x_i = sum_c a_ic v2_c with v2_c = y_c
+      // past the head, are taken here too (row j broadcast in each 16-lane
+      // group); only the head term a_{i,j+1} u0 waits for the reflector, so
+      // the right reflector costs one barrier less.  Column j+1 goes to xs
+      // (each entry is read and then overwritten by the same thread below).
       {
         double part = 0.0;
-        if (rl == jj) {
+        double xr[9], xi[9];
 #pragma unroll
-          for (int b = 0; b < NS; ++b) {
-            if (!live(b)) continue;
-            const int c = col(b);
-            const cplx x = get(0, b);
-            cplx y = {0.0, 0.0};
-            if (c > j && c < n) y = cplx{x.re, -x.im};
+        for (int a = 0; a < NA; ++a) xr[a] = xi[a] = 0.0;
+        const int src = (lane & 48) | jj;
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+          if (!live(b)) continue;                  // scalar
+          const int c = col(b);
+          const cplx x0 = get(0, b);
+          const cplx xj = {__shfl(x0.re, src), __shfl(x0.im, src)};   // a_jc
+          cplx y = {0.0, 0.0};
+          if (c > j && c < n) y = cplx{xj.re, -xj.im};
+          if (rl == jj) {
             yR[c] = y;
             part = fma(y.re, y.re, fma(y.im, y.im, part));
+          }
+          if (c == j + 1) {                        // the group holding column j+1
+#pragma unroll
+            for (int a = 0; a < NA; ++a) xs[rb + 16 * a] = get(a, b);
+          }
+          const cplx yh = c > j + 1 ? y : cplx{0.0, 0.0};
+#pragma unroll
+          for (int a = 0; a < NA; ++a) {
+            const cplx x = get(a, b);
+            xr[a] = fma(x.re, yh.re, fma(-x.im, yh.im, xr[a]));
+            xi[a] = fma(x.re, yh.im, fma(x.im, yh.re, xi[a]));
           }
         }
         part = rows4_sum(part);
         if (lane == jj) red[wave] = part;
-      }
-      __syncthreads();
-      const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
-      double tau2;
-      cplx beta;
-      const cplx u0 = svt_house(yR[j + 1], ny2, hthr, &tau2, &beta);
-      if (tid == 0) bd[n + j] = cplx{beta.re, -beta.im};
-      // ---- rows i > j: a -= tau2 (a . v2) conj(v2)
-      cplx v2[NS];
-      if (tau2 != 0.0) {
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-          const int c = col(b);
-          v2[b] = cplx{0.0, 0.0};
-          if (live(b) && c > j + 1) v2[b] = yR[c];
-          if (c == j + 1) v2[b] = u0;
-        }
-        double xr[9], xi[9];
-#pragma unroll
-        for (int a = 0; a < NA; ++a) xr[a] = xi[a] = 0.0;
-#pragma unroll
-        for (int b = 0; b < NS; ++b) {
-          if (!live(b)) continue;                  // scalar
-#pragma unroll
-          for (int a = 0; a < NA; ++a) {
-            const cplx x = get(a, b);
-            xr[a] = fma(x.re, v2[b].re, fma(-x.im, v2[b].im, xr[a]));
-            xi[a] = fma(x.re, v2[b].im, fma(x.im, v2[b].re, xi[a]));
-          }
-        }
         // sums over the wave's four 16-lane rows as a reduce-scatter: the
         // first swaps leave re(a) in rows 0-1 and im(a) in rows 2-3, the
         // second ones rows a < H in the even 16-lane rows and a >= H in the
@@ -1578,14 +1569,29 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
         }
       }
       __syncthreads();
+      const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
+      double tau2;
+      cplx beta;
+      const cplx u0 = svt_house(yR[j + 1], ny2, hthr, &tau2, &beta);
+      if (tid == 0) bd[n + j] = cplx{beta.re, -beta.im};
+      // ---- rows i > j: a -= tau2 x_i conj(v2), x_i = partial sums + a_{i,j+1} u0
       if (tau2 != 0.0 && tid < mp && tid > j) {
-        double sr = 0.0, si = 0.0;
+        const cplx aj1 = xs[tid];
+        double sr = aj1.re * u0.re - aj1.im * u0.im, si = aj1.re * u0.im + aj1.im * u0.re;
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
           sr += xpr[w * NR + tid];
           si += xpi[w * NR + tid];
         }
         xs[tid] = cplx{tau2 * sr, tau2 * si};
+      }
+      cplx v2[NS];
+#pragma unroll
+      for (int b = 0; b < NS; ++b) {
+        const int c = col(b);
+        v2[b] = cplx{0.0, 0.0};
+        if (live(b) && c > j + 1) v2[b] = yR[c];
+        if (c == j + 1) v2[b] = u0;
       }
       __syncthreads();
       if (tau2 != 0.0) {
