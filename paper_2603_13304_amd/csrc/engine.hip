@@ -51,7 +51,7 @@ struct LaunchRec {
   int count = 0;
   dim3 grid;
   size_t lds = 0;
-  int variant = 0;       // kernel variant (QR: 1 = blocked tall kernel, 2 = k_qr_small, 3 =
+  int variant = 0;       // kernel variant (GEMM: tile shape; QR: 1 = blocked tall kernel, 2 = k_qr_small, 3 =
                          // k_qr_mid (R only); Jacobi: 1 = rows
                          // split between LDS and the work buffer, 2 = top-k SVD through
                          // bidiagonalisation: k_svt_bidiag then k_svd_top)
@@ -178,6 +178,7 @@ size_t push_descs(std::vector<char>* blob, const std::vector<T>& v) {
 // kernel variant an op runs with (part of its bucket key, so that an item
 // runs the same kernel whether it is launched alone or in a batch)
 int op_variant(const Op& op) {
+  if (op.type == OPK_GEMM) return op.i[0] <= 16 ? 1 : op.i[1] <= 16 ? 2 : 0;   // k_gemm tile shape
   if (op.type == OPK_QR) {
     const int64_t m = op.i[0], n = op.i[1], k = std::min(m, n);
     if (m <= QRS_MAXM && n <= QRS_MAXN) return 2;   // k_qr_small
@@ -256,8 +257,9 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             v.push_back(g);
           }
           rec.desc_off = push_descs(blob, v);
-          rec.grid = dim3(unsigned((mN + 63) / 64),
-                          unsigned(std::min<int64_t>(65535, (mM + 63) / 64)), unsigned(v.size()));
+          const int tm = rec.variant == 1 ? 16 : 64, tn = rec.variant == 2 ? 16 : 64;
+          rec.grid = dim3(unsigned((mN + tn - 1) / tn),
+                          unsigned(std::min<int64_t>(65535, (mM + tm - 1) / tm)), unsigned(v.size()));
           break;
         }
         case OPK_PERM: {
@@ -450,14 +452,23 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
   const void* d = desc_dev + r.desc_off;
   dim3 blk(256);
   switch (r.type) {
-    case OPK_GEMM:
-      if (r.prec == PREC_FP64)
-        hipLaunchKernelGGL(k_gemm<PREC_FP64>, r.grid, blk, 0, stream, (const GemmDesc*)d);
-      else if (r.prec == PREC_FP32)
-        hipLaunchKernelGGL(k_gemm<PREC_FP32>, r.grid, blk, 0, stream, (const GemmDesc*)d);
-      else
-        hipLaunchKernelGGL(k_gemm<PREC_BF16X3>, r.grid, blk, 0, stream, (const GemmDesc*)d);
+    case OPK_GEMM: {
+      // variant = tile shape: 0 64x64, 1 16x64 (M <= 16), 2 64x16 (N <= 16)
+      const GemmDesc* gd = (const GemmDesc*)d;
+#define PN_GEMM(PP)                                                                         \
+  if (r.variant == 1) hipLaunchKernelGGL((k_gemm<PP, 1>), r.grid, blk, 0, stream, gd);      \
+  else if (r.variant == 2) hipLaunchKernelGGL((k_gemm<PP, 2>), r.grid, blk, 0, stream, gd); \
+  else hipLaunchKernelGGL((k_gemm<PP, 0>), r.grid, blk, 0, stream, gd);
+      if (r.prec == PREC_FP64) {
+        PN_GEMM(PREC_FP64)
+      } else if (r.prec == PREC_FP32) {
+        PN_GEMM(PREC_FP32)
+      } else {
+        PN_GEMM(PREC_BF16X3)
+      }
+#undef PN_GEMM
       break;
+    }
     case OPK_PERM:
       hipLaunchKernelGGL(k_permute, r.grid, blk, 0, stream, (const PermDesc*)d);
       break;

@@ -1,8 +1,9 @@
 // HIP kernels for the BlockBP boundary-chain engine (gfx950 / CDNA4).
 //
-// * k_gemm<P>: batched complex GEMM on the matrix cores.  One 64x64 output
-//   tile per 256-thread workgroup, four wave64s each owning a 32x32 quadrant
-//   (2x2 MFMA 16x16 tiles).  A complex product is four real MFMA products
+// * k_gemm<P, SH>: batched complex GEMM on the matrix cores.  One 64x64
+//   output tile per 256-thread workgroup, four wave64s each owning a 32x32
+//   quadrant (2x2 MFMA 16x16 tiles); 16x64 or 64x16 tiles for products with
+//   at most 16 rows or columns.  A complex product is four real MFMA products
 //   (re*re - im*im, re*im + im*re).  P selects the arithmetic:
 //     PREC_FP64   v_mfma_f64_16x16x4   (complex128 in, FP64 accumulate)
 //     PREC_FP32   v_mfma_f32_16x16x4   (operands rounded to FP32, FP32 acc)
@@ -59,7 +60,16 @@ __device__ __forceinline__ cplx ld_op(gptr<const cplx> X, int ld, int op, int r,
 }
 
 // ------------------------------------------------------------------ GEMM
-constexpr int GT_M = 64, GT_N = 64;
+// Tile shapes (SH): 0 = 64x64 output tile, four waves of 2x2 16x16 MFMA
+// blocks; 1 = 16x64 for M <= 16, four waves side by side along N, one block
+// each; 2 = 64x16 for N <= 16, four waves along M.  The narrow shapes stop
+// the matrix cores from multiplying padding on products with 16 or fewer rows
+// or columns.
+template <int SH>
+struct GemmTile {
+  static constexpr int TM = SH == 1 ? 16 : 64, TN = SH == 2 ? 16 : 64;
+  static constexpr int IB = SH == 0 ? 2 : 1, JB = SH == 0 ? 2 : 1;   // 16x16 blocks per wave
+};
 
 template <int P>
 struct GemmCfg;
@@ -76,8 +86,10 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* hi, __bf16* lo) {
   *lo = (__bf16)(x - (float)h);
 }
 
-template <int P>
+template <int P, int SH>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs) {
+  constexpr int GT_M = GemmTile<SH>::TM, GT_N = GemmTile<SH>::TN;
+  constexpr int IB = GemmTile<SH>::IB, JB = GemmTile<SH>::JB;
   typedef typename GemmCfg<P>::T T;
   constexpr int TK = GemmCfg<P>::TK;
   constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;
@@ -91,11 +103,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   // M tiles are grid-strided (the grid's y extent is capped at 65535)
   for (int m0 = blockIdx.y * GT_M; m0 < g.M; m0 += gridDim.y * GT_M) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = SH == 0 ? (wave >> 1) * 32 : SH == 2 ? wave * 16 : 0;
+  const int wn = SH == 0 ? (wave & 1) * 32 : SH == 1 ? wave * 16 : 0;
   typedef typename std::conditional<P == PREC_FP64, d4, f4>::type acc_t;
-  acc_t accr[2][2], acci[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
+  acc_t accr[IB][JB], acci[IB][JB];
+  for (int i = 0; i < IB; ++i)
+    for (int j = 0; j < JB; ++j) {
       accr[i][j] = acc_t{0, 0, 0, 0};
       acci[i][j] = acc_t{0, 0, 0, 0};
     }
@@ -150,18 +163,21 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 #pragma unroll
       for (int kk = 0; kk < TK; kk += 4) {
         const int kq = kk + (lane >> 4);
-        T ar[2], ai[2], br[2], bi[2];
+        T ar[IB], ai[IB], br[JB], bi[JB];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < IB; ++i) {
           ar[i] = As_r[kq][wm + i * 16 + (lane & 15)];
           ai[i] = As_i[kq][wm + i * 16 + (lane & 15)];
-          br[i] = Bs_r[kq][wn + i * 16 + (lane & 15)];
-          bi[i] = Bs_i[kq][wn + i * 16 + (lane & 15)];
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < JB; ++j) {
+          br[j] = Bs_r[kq][wn + j * 16 + (lane & 15)];
+          bi[j] = Bs_i[kq][wn + j * 16 + (lane & 15)];
+        }
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+        for (int i = 0; i < IB; ++i)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) {
             if constexpr (P == PREC_FP64) {
               accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], accr[i][j], 0, 0, 0);
               accr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bi[j], accr[i][j], 0, 0, 0);
@@ -178,10 +194,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     } else {
       // split-BF16, three-term products, K = 32 per MFMA
       const int kb = 8 * (lane >> 4);
-      bf8 arh[2], arl[2], aih[2], ail[2], anh[2], anl[2];
-      bf8 brh[2], brl[2], bih[2], bil[2];
+      bf8 arh[IB], arl[IB], aih[IB], ail[IB], anh[IB], anl[IB];
+      bf8 brh[JB], brl[JB], bih[JB], bil[JB];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < IB; ++i) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
           __bf16 h, l;
@@ -190,10 +206,17 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
           split_bf16(As_i[kb + t][wm + i * 16 + (lane & 15)], &h, &l);
           aih[i][t] = h; ail[i][t] = l;
           anh[i][t] = -h; anl[i][t] = -l;
-          split_bf16(Bs_r[kb + t][wn + i * 16 + (lane & 15)], &h, &l);
-          brh[i][t] = h; brl[i][t] = l;
-          split_bf16(Bs_i[kb + t][wn + i * 16 + (lane & 15)], &h, &l);
-          bih[i][t] = h; bil[i][t] = l;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          __bf16 h, l;
+          split_bf16(Bs_r[kb + t][wn + j * 16 + (lane & 15)], &h, &l);
+          brh[j][t] = h; brl[j][t] = l;
+          split_bf16(Bs_i[kb + t][wn + j * 16 + (lane & 15)], &h, &l);
+          bih[j][t] = h; bil[j][t] = l;
         }
       }
 #define PN_MFMA3(acc, xh, xl, yh, yl)                                      \
@@ -201,9 +224,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, yl, acc, 0, 0, 0);     \
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xl, yh, acc, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < JB; ++j) {
           PN_MFMA3(accr[i][j], arh[i], arl[i], brh[j], brl[j]);
           PN_MFMA3(accr[i][j], anh[i], anl[i], bih[j], bil[j]);
           PN_MFMA3(acci[i][j], arh[i], arl[i], bih[j], bil[j]);
@@ -216,9 +239,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   // epilogue: f64 layout row = lane/16 + 4t, f32 layout row = 4(lane/16) + t
   const bool beta0 = (g.beta.re == 0.0 && g.beta.im == 0.0);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JB; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         int rr = (P == PREC_FP64) ? ((lane >> 4) + 4 * t) : (4 * (lane >> 4) + t);
@@ -241,9 +264,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   }
 }
 
-template __global__ void k_gemm<PREC_FP64>(const GemmDesc*);
-template __global__ void k_gemm<PREC_FP32>(const GemmDesc*);
-template __global__ void k_gemm<PREC_BF16X3>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP64, 0>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP32, 0>(const GemmDesc*);
+template __global__ void k_gemm<PREC_BF16X3, 0>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP64, 1>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP32, 1>(const GemmDesc*);
+template __global__ void k_gemm<PREC_BF16X3, 1>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP64, 2>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP32, 2>(const GemmDesc*);
+template __global__ void k_gemm<PREC_BF16X3, 2>(const GemmDesc*);
 
 // --------------------------------------------------------------- permute
 __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ descs) {
