@@ -594,14 +594,13 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
   const cplx x0 = {readlane_d(mine.re, src), readlane_d(mine.im, src)};
   const double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im), nx = sqrt(nx2);
   double tau = 0.0;
-  cplx alpha = {0.0, 0.0}, v0 = x0;
+  cplx ph = {1.0, 0.0}, v0 = x0;
   if (nx > 0.0) {
+    // alpha = -ph nx; ||v||^2 = 2 nx (nx + |x0|), so tau does not wait for v0
     const double iax = ax0 > 0.0 ? svt_rcp(ax0) : 0.0;
-    const cplx ph = ax0 > 0.0 ? cplx{x0.re * iax, x0.im * iax} : cplx{1.0, 0.0};
-    alpha = cplx{-ph.re * nx, -ph.im * nx};
-    v0 = cplx{x0.re - alpha.re, x0.im - alpha.im};
-    const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
-    tau = nv2 > 0.0 ? 2.0 * svt_rcp(nv2) : 0.0;
+    if (ax0 > 0.0) ph = cplx{x0.re * iax, x0.im * iax};
+    tau = svt_rcp(nx * (nx + ax0));
+    v0 = cplx{x0.re + ph.re * nx, x0.im + ph.im * nx};
   }
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
@@ -609,11 +608,10 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
     if (r < QRS_MAXM) Vr[r] = r < j ? cplx{0.0, 0.0} : r == j ? v0 : a[t];
   }
   if (gl == 0) {
+    // |alpha| = nx and its unit phase is -ph (1 for a zero column)
     *tau_o = tau;
-    const double aa = sqrt(alpha.re * alpha.re + alpha.im * alpha.im);
-    const double iaa = aa > 0.0 ? svt_rcp(aa) : 0.0;
-    *phs_o = aa > 0.0 ? cplx{alpha.re * iaa, alpha.im * iaa} : cplx{1.0, 0.0};
-    *alpha_o = cplx{aa * (1.0 / sc), 0.0};              // sc is a power of two
+    *phs_o = nx > 0.0 ? cplx{-ph.re, -ph.im} : cplx{1.0, 0.0};
+    *alpha_o = cplx{nx * (1.0 / sc), 0.0};              // sc is a power of two
   }
 }
 
@@ -1386,12 +1384,13 @@ __device__ __forceinline__ cplx svt_house(cplx x0, double nx2, double thr, doubl
   *tau = 0.0;
   *alpha = x0;
   if (!(nx2 > thr) || !(nx > 0.0)) return x0;
+  // ||v||^2 = |x0 - alpha|^2 + (nx2 - |x0|^2) = 2 nx (nx + |x0|): tau does
+  // not wait for alpha
   const double r = ax0 > 0.0 ? nx / ax0 : 0.0;
+  const double hv = nx * (nx + ax0);
+  *tau = hv > 0.0 ? 1.0 / hv : 0.0;
   *alpha = ax0 > 0.0 ? cplx{-x0.re * r, -x0.im * r} : cplx{-nx, 0.0};
-  const cplx v0 = {x0.re - alpha->re, x0.im - alpha->im};
-  const double nv2 = nx2 - ax0 * ax0 + v0.re * v0.re + v0.im * v0.im;
-  *tau = nv2 > 0.0 ? 2.0 / nv2 : 0.0;
-  return v0;
+  return cplx{x0.re - alpha->re, x0.im - alpha->im};
 }
 
 // Stage 1 (k_svt_bidiag, 512 threads): the matrix stays on chip.  Thread
