@@ -1351,13 +1351,7 @@ __device__ __forceinline__ int svt_count(const double* c2, int N, double x) {
     P = Q;
     Q = R;
   };
-  int i = 0;
-  for (const int r = (N - 1) & 3; i < r; ++i) step(c2[i]);
-  // the next group's coefficients are loaded during the current group
-  double a0 = c2[i], a1 = c2[i + 1], a2 = c2[i + 2], a3 = c2[i + 3];
-  for (; i < N - 1; i += 4) {
-    const int nx = i + 4 < N - 1 ? i + 4 : i;
-    const double n0 = c2[nx], n1 = c2[nx + 1], n2 = c2[nx + 2], n3 = c2[nx + 3];
+  auto group = [&](double a0, double a1, double a2, double a3) {
     step(a0);
     step(a1);
     step(a2);
@@ -1365,10 +1359,20 @@ __device__ __forceinline__ int svt_count(const double* c2, int N, double x) {
     const int e = __builtin_amdgcn_frexp_exp(Q != 0.0 ? Q : P);
     Q = ldexp(Q, -e);
     P = ldexp(P, -e);
-    a0 = n0;
-    a1 = n1;
-    a2 = n2;
-    a3 = n3;
+  };
+  int i = 0;
+  for (const int r = (N - 1) & 3; i < r; ++i) step(c2[i]);
+  for (int g = ((N - 1 - i) >> 2) & 3; g > 0; --g, i += 4) group(c2[i], c2[i + 1], c2[i + 2], c2[i + 3]);
+  // blocks of 16 steps: the block's coefficients are all read first, so the
+  // LDS latency is paid once per block
+  for (; i < N - 1; i += 16) {
+    double c[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) c[q] = c2[i + q];
+    group(c[0], c[1], c[2], c[3]);
+    group(c[4], c[5], c[6], c[7]);
+    group(c[8], c[9], c[10], c[11]);
+    group(c[12], c[13], c[14], c[15]);
   }
   return cnt;
 }
