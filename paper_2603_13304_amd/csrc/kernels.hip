@@ -1601,20 +1601,27 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
         }
       }
       __syncthreads();
+      // the waves' partial row sums are read while the reflector is formed
+      const bool xrow = tid < mp && tid > j;
+      double pr = 0.0, pi = 0.0;
+      cplx aj1 = {0.0, 0.0};
+      if (xrow) {
+        aj1 = xs[tid];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          pr += xpr[w * NR + tid];
+          pi += xpi[w * NR + tid];
+        }
+      }
       const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
       double tau2;
       cplx beta;
       const cplx u0 = svt_house(yR[j + 1], ny2, hthr, &tau2, &beta);
       if (tid == 0) bd[n + j] = cplx{beta.re, -beta.im};
       // ---- rows i > j: a -= tau2 x_i conj(v2), x_i = partial sums + a_{i,j+1} u0
-      if (tau2 != 0.0 && tid < mp && tid > j) {
-        const cplx aj1 = xs[tid];
-        double sr = aj1.re * u0.re - aj1.im * u0.im, si = aj1.re * u0.im + aj1.im * u0.re;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          sr += xpr[w * NR + tid];
-          si += xpi[w * NR + tid];
-        }
+      if (tau2 != 0.0 && xrow) {
+        const double sr = fma(aj1.re, u0.re, fma(-aj1.im, u0.im, pr));
+        const double si = fma(aj1.re, u0.im, fma(aj1.im, u0.re, pi));
         xs[tid] = cplx{tau2 * sr, tau2 * si};
       }
       cplx v2[NS];
