@@ -574,7 +574,10 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
   for (int t = 0; t < 9; ++t)
     if (gl + 16 * t >= j) part += a[t].re * a[t].re + a[t].im * a[t].im;
   double nx2 = group16_sum(part);
-  const double sc = house_rescale(nx2);          // uniform within the group
+  // a tiny column is rescaled by the power of two 2^es (exact; es = 0 when
+  // no rescaling is needed), as house_rescale does
+  const int es = (nx2 > 0.0 && nx2 < 1e-200) ? -ilogb(sqrt(nx2)) : 0;   // uniform within the group
+  const double sc = ldexp(1.0, es);
   if (sc != 1.0) {
     part = 0.0;
 #pragma unroll
@@ -611,7 +614,7 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
     // |alpha| = nx and its unit phase is -ph (1 for a zero column)
     *tau_o = tau;
     *phs_o = nx > 0.0 ? cplx{-ph.re, -ph.im} : cplx{1.0, 0.0};
-    *alpha_o = cplx{nx * (1.0 / sc), 0.0};              // sc is a power of two
+    *alpha_o = cplx{ldexp(nx, -es), 0.0};
   }
 }
 
@@ -675,12 +678,18 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
   cplx q[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) q[t] = cplx{gl + 16 * t == g ? 1.0 : 0.0, 0.0};
-  for (int j = g; j >= 0; --j) {
-    const double tau = tau_s[j];                            // tau = 0 changes nothing
-    cplx v[9];
+  // two reflectors per pass, both read before the first is applied (tau = 0
+  // changes nothing)
+  for (int j = g; j >= 0; j -= 2) {
+    const int j1 = j > 0 ? j - 1 : 0;
+    const double tau = tau_s[j], tau1 = j > 0 ? tau_s[j1] : 0.0;
+    cplx v[9], w[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) v[t] = V[j][gl + 16 * t];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) w[t] = V[j1][gl + 16 * t];
     house_apply(q, v, tau);
+    house_apply(q, w, tau1);
   }
   const cplx ph = phs[g];
 #pragma unroll
