@@ -324,7 +324,7 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             jd.A = resolve(h, op->a); jd.work = resolve(h, op->b); jd.U = resolve(h, op->c);
             jd.sigma = reinterpret_cast<double*>(resolve(h, op->d));
             jd.rows = int(op->i[0]); jd.cols = int(op->i[1]); jd.lda = int(op->i[2]);
-            jd.conjT = int(op->i[3]); jd.keep = int(op->i[4]);
+            jd.conjT = int(op->i[3]); jd.keep = int(op->i[4]); jd.gauge = int(op->i[6]);
             if (rec.variant == 2) {
               // complex Householder bidiagonalisation, 4 x (4 m n^2 - 4 n^3 / 3)
               const double m = jd.rows, n = jd.cols;

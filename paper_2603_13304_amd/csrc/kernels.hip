@@ -2170,6 +2170,48 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
       }
       bsel ^= 1;
     }
+    // column gauge (when asked): the entry of largest modulus, the first row
+    // on ties, made real and positive.  |u_i|^2 is the rounded sum of the
+    // rounded squares, so that ties fall as in a plain evaluation
+    if (act && mine && dsc.gauge) {
+      double best = -1.0;
+      int bi = 0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int i = rl + 16 * t;
+        double q;
+        {
+#pragma clang fp contract(off)
+          q = uc[t].re * uc[t].re + uc[t].im * uc[t].im;
+        }
+        if (i < m && q > best) {
+          best = q;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {                 // within the 16-lane group
+        const double ob = __shfl_xor(best, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      cplx x = uc[0];
+#pragma unroll
+      for (int t = 1; t < 9; ++t)
+        if (t == (bi >> 4)) x = uc[t];
+      const int src = (lane & 48) | (bi & 15);
+      x = cplx{__shfl(x.re, src), __shfl(x.im, src)};
+      const double a = sqrt(x.re * x.re + x.im * x.im);
+      if (a > 0.0) {
+        const cplx ph = {x.re / a, x.im / a};
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+          uc[t] = cplx{uc[t].re * ph.re + uc[t].im * ph.im, uc[t].im * ph.re - uc[t].re * ph.im};
+      }
+    }
     if (act && mine) {
 #pragma unroll
       for (int t = 0; t < 9; ++t) {

@@ -67,6 +67,8 @@ struct JacobiDesc {
   cplx* U;
   double* sigma;
   int rows, cols, lda, conjT, keep;
+  int gauge;    // k_svd_top only: each kept column's entry of largest modulus
+                // (first row on ties) made real and positive
 };
 // k_svt_bidiag followed by k_svd_top take the same descriptor and write the
 // same outputs for keep <= cols <= rows <= 144 through Householder

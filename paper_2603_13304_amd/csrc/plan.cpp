@@ -175,10 +175,12 @@ struct Compiler::Lane {
   // leading `keep` left singular vectors U (rows x keep) and values of the
   // rows x cols matrix A (element (i, c) at A[i*lda + c], conj(A[c*lda + i])
   // with conjT)
-  void jacobi(Ref A, int64_t rows, int64_t cols, int64_t lda, int conjT, int64_t keep, Ref U,
-              Ref sig) {
-    if (rows > kJacobiMaxRows) { err = "Jacobi SVD with more than 144 rows"; return; }
-    if (cols > rows || cols > kJacobiMaxCols) { err = "Jacobi SVD needs cols <= rows"; return; }
+  // with gauge, the top-k kernel also fixes the columns' gauge (as colphase
+  // does); returns whether it did
+  bool jacobi(Ref A, int64_t rows, int64_t cols, int64_t lda, int conjT, int64_t keep, Ref U,
+              Ref sig, bool gauge = false) {
+    if (rows > kJacobiMaxRows) { err = "Jacobi SVD with more than 144 rows"; return false; }
+    if (cols > rows || cols > kJacobiMaxCols) { err = "Jacobi SVD needs cols <= rows"; return false; }
     Op op;
     op.type = OPK_JACOBI;
     // wide blocks with a truncated rank go through bidiagonalisation: its
@@ -191,7 +193,9 @@ struct Compiler::Lane {
     op.b = scratch(top ? svd_top_work_elems(rows, cols, keep) : jacobi_work_elems(rows, cols));
     op.i[0] = rows; op.i[1] = cols; op.i[2] = lda; op.i[3] = conjT; op.i[4] = keep;
     op.i[5] = top ? 1 : 0;
+    op.i[6] = top && gauge ? 1 : 0;
     push(op);
+    return top && gauge;
   }
   void omega(Ref dst, int64_t n, int64_t k, uint64_t prefix, bool sweep_tag) {
     Op op;
@@ -316,10 +320,13 @@ struct Compiler::Lane {
       colphase(Lout, Rout, m, keep, n);
       return 0;
     }
+    // where L is the SVD's U itself, the top-k kernel fixes the gauge before
+    // R = L^H M is formed, so R follows without the colphase pass
+    bool gauged = false;
     if (m >= n && m <= kJacobiMaxRows) {
       // M W = U Sigma directly on the columns of M
       Ref sig = scratch(keep);
-      jacobi(M, m, n, n, 0, keep, Lout, sig);
+      gauged = jacobi(M, m, n, n, 0, keep, Lout, sig, true);
       gemm(Lout, M, Rout, keep, n, m, keep, n, n, OP_C, OP_N, PREC_FP64);
     } else if (m < n) {
       // M^H = Q3 R3, M = R3^H Q3^H: the left singular vectors of M are those
@@ -327,7 +334,7 @@ struct Compiler::Lane {
       Ref R3 = scratch(m * m);
       qr(M, n, m, n, 1, Ref(), R3);
       Ref sig = scratch(keep);
-      jacobi(R3, m, m, m, 1, keep, Lout, sig);
+      gauged = jacobi(R3, m, m, m, 1, keep, Lout, sig, true);
       gemm(Lout, M, Rout, keep, n, m, keep, n, n, OP_C, OP_N, PREC_FP64);
     } else {
       // tall: M = Q R, left singular vectors Q U with U those of R (n x n)
@@ -338,7 +345,7 @@ struct Compiler::Lane {
       gemm(Q, U, Lout, m, keep, n, n, keep, keep, OP_N, OP_N, PREC_FP64);
       gemm(U, R, Rout, keep, n, n, keep, n, n, OP_C, OP_N, PREC_FP64);
     }
-    colphase(Lout, Rout, m, keep, n);
+    if (!gauged) colphase(Lout, Rout, m, keep, n);
     return 0;
   }
 
