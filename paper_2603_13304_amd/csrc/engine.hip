@@ -296,6 +296,7 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             q.A = resolve(h, op->a); q.work = resolve(h, op->b);
             q.Q = resolve(h, op->c); q.R = resolve(h, op->d);
             q.m = int(op->i[0]); q.n = int(op->i[1]); q.lda = int(op->i[2]); q.conjT = int(op->i[3]);
+            q.qh = int(op->i[4]);
             double m = q.m, n = q.n, k = std::min(q.m, q.n);
             // Householder R (complex: 8 flops per MAC), plus the same again
             // for the explicit Q

@@ -516,6 +516,14 @@ __device__ __forceinline__ void qr_body(const QrDesc& d, PW W, PW Qt, double* ta
     }
     __syncthreads();
   }
+  if (d.qh) {
+    // Q^H shares the column-major order of Qt: contiguous on both sides
+    for (int64_t e = tid; e < (int64_t)m * k; e += 256) {
+      const cplx ph = phs[e / m], x = Qt[e];
+      Qout[e] = cplx{x.re * ph.re - x.im * ph.im, -(x.re * ph.im + x.im * ph.re)};
+    }
+    return;
+  }
   for (int64_t e = tid; e < (int64_t)m * k; e += 256) {
     int r = (int)(e / k), c = (int)(e % k);
     cplx ph = phs[c], x = Qt[(int64_t)c * m + r];
@@ -695,7 +703,10 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     const int r = gl + 16 * t;
-    if (r < m) Qout[(int64_t)r * k + g] = cplx{q[t].re * ph.re - q[t].im * ph.im, q[t].re * ph.im + q[t].im * ph.re};
+    if (r >= m) continue;
+    const cplx x = {q[t].re * ph.re - q[t].im * ph.im, q[t].re * ph.im + q[t].im * ph.re};
+    if (d.qh) Qout[(int64_t)g * m + r] = cplx{x.re, -x.im};
+    else Qout[(int64_t)r * k + g] = x;
   }
 }
 
@@ -1049,6 +1060,13 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qr_tall(const QrDesc* __restric
     for (int c = p0 + wave; c < k; c += NW)
       qrt_apply<false>(Qt + (int64_t)c * m + p0, P, ldp, T, mr, pb, lane);
     __syncthreads();
+  }
+  if (d.qh) {
+    for (int64_t e = tid; e < (int64_t)m * k; e += QRT_THREADS) {
+      const cplx ph = phs[e / m], x = Qt[e];
+      d.Q[e] = cplx{x.re * ph.re - x.im * ph.im, -(x.re * ph.im + x.im * ph.re)};
+    }
+    return;
   }
   for (int64_t e = tid; e < (int64_t)m * k; e += QRT_THREADS) {
     const int r = (int)(e / k), c = (int)(e % k);

@@ -50,6 +50,7 @@ struct QrDesc {
   cplx* Q;
   cplx* R;
   int m, n, lda, conjT;
+  int qh;       // Q written as Q^H (k x m, row-major) instead of Q (m x k)
 };
 
 // One-sided Jacobi SVD of the rows x cols matrix A with element (i, c) at

@@ -163,13 +163,14 @@ struct Compiler::Lane {
     for (size_t k = 0; k < od.size(); ++k) { op.i[2 + k] = od[k]; op.i[18 + k] = os[k]; }
     push(op);
   }
-  // Q may be an invalid Ref: only R is produced
-  void qr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R) {
+  // Q may be an invalid Ref: only R is produced; with qh, Q^H (k x m) is
+  // written in place of Q
+  void qr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh = false) {
     if (std::min(m, n) > 256) { err = "QR width above 256"; return; }
     Op op;
     op.type = OPK_QR;
     op.a = A; op.b = scratch(m * (n + (Q.valid() ? std::min(m, n) : 0))); op.c = Q; op.d = R;
-    op.i[0] = m; op.i[1] = n; op.i[2] = lda; op.i[3] = conjT;
+    op.i[0] = m; op.i[1] = n; op.i[2] = lda; op.i[3] = conjT; op.i[4] = qh ? 1 : 0;
     push(op);
   }
   // leading `keep` left singular vectors U (rows x keep) and values of the
@@ -266,11 +267,9 @@ struct Compiler::Lane {
     CSite& A = ch[j];
     CSite& B = ch[j - 1];
     int64_t m = int64_t(A.P) * A.r, n = A.l, k = std::min(m, n);
-    // A^H (m x n) = Q' R'  ->  A = R'^H Q'^H
-    Ref Qp = scratch(m * k), Rp = scratch(k * n);
-    qr(A.buf, m, n, m, 1, Qp, Rp);
-    Ref NA = chain_alloc(k * m);
-    perm(Qp, NA, {int(m), int(k)}, {1, 0}, 1);
+    // A^H (m x n) = Q' R'  ->  A = R'^H Q'^H; the QR writes Q'^H directly
+    Ref NA = chain_alloc(k * m), Rp = scratch(k * n);
+    qr(A.buf, m, n, m, 1, NA, Rp, true);
     Ref NB = chain_alloc(int64_t(B.l) * B.P * k);
     gemm(B.buf, Rp, NB, int64_t(B.l) * B.P, k, n, n, n, k, OP_N, OP_C, PREC_FP64);
     A.buf = NA; A.l = int(k);
