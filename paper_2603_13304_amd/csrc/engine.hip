@@ -247,6 +247,12 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             g.opA = int(op->i[6]); g.opB = int(op->i[7]);
             g.alpha = cplx{op->x[0], op->x[1]};
             g.beta = cplx{op->x[2], op->x[3]};
+            g.sc_n = int(op->i[10]); g.sc_nr = int(op->i[11]); g.sc_conj = int(op->i[12]);
+            for (int k = 0; k < GEMM_SC_MAX; ++k) {
+              g.sc_dim[k] = k < g.sc_n ? int(op->i[16 + k]) : 1;
+              g.sc_inv[k] = 1.0 / g.sc_dim[k];
+              g.sc_ds[k] = k < g.sc_n ? op->i[32 + k] : 0;
+            }
             mM = std::max<int64_t>(mM, g.M);
             mN = std::max<int64_t>(mN, g.N);
             double f = 8.0 * double(g.M) * double(g.N) * double(g.K);

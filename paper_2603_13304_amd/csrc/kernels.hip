@@ -86,6 +86,21 @@ __device__ __forceinline__ void split_bf16(float x, __bf16* hi, __bf16* lo) {
   *lo = (__bf16)(x - (float)h);
 }
 
+// Offset contributed by index x of a scatter store, split over axes
+// [k0, k1) (last fastest).  The quotients come from the double reciprocal:
+// for dims up to 2^16 and x < 2^31, x + 1/2 keeps every floor exact.
+__device__ __forceinline__ int64_t gemm_sc_offset(const GemmDesc* __restrict__ g, int k0, int k1,
+                                                  int x) {
+  int64_t off = 0;
+  if (k1 <= k0) return 0;
+  for (int k = k1 - 1; k > k0; --k) {
+    const int q = (int)floor(((double)x + 0.5) * g->sc_inv[k]);
+    off += (int64_t)(x - q * g->sc_dim[k]) * g->sc_ds[k];
+    x = q;
+  }
+  return off + (int64_t)x * g->sc_ds[k0];
+}
+
 template <int P, int SH>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs) {
   constexpr int GT_M = GemmTile<SH>::TM, GT_N = GemmTile<SH>::TN;
@@ -237,6 +252,35 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     __syncthreads();
   }
   // epilogue: f64 layout row = lane/16 + 4t, f32 layout row = 4(lane/16) + t
+  if (g.sc_n > 0) {
+    // transposed store: each row and column offset is formed once
+    const GemmDesc* const gp = descs + blockIdx.z;
+    int64_t co[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const int c = n0 + wn + j * 16 + (lane & 15);
+      co[j] = c < g.N ? gemm_sc_offset(gp, g.sc_nr, g.sc_n, c) : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < IB; ++i)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int rr = (P == PREC_FP64) ? ((lane >> 4) + 4 * t) : (4 * (lane >> 4) + t);
+        const int r = m0 + wm + i * 16 + rr;
+        if (r >= g.M) continue;
+        const int64_t ro = gemm_sc_offset(gp, 0, g.sc_nr, r);
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+          const int c = n0 + wn + j * 16 + (lane & 15);
+          if (c >= g.N) continue;
+          const double vr = (double)accr[i][j][t], vi = (double)acci[i][j][t];
+          cplx out = {g.alpha.re * vr - g.alpha.im * vi, g.alpha.re * vi + g.alpha.im * vr};
+          if (g.sc_conj) out.im = -out.im;
+          Cg[ro + co[j]] = out;
+        }
+      }
+    continue;
+  }
   const bool beta0 = (g.beta.re == 0.0 && g.beta.im == 0.0);
 #pragma unroll
   for (int i = 0; i < IB; ++i)

@@ -16,6 +16,8 @@ struct cplx {
 enum GemmOp { OP_N = 0, OP_T = 1, OP_C = 2 };        // op(X) = X, X^T, X^H
 enum Precision { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2 };
 
+constexpr int GEMM_SC_MAX = 12;   // scatter-store axes
+
 // C = alpha * op(A) * op(B) + beta * C, row-major, op(A) is M x K, op(B) K x N.
 struct GemmDesc {
   const cplx* A;
@@ -25,6 +27,15 @@ struct GemmDesc {
   int lda, ldb, ldc;
   int opA, opB;
   cplx alpha, beta;
+  // Scatter store (sc_n > 0, beta = 0): the output is written already
+  // transposed.  Element (r, c) goes to C + off_r(r) + off_c(c); the first
+  // sc_nr axes split r, the other sc_n - sc_nr split c (row-major, last axis
+  // fastest), axis k adding idx_k * sc_ds[k] (sc_inv[k] = 1 / sc_dim[k]);
+  // sc_conj stores the conjugate.
+  int sc_n, sc_nr, sc_conj;
+  int sc_dim[GEMM_SC_MAX];
+  double sc_inv[GEMM_SC_MAX];
+  int64_t sc_ds[GEMM_SC_MAX];
 };
 
 // dst[o] = src[sum_k idx_k(o) * stride[k]] for o over the row-major output

@@ -785,6 +785,128 @@ std::pair<Ref, Ref> Compiler::ensure_smat(int tensor, const std::vector<int>& in
   return smat[k];
 }
 
+namespace {
+
+bool same_ref(const Ref& x, const Ref& y) { return x.region == y.region && x.off == y.off; }
+
+// Does op q touch buffer r, and only as an output (so that the contents it
+// held before are dead)?  Every reference in a plan names a whole buffer.
+// Returns 0: not touched, 1: written only, 2: read.
+int touches(const Op& q, const Ref& r) {
+  const bool a = same_ref(q.a, r), b = same_ref(q.b, r), c = same_ref(q.c, r),
+             d = same_ref(q.d, r);
+  bool ref = false;
+  for (const Ref& x : q.refs) ref = ref || same_ref(x, r);
+  if (!(a || b || c || d || ref)) return 0;
+  if (ref) return 2;
+  switch (q.type) {
+    case OPK_GEMM: return (a || b || (c && (q.x[2] != 0.0 || q.x[3] != 0.0))) ? 2 : 1;
+    case OPK_PERM: return a ? 2 : 1;
+    case OPK_PAD: return (a || q.i[7] != 0) ? 2 : 1;   // modes 1, 2 keep the rest of dst
+    case OPK_QR: case OPK_JACOBI: return a ? 2 : 1;
+    case OPK_OMEGA: return 1;
+    default: return 2;
+  }
+}
+
+// [lo, hi) element range of a GEMM operand stored rows x cols with leading
+// dimension ld, or transposed
+void operand_range(const Ref& x, bool trans, int64_t rows, int64_t cols, int64_t ld,
+                   int64_t* lo, int64_t* hi) {
+  *lo = x.off;
+  *hi = x.off + (trans ? (cols - 1) * ld + rows : (rows - 1) * ld + cols);
+}
+
+// A transpose that only reads the output of the GEMM just before it is
+// folded into that GEMM's store: the GEMM writes the transposed layout
+// directly (one launch and one pass over the data fewer).  Applies when the
+// GEMM writes a dense lane buffer without accumulating, the destination
+// does not overlap the GEMM's operands, and no later op of the lane reads
+// the untransposed buffer.
+void fuse_gemm_perm(LaneOps& L) {
+  auto& ops = L.ops;
+  std::vector<bool> drop(ops.size(), false);
+  for (size_t p = 1; p < ops.size(); ++p) {
+    Op& g = ops[p - 1].second;
+    const Op& t = ops[p].second;
+    if (t.type != OPK_PERM || g.type != OPK_GEMM || drop[p - 1] || g.i[10] != 0) continue;
+    if (!same_ref(g.c, t.a) || g.c.region < RG_LANE0) continue;
+    if (g.x[2] != 0.0 || g.x[3] != 0.0) continue;
+    const int64_t M = g.i[0], N = g.i[1], K = g.i[2];
+    if (g.i[5] != N || M < 1 || N < 1) continue;
+    // the transpose: output axis k has extent od[k] and source stride os[k]
+    const int n = int(t.i[0]);
+    struct Ax { int64_t dim, src, dst; };
+    std::vector<Ax> ax(n);
+    int64_t total = 1;
+    for (int k = n - 1; k >= 0; --k) {
+      ax[k] = Ax{t.i[2 + k], t.i[18 + k], total};
+      total *= ax[k].dim;
+    }
+    if (total != M * N) continue;
+    // source order (slowest first) must be a dense mixed radix
+    std::sort(ax.begin(), ax.end(), [](const Ax& x, const Ax& y) { return x.src > y.src; });
+    bool ok = true;
+    for (int k = 0; k < n; ++k)
+      ok = ok && ax[k].src == (k + 1 < n ? ax[k + 1].src * ax[k + 1].dim : 1);
+    if (!ok) continue;
+    // split at the column extent N: axes below it index the GEMM column
+    std::vector<Ax> rows, cols;
+    int64_t prod = 1;
+    for (int k = n - 1; k >= 0; --k) {
+      const Ax& x = ax[k];
+      if (prod == N) { rows.insert(rows.begin(), x); continue; }
+      if (prod * x.dim <= N) { cols.insert(cols.begin(), x); prod *= x.dim; continue; }
+      if (N % prod != 0 || x.dim % (N / prod) != 0) { ok = false; break; }
+      const int64_t f = N / prod;
+      cols.insert(cols.begin(), Ax{f, x.src, x.dst});
+      rows.insert(rows.begin(), Ax{x.dim / f, x.src * f, x.dst * f});
+      prod = N;
+    }
+    if (!ok || prod != N) continue;
+    if (int(rows.size() + cols.size()) > GEMM_SC_MAX) continue;
+    for (const Ax& x : rows) ok = ok && x.dim <= 65536;
+    for (const Ax& x : cols) ok = ok && x.dim <= 65536;
+    if (!ok) continue;
+    // destination apart from the operands
+    if (t.b.region == g.a.region || t.b.region == g.b.region) {
+      int64_t lo, hi;
+      const int64_t dlo = t.b.off, dhi = t.b.off + M * N;
+      if (t.b.region == g.a.region) {
+        operand_range(g.a, g.i[6] != OP_N, M, K, g.i[3], &lo, &hi);
+        if (lo < dhi && dlo < hi) continue;
+      }
+      if (t.b.region == g.b.region) {
+        operand_range(g.b, g.i[7] != OP_N, K, N, g.i[4], &lo, &hi);
+        if (lo < dhi && dlo < hi) continue;
+      }
+    }
+    // the untransposed buffer must be dead after the transpose
+    int use = 0;
+    for (size_t q = p + 1; q < ops.size() && use == 0; ++q) use = touches(ops[q].second, t.a);
+    if (use == 2) continue;
+    int k = 0;
+    for (const Ax& x : rows) { g.i[16 + k] = x.dim; g.i[32 + k] = x.dst; ++k; }
+    for (const Ax& x : cols) { g.i[16 + k] = x.dim; g.i[32 + k] = x.dst; ++k; }
+    g.i[10] = k;
+    g.i[11] = int64_t(rows.size());
+    g.i[12] = t.i[1];
+    g.c = t.b;
+    drop[p] = true;
+  }
+  // compact in place (an element is never moved onto itself: a self-moved
+  // vector comes out empty)
+  size_t w = 0;
+  for (size_t p = 0; p < ops.size(); ++p) {
+    if (drop[p]) continue;
+    if (w != p) ops[w] = std::move(ops[p]);
+    ++w;
+  }
+  ops.resize(w);
+}
+
+}  // namespace
+
 bool Compiler::build_sweep(int parity, Plan* out) {
   const Problem& P = prob;
   int nm = int(P.msg_keys.size());
@@ -881,6 +1003,7 @@ bool Compiler::build_sweep(int parity, Plan* out) {
       }
     }
     if (!L.err.empty()) { error = L.err; return false; }
+    fuse_gemm_perm(out->lanes[m]);
     lane_size[2 * m] = std::max(lane_size[2 * m], L.chain_top);
     lane_size[2 * m + 1] = std::max(lane_size[2 * m + 1], L.scratch_max);
   }
@@ -1008,6 +1131,7 @@ bool Compiler::build_expect(int parity, const std::vector<std::pair<int, int>>& 
     (*carry_order)[bi] = order;
     (*rho_off)[bi] = roff;
     if (!L.err.empty()) { error = L.err; return false; }
+    fuse_gemm_perm(out->lanes[bi]);
     lane_size[2 * bi] = std::max(lane_size[2 * bi], L.chain_top);
     lane_size[2 * bi + 1] = std::max(lane_size[2 * bi + 1], L.scratch_max);
   }
