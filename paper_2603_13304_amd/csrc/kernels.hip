@@ -253,32 +253,37 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   }
   // epilogue: f64 layout row = lane/16 + 4t, f32 layout row = 4(lane/16) + t
   if (g.sc_n > 0) {
-    // transposed store: each row and column offset is formed once
+    // transposed store: the tile's row and column offsets are formed once,
+    // one per thread, and shared through LDS
+    __shared__ int64_t sc_ro[GT_M], sc_co[GT_N];
     const GemmDesc* const gp = descs + blockIdx.z;
-    int64_t co[JB];
-#pragma unroll
-    for (int j = 0; j < JB; ++j) {
-      const int c = n0 + wn + j * 16 + (lane & 15);
-      co[j] = c < g.N ? gemm_sc_offset(gp, g.sc_nr, g.sc_n, c) : 0;
+    if (tid < GT_M) {
+      const int r = m0 + tid;
+      sc_ro[tid] = r < g.M ? gemm_sc_offset(gp, 0, g.sc_nr, r) : 0;
+    } else if (tid >= 128 && tid < 128 + GT_N) {
+      const int c = n0 + tid - 128;
+      sc_co[tid - 128] = c < g.N ? gemm_sc_offset(gp, g.sc_nr, g.sc_n, c) : 0;
     }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < IB; ++i)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int rr = (P == PREC_FP64) ? ((lane >> 4) + 4 * t) : (4 * (lane >> 4) + t);
-        const int r = m0 + wm + i * 16 + rr;
-        if (r >= g.M) continue;
-        const int64_t ro = gemm_sc_offset(gp, 0, g.sc_nr, r);
+        const int rl = wm + i * 16 + rr;
+        if (m0 + rl >= g.M) continue;
+        const int64_t ro = sc_ro[rl];
 #pragma unroll
         for (int j = 0; j < JB; ++j) {
-          const int c = n0 + wn + j * 16 + (lane & 15);
-          if (c >= g.N) continue;
+          const int cl = wn + j * 16 + (lane & 15);
+          if (n0 + cl >= g.N) continue;
           const double vr = (double)accr[i][j][t], vi = (double)acci[i][j][t];
           cplx out = {g.alpha.re * vr - g.alpha.im * vi, g.alpha.re * vi + g.alpha.im * vr};
           if (g.sc_conj) out.im = -out.im;
-          Cg[ro + co[j]] = out;
+          Cg[ro + sc_co[cl]] = out;
         }
       }
+    __syncthreads();   // the offsets are rewritten by the next M tile
     continue;
   }
   const bool beta0 = (g.beta.re == 0.0 && g.beta.im == 0.0);
