@@ -1682,12 +1682,26 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
       double pr = 0.0, pi = 0.0;
       cplx aj1 = {0.0, 0.0};
       if (xrow) {
+        // all 17 loads are issued before the first add (under register
+        // pressure the scheduler would otherwise wait on each in turn)
+        double a[NW], b[NW];
         aj1 = xs[tid];
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
-          pr += xpr[w * NR + tid];
-          pi += xpi[w * NR + tid];
+          a[w] = xpr[w * NR + tid];
+          b[w] = xpi[w * NR + tid];
         }
+        __builtin_amdgcn_sched_group_barrier(0x0100, 2 * NW + 1, 0);   // DS reads
+        __builtin_amdgcn_sched_group_barrier(0x0002, 2 * NW - 2, 0);   // VALU adds
+#pragma unroll
+        for (int h = NW / 2; h > 0; h >>= 1)
+#pragma unroll
+          for (int w = 0; w < h; ++w) {
+            a[w] += a[w + h];
+            b[w] += b[w + h];
+          }
+        pr = a[0];
+        pi = b[0];
       }
       const double ny2 = group16_sum(rl < NW ? red[rl] : 0.0);
       double tau2;
