@@ -1533,8 +1533,13 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
     };
     // LDS element of row slot a (index clamped in range for every lane;
     // padded row slots read 0)
+    // one index form for reads and writes, so that the compiler can tell
+    // the rows of a slot apart
+    auto lds_idx = [&](int gmask, int a) {
+      return (cg & gmask) * SVT_MAXN + (a + r < 9 ? rb + 16 * a : 0);
+    };
     auto lds_at = [&](const cplx* base, int gmask, int a) -> cplx {
-      cplx x = base[(cg & gmask) * SVT_MAXN + (a + r < 9 ? rb + 16 * a : 0)];
+      cplx x = base[lds_idx(gmask, a)];
       if (a + r >= 9) x = cplx{0.0, 0.0};
       return x;
     };
@@ -1547,8 +1552,8 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
       return x;
     };
     auto put = [&](int a, int b, cplx x) {
-      if (b == 0) { if (a + r < 9) xl[cg * SVT_MAXN + rb + 16 * a] = x; }
-      else if (b == 4) { if (a + r < 9) xa[cg * SVT_MAXN + rb + 16 * a] = x; }
+      if (b == 0) { if (a + r < 9) xl[lds_idx(31, a)] = x; }
+      else if (b == 4) { if (a + r < 9) xa[lds_idx(15, a)] = x; }
       else if (b == 1) A[a][0] = x;
       else if (b == 2) A[a][1] = x;
       else A[a][2] = x;
@@ -1734,12 +1739,17 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
 #pragma unroll
         for (int b = 0; b < NS; ++b) {
           if (!live(b)) continue;
+          // every row of the slot is read before the first write back (the
+          // LDS slots' reads and writes use different index forms, so they
+          // would otherwise be kept in order, one round trip per row)
+          cplx y[9];
+#pragma unroll
+          for (int a = 0; a < NA; ++a) y[a] = get(a, b);
 #pragma unroll
           for (int a = 0; a < NA; ++a) {
-            cplx y = get(a, b);
-            y.re = fma(-x[a].re, v2[b].re, fma(-x[a].im, v2[b].im, y.re));   // x conj(v2)
-            y.im = fma(-x[a].im, v2[b].re, fma(x[a].re, v2[b].im, y.im));
-            put(a, b, y);
+            y[a].re = fma(-x[a].re, v2[b].re, fma(-x[a].im, v2[b].im, y[a].re));   // x conj(v2)
+            y[a].im = fma(-x[a].im, v2[b].re, fma(x[a].re, v2[b].im, y[a].im));
+            put(a, b, y[a]);
           }
         }
       }
