@@ -626,14 +626,17 @@ constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
 // from j on may be left rescaled.
 __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, int lane, cplx* Vr,
                                                    double* tau_o, cplx* phs_o, cplx* alpha_o) {
-  double part = 0.0;
+  // three partial sums keep the dependent chain short
+  double p3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < 9; ++t)
-    if (gl + 16 * t >= j) part += a[t].re * a[t].re + a[t].im * a[t].im;
+    if (gl + 16 * t >= j) p3[t % 3] = fma(a[t].re, a[t].re, fma(a[t].im, a[t].im, p3[t % 3]));
+  double part = p3[0] + p3[1] + p3[2];
   double nx2 = group16_sum(part);
-  // a tiny column is rescaled by the power of two 2^es (exact; es = 0 when
-  // no rescaling is needed), as house_rescale does
-  const int es = (nx2 > 0.0 && nx2 < 1e-200) ? -ilogb(sqrt(nx2)) : 0;   // uniform within the group
+  // a tiny column is rescaled by the power of two 2^es that brings its
+  // squared norm into [1/2, 2) (exact; es = 0 when no rescaling is needed),
+  // taken from the exponent of nx2 alone
+  const int es = (nx2 > 0.0 && nx2 < 1e-200) ? -(__builtin_amdgcn_frexp_exp(nx2) >> 1) : 0;
   const double sc = ldexp(1.0, es);
   if (sc != 1.0) {
     part = 0.0;
