@@ -54,7 +54,8 @@ struct LaunchRec {
   int variant = 0;       // kernel variant (GEMM: tile shape; QR: 1 = blocked tall kernel, 2 = k_qr_small, 3 =
                          // k_qr_mid (R only); Jacobi: 1 = rows
                          // split between LDS and the work buffer, 2 = top-k SVD through
-                         // bidiagonalisation: k_svt_bidiag then k_svd_top)
+                         // bidiagonalisation: k_svt_bidiag, k_svd_top, k_svd_back)
+  int aux = 0;           // top-k SVD: the largest kept count (k_svd_back's grid)
   double gemm_flops = 0.0, contraction_flops = 0.0;
   double flops = 0.0;    // algorithmic flops of the launch (8 per complex MAC)
   double bytes = 0.0;    // algorithmic bytes moved (operands read once, results written once)
@@ -346,6 +347,7 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
               rec.flops += 0.5 * jd.cols * (jd.cols - 1.0) * 24.0 * jd.rows;
             }
             rec.bytes += 16.0 * (double(jd.rows) * jd.cols + double(jd.rows) * jd.keep);
+            rec.aux = std::max(rec.aux, jd.keep);
             v.push_back(jd);
           }
           rec.desc_off = push_descs(blob, v);
@@ -494,8 +496,11 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
       if (r.variant == 2) {
         if (part != 1)
           hipLaunchKernelGGL(k_svt_bidiag, r.grid, dim3(SVB_THREADS), 0, stream, (const JacobiDesc*)d);
-        if (part != 0)
+        if (part != 0) {
           hipLaunchKernelGGL(k_svd_top, r.grid, dim3(SVT_THREADS), 0, stream, (const JacobiDesc*)d);
+          const dim3 gb(unsigned((r.aux + SVK_VALS - 1) / SVK_VALS), r.grid.x);
+          hipLaunchKernelGGL(k_svd_back, gb, dim3(256), 0, stream, (const JacobiDesc*)d);
+        }
       }
       else if (r.variant)
         hipLaunchKernelGGL(k_jacobi<true>, r.grid, dim3(JAC_THREADS), r.lds, stream,

@@ -1396,8 +1396,9 @@ template __global__ void k_jacobi<true>(const JacobiDesc*);
 //      singular vector u of B';
 //   4. U = Q_L D_L u through the stored reflectors.
 // Singular values at or below 1e-15 ||A||_F give zero columns, as k_jacobi.
-// Step 1 is its own kernel (k_svt_bidiag, the matrix held on chip); steps 2-4
-// run in k_svd_top on what it leaves in the work buffer.
+// Step 1 is its own kernel (k_svt_bidiag, the matrix held on chip); steps 2
+// and 3 run in k_svd_top on what it leaves in the work buffer, and step 4 in
+// k_svd_back (several workgroups per block).
 constexpr int SVT_THREADS = 1024;
 constexpr int SVT_MAXN = 144;          // rows and cols limit, as k_jacobi
 constexpr int SVT_ITERS = 3;           // inverse iteration steps
@@ -1492,6 +1493,13 @@ __host__ __device__ inline int64_t svt_bd_off(int64_t rows, int64_t cols) {
 __host__ __device__ inline int64_t svt_pv_off(int64_t rows, int64_t cols) {
   return svt_bd_off(rows, cols) + 3 * cols + 2;
 }
+// the unit phases D_L of the real bidiagonal (cols complex), after the
+// per-value vectors
+__host__ __device__ inline int64_t svt_ph_off(int64_t rows, int64_t cols, int64_t keep) {
+  return svt_pv_off(rows, cols) + ((2 * cols + 2 * rows) * keep + 1) / 2;
+}
+constexpr int SVK_VALS = 4;     // k_svd_back: values per workgroup (one wave each)
+constexpr int SVK_CH = 16;      // k_svd_back: reflectors per LDS chunk
 
 // One block of 16 bidiagonalisation steps (steps j0 .. j0+15) after r row
 // shifts, with NA = nt - r live row slots: every row-slot loop has a
@@ -1567,7 +1575,7 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
       const int bj = s == 0 ? 0 : 1;               // column slot of column j
       // ---- left reflector from column j (lanes cg == j % 32), rows j..m-1
       if (cg == (j & 31)) {
-        double part = 0.0;
+        double p3[3] = {0.0, 0.0, 0.0};   // three partial sums: a short chain
         cplx head = {0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < NA; ++a) {
@@ -1577,9 +1585,9 @@ __device__ __forceinline__ void svb_block(cplx (&A)[9][3], const SvbCtx& c, int 
           if (i < j || i >= m) v = cplx{0.0, 0.0};
           uL[i] = v;
           if (i > j && i < m) W[(int64_t)j * mp + i] = v;
-          part = fma(v.re, v.re, fma(v.im, v.im, part));
+          p3[a % 3] = fma(v.re, v.re, fma(v.im, v.im, p3[a % 3]));
         }
-        const double nx2 = group16_sum(part);
+        const double nx2 = group16_sum(p3[0] + p3[1] + p3[2]);
         // only the group of column j is active here: its lanes share lane & 48
         const int src = __builtin_amdgcn_readfirstlane(lane & 48) | jj;
         const cplx x0 = {readlane_d(head.re, src), readlane_d(head.im, src)};
@@ -1858,7 +1866,7 @@ __global__ __launch_bounds__(SVB_THREADS) void k_svt_bidiag(const JacobiDesc* __
 #undef SVB_BLOCK
 }
 
-// Stages 2-4 on the bidiagonal and reflectors written by k_svt_bidiag.
+// Stages 2 and 3 on the bidiagonal written by k_svt_bidiag.
 __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __restrict__ descs) {
   const JacobiDesc dsc = descs[blockIdx.x];
   const int m = dsc.rows, n = dsc.cols, k = dsc.keep, N = 2 * n;
@@ -2194,126 +2202,169 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
     }
     __syncthreads();
   }
-  // ---- 4. U = Q_L D_L u: 16 lanes per value (lane r of the group holds rows
-  // r + 16 t, t < nt), four values per wave.  The reflectors pass through two
-  // LDS chunks of CH: while the waves holding values apply one chunk, the
-  // other waves load the next (with every wave busy, the chunks are loaded
-  // in turn)
-  constexpr int CH = 32;                                // reflectors per chunk
-  static_assert(2 * CH * SVT_MAXN * 2 <= SVT_BATCH * (4 * 2 * SVT_MAXN + 2), "two chunks fit");
-  cplx* const chunk0 = reinterpret_cast<cplx*>(iib);    // [c][row], rows 0..mp-1
-  const int g16 = lane >> 4, rl = lane & 15;
-  for (int vb = 0; vb < k; vb += 4 * NW) {
-    const int v = vb + 4 * wave + g16;
-    const bool act = vb + 4 * wave < k;                 // wave-uniform
-    const bool mine = v < k;                            // uniform in the 16-lane group
-    const int wa = (min(k - vb, 4 * NW) + 3) / 4;       // waves holding values
-    bool zero = true;
-    cplx uc[9];
+  // the values (zero at or below the noise floor) and the unit phases D_L
+  // for k_svd_back
+  const gptr<cplx> php = to_global(dsc.work + svt_ph_off(m, n, k));
+  for (int v = tid; v < k; v += SVT_THREADS) sgout[v] = sig[v] * sig[v] <= floor2 ? 0.0 : sig[v];
+  for (int j = tid; j < n; j += SVT_THREADS) php[j] = pL[j];
+}
+
+// Stage 4 of the top-k SVD, U = Q_L D_L u, one wave per kept value (lane r
+// holds rows r + 64 t), SVK_VALS values per workgroup, so that the values of
+// one block spread over several CUs.  The left reflectors pass through LDS
+// in chunks of SVK_CH, double-buffered: the next chunk's global loads are in
+// flight while the current chunk is applied.
+__global__ __launch_bounds__(256) void k_svd_back(const JacobiDesc* __restrict__ descs) {
+  const JacobiDesc dsc = descs[blockIdx.y];
+  const int m = dsc.rows, n = dsc.cols, k = dsc.keep;
+  if (n > SVT_MAXN || m > SVT_MAXN || n > m || k > n || n < 1) return;   // excluded by the plan
+  const int v0 = blockIdx.x * SVK_VALS;
+  if (v0 >= k) return;                                  // uniform: the grid covers the largest keep
+  const int nt = (m + 15) / 16, mp = nt * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int v = v0 + wave;
+  const bool mine = v < k;                              // wave-uniform
+  const gptr<const cplx> W = to_global(dsc.work);      // reflectors, mp x n column-major
+  const gptr<const cplx> bd = W + svt_bd_off(m, n);
+  const gptr<const double> pv = to_global(reinterpret_cast<const double*>(dsc.work + svt_pv_off(m, n)));
+  const gptr<const cplx> php = W + svt_ph_off(m, n, k);
+  const gptr<cplx> Uout = to_global(dsc.U);
+  const gptr<const double> sgv = to_global(dsc.sigma);
+  __shared__ cplx chb[2][SVK_CH * SVT_MAXN];             // [c][row], rows 0..mp-1
+  __shared__ double tau_s[SVT_MAXN];
+  for (int j = tid; j < n; j += 256) tau_s[j] = bd[2 * n + j].re;
+  constexpr int T = 3;                                  // rows per lane: 64 * 3 >= SVT_MAXN
+  constexpr int E = SVK_CH * SVT_MAXN / 256;            // chunk elements per thread
+  static_assert(E * 256 == SVK_CH * SVT_MAXN, "chunk split");
+  // u = D_L z_u / ||z_u|| (the u half of the Golub-Kahan eigenvector)
+  cplx uc[T];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) uc[t] = cplx{0.0, 0.0};
-    if (act && mine) {
-      const gptr<const double> z = pv + (int64_t)v * svt_stride(m, n);
-      zero = sig[v] * sig[v] <= floor2;
-      double s = 0.0;
+  for (int t = 0; t < T; ++t) uc[t] = cplx{0.0, 0.0};
+  if (mine) {
+    const gptr<const double> z = pv + (int64_t)v * svt_stride(m, n);
+    double s = 0.0;
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int i = rl + 16 * t;
-        if (i < n) s += z[2 * i + 1] * z[2 * i + 1];
-      }
-      s = group16_sum(s);
-      const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int t = 0; t < T; ++t) {
+      const int i = lane + 64 * t;
+      if (i < n) s += z[2 * i + 1] * z[2 * i + 1];
+    }
+    s = wave_sum_all(s);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    if (sgv[v] != 0.0) {
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int i = rl + 16 * t;
-        if (i < n && !zero) uc[t] = cplx{pL[i].re * z[2 * i + 1] * inv, pL[i].im * z[2 * i + 1] * inv};
+      for (int t = 0; t < T; ++t) {
+        const int i = lane + 64 * t;
+        if (i < n) {
+          const cplx ph = php[i];
+          const double x = z[2 * i + 1] * inv;
+          uc[t] = cplx{ph.re * x, ph.im * x};
+        }
       }
     }
-    // reflectors j0 .. j1-1 into chunk buffer bsel, by threads t0, t0 + dt, ..
-    auto stage = [&](int bsel, int j0, int j1, int t0, int dt) {
-      cplx* const ch = chunk0 + bsel * CH * SVT_MAXN;
-      for (int e = t0; e < (j1 - j0) * mp; e += dt) {
-        const int c = e / mp, i = e - c * mp, j = j0 + c;
-        ch[e] = (i >= j && i < m) ? cplx(W[(int64_t)j * mp + i]) : cplx{0.0, 0.0};
+  }
+  // reflectors j0 .. j0 + SVK_CH - 1 (those below 0 or at n and above are
+  // zero), element e = c mp + i of the chunk
+  cplx nx[E];
+  auto fetch = [&](int j0) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int e = tid + 256 * q;
+      const int c = e / mp, i = e - c * mp, j = j0 + c;
+      const bool ok = c < SVK_CH && j >= 0 && j < n && i >= j && i < m;
+      nx[q] = ok ? cplx(W[(int64_t)j * mp + i]) : cplx{0.0, 0.0};
+    }
+  };
+  auto put = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int e = tid + 256 * q;
+      if (e < SVK_CH * mp) chb[b][e] = nx[q];
+    }
+  };
+  const int nch = (n + SVK_CH - 1) / SVK_CH;
+  int j0 = n - SVK_CH;                                  // the last chunk first
+  fetch(j0);
+  put(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c, j0 -= SVK_CH) {
+    const int b = c & 1;
+    if (c + 1 < nch) fetch(j0 - SVK_CH);                // in flight while this chunk is applied
+    if (mine) {
+      const int jlo = j0 > 0 ? j0 : 0;
+      for (int j = j0 + SVK_CH - 1; j >= jlo; --j) {
+        const double tau = tau_s[j];                    // tau = 0 leaves uc exactly as it is
+        const cplx* const a0 = &chb[b][(j - j0) * mp];
+        cplx a[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const int i = lane + 64 * t;                  // rows past mp read zero
+          a[t] = a0[i < mp ? i : 0];
+          if (i >= mp) a[t] = cplx{0.0, 0.0};
+        }
+        double wr = 0.0, wi = 0.0;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          wr = fma(a[t].re, uc[t].re, fma(a[t].im, uc[t].im, wr));
+          wi = fma(a[t].re, uc[t].im, fma(-a[t].im, uc[t].re, wi));
+        }
+        wr = tau * wave_sum_all(wr);
+        wi = tau * wave_sum_all(wi);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          uc[t].re = fma(-a[t].re, wr, fma(a[t].im, wi, uc[t].re));
+          uc[t].im = fma(-a[t].re, wi, fma(-a[t].im, wr, uc[t].im));
+        }
       }
-    };
-    const bool split = wa < NW;                         // spare waves load ahead
-    __syncthreads();                                    // iib is free
-    stage(0, n > CH ? n - CH : 0, n, tid, SVT_THREADS);
+    }
+    if (c + 1 < nch) put(b ^ 1);                        // read by every wave after the barrier
     __syncthreads();
-    int bsel = 0;
-    for (int j1 = n; j1 > 0; j1 -= CH) {
-      const int j0 = j1 > CH ? j1 - CH : 0;
-      const int n0 = j0 > CH ? j0 - CH : 0;             // next chunk n0 .. j0-1
-      if (split && wave >= wa && j0 > 0) stage(bsel ^ 1, n0, j0, tid - 64 * wa, SVT_THREADS - 64 * wa);
-      if (act) {
-        const cplx* const ch = chunk0 + bsel * CH * SVT_MAXN;
-        for (int j = j1 - 1; j >= j0; --j) {
-          const double tau = tauL[j];                   // tau = 0 leaves uc exactly as it is
-          const cplx* vj = ch + (j - j0) * mp;
-          cplx a[9];
+  }
+  if (!mine) return;
+  // column gauge (when asked): the entry of largest modulus, the first row
+  // on ties, made real and positive.  |u_i|^2 is the rounded sum of the
+  // rounded squares, so that ties fall as in a plain evaluation
+  if (dsc.gauge) {
+    double best = -1.0;
+    int bi = 0;
 #pragma unroll
-          for (int t = 0; t < 9; ++t) a[t] = t < nt ? vj[rl + 16 * t] : cplx{0.0, 0.0};
-          house_apply(uc, a, tau);
-        }
-      }
-      __syncthreads();                                  // next chunk in, this one consumed
-      if (!split && j0 > 0) {
-        stage(bsel ^ 1, n0, j0, tid, SVT_THREADS);
-        __syncthreads();
-      }
-      bsel ^= 1;
-    }
-    // column gauge (when asked): the entry of largest modulus, the first row
-    // on ties, made real and positive.  |u_i|^2 is the rounded sum of the
-    // rounded squares, so that ties fall as in a plain evaluation
-    if (act && mine && dsc.gauge) {
-      double best = -1.0;
-      int bi = 0;
-#pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int i = rl + 16 * t;
-        double q;
-        {
+    for (int t = 0; t < T; ++t) {
+      const int i = lane + 64 * t;
+      double q;
+      {
 #pragma clang fp contract(off)
-          q = uc[t].re * uc[t].re + uc[t].im * uc[t].im;
-        }
-        if (i < m && q > best) {
-          best = q;
-          bi = i;
-        }
+        q = uc[t].re * uc[t].re + uc[t].im * uc[t].im;
       }
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) {                 // within the 16-lane group
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      cplx x = uc[0];
-#pragma unroll
-      for (int t = 1; t < 9; ++t)
-        if (t == (bi >> 4)) x = uc[t];
-      const int src = (lane & 48) | (bi & 15);
-      x = cplx{__shfl(x.re, src), __shfl(x.im, src)};
-      const double a = sqrt(x.re * x.re + x.im * x.im);
-      if (a > 0.0) {
-        const cplx ph = {x.re / a, x.im / a};
-#pragma unroll
-        for (int t = 0; t < 9; ++t)
-          uc[t] = cplx{uc[t].re * ph.re + uc[t].im * ph.im, uc[t].im * ph.re - uc[t].re * ph.im};
+      if (i < m && q > best) {
+        best = q;
+        bi = i;
       }
     }
-    if (act && mine) {
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int i = rl + 16 * t;
-        if (i < m) Uout[(int64_t)i * k + v] = uc[t];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
       }
-      if (rl == 0) sgout[v] = zero ? 0.0 : sig[v];
     }
+    cplx x = uc[0];
+#pragma unroll
+    for (int t = 1; t < T; ++t)
+      if (t == (bi >> 6)) x = uc[t];
+    x = cplx{__shfl(x.re, bi & 63), __shfl(x.im, bi & 63)};
+    const double a = sqrt(x.re * x.re + x.im * x.im);
+    if (a > 0.0) {
+      const cplx ph = {x.re / a, x.im / a};
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        uc[t] = cplx{uc[t].re * ph.re + uc[t].im * ph.im, uc[t].im * ph.re - uc[t].re * ph.im};
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int i = lane + 64 * t;
+    if (i < m) Uout[(int64_t)i * k + v] = uc[t];
   }
 }
 

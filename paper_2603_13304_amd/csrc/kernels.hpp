@@ -79,16 +79,18 @@ struct JacobiDesc {
   cplx* U;
   double* sigma;
   int rows, cols, lda, conjT, keep;
-  int gauge;    // k_svd_top only: each kept column's entry of largest modulus
+  int gauge;    // top-k SVD only (k_svd_back): each kept column's entry of largest modulus
                 // (first row on ties) made real and positive
 };
 // k_svt_bidiag followed by k_svd_top take the same descriptor and write the
 // same outputs for keep <= cols <= rows <= 144 through Householder
 // bidiagonalisation, bisection on the Golub-Kahan tridiagonal and inverse
 // iteration, with the larger scratch below (the left reflectors, rows padded
-// to 16; the bidiagonal, 3 cols + 2; per value 2 cols + 2 rows doubles).
+// to 16; the bidiagonal, 3 cols + 2; per value 2 cols + 2 rows doubles; the
+// unit phases of the real bidiagonal, cols).  k_svd_back then forms the
+// singular vectors from what k_svd_top leaves there.
 inline int64_t svd_top_work_elems(int64_t rows, int64_t cols, int64_t keep) {
-  return (rows + 15) / 16 * 16 * cols + 3 * cols + 2 + ((2 * cols + 2 * rows) * keep + 1) / 2 + 16;
+  return (rows + 15) / 16 * 16 * cols + 3 * cols + 2 + ((2 * cols + 2 * rows) * keep + 1) / 2 + cols + 16;
 }
 
 // Random sign sketch: out[i, j] = (+-1 +- 1j)/sqrt(2) from SplitMix64 output
