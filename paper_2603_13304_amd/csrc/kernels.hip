@@ -2026,6 +2026,7 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
   for (int v0b = 0; v0b < k; v0b += SVT_BATCH) {
     const int kb = k - v0b < SVT_BATCH ? k - v0b : SVT_BATCH;
     bool zv = true;
+    double bfw = 0.0;   // the first solve's forward substitution, carried value
     if (tid < kb) {
       const int v = v0b + tid;
       double* rec = iib + (int64_t)tid * pstr;
@@ -2045,22 +2046,30 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
         // rounding, used in every solve)
         const double ls = ldexp(lam, -bexp);
         double di = -ls, ui = off[0], li = off[0];
+        // the first solve's forward substitution runs along (same steps and
+        // order as the later ones): its right side, the start vector, is
+        // already in slot 3
+        double bf = rec[3];
 #pragma unroll 4
         for (int i = 0; i < N - 1; ++i) {
           const double un = off[i + 1];                  // zero past the end
+          const double bn = rec[4 * i + 7];
           const bool sw = fabs(di) < fabs(li);
           const double p = sw ? li : di, o = sw ? di : li;
           const double r1 = sw ? -ls : ui, o1 = sw ? ui : -ls;
           const double rp = svt_rcp(fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p);
           const double f0 = o * rp;
           const double fct = __hiloint2double(__double2hiint(f0), (__double2loint(f0) & ~1) | int(sw));
+          const double rb = sw ? bn : bf, ob = sw ? bf : bn;
+          bf = ob - fct * rb;
           reinterpret_cast<d2v*>(rec + 4 * i)[0] = d2v{rp, r1};
-          rec[4 * i + 2] = fct;
+          reinterpret_cast<d2v*>(rec + 4 * i + 2)[0] = d2v{fct, rb};
           di = o1 - fct * r1;
           ui = sw ? -fct * un : un;
           li = un;
         }
         rec[4 * (N - 1)] = svt_rcp(fabs(di) < tiny ? (di < 0.0 ? -tiny : tiny) : di);
+        bfw = bf;
       }
     }
     for (int it = 0; it < SVT_ITERS; ++it) {
@@ -2085,16 +2094,20 @@ __global__ __launch_bounds__(SVT_THREADS) void k_svd_top(const JacobiDesc* __res
           return rb;
         };
         int i = 0;
-        for (const int r = (N - 1) & 7; i < r; ++i) rec[4 * i + 3] = fstep(rec[4 * i + 2], rec[4 * i + 7]);
-        for (; i < N - 1; i += 8) {
-          d2v fb[9];                                     // (multiplier, b) of steps i .. i+8
+        if (it == 0) {
+          bi = bfw;                                      // ran with the factorisation
+        } else {
+          for (const int r = (N - 1) & 7; i < r; ++i) rec[4 * i + 3] = fstep(rec[4 * i + 2], rec[4 * i + 7]);
+          for (; i < N - 1; i += 8) {
+            d2v fb[9];                                   // (multiplier, b) of steps i .. i+8
 #pragma unroll
-          for (int t = 0; t < 9; ++t) fb[t] = reinterpret_cast<const d2v*>(rec + 4 * (i + t) + 2)[0];
-          double rb[8];
+            for (int t = 0; t < 9; ++t) fb[t] = reinterpret_cast<const d2v*>(rec + 4 * (i + t) + 2)[0];
+            double rb[8];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) rb[t] = fstep(fb[t][0], fb[t + 1][1]);
+            for (int t = 0; t < 8; ++t) rb[t] = fstep(fb[t][0], fb[t + 1][1]);
 #pragma unroll
-          for (int t = 0; t < 8; ++t) rec[4 * (i + t) + 3] = rb[t];
+            for (int t = 0; t < 8; ++t) rec[4 * (i + t) + 3] = rb[t];
+          }
         }
         // back substitution in place, the last two values in registers.  A
         // tiny pivot can multiply the solution by up to 1/eps: after every
