@@ -51,7 +51,8 @@ struct LaunchRec {
   int count = 0;
   dim3 grid;
   size_t lds = 0;
-  int variant = 0;       // kernel variant (GEMM: tile shape; QR: 1 = blocked tall kernel, 2 = k_qr_small, 3 =
+  int variant = 0;       // kernel variant (GEMM: tile shape; QR: 1 = blocked tall kernel, 2 = k_qr_small
+                         // (144 x 16), 4 = k_qr_small (288 x 32), 3 =
                          // k_qr_mid (R only); Jacobi: 1 = rows
                          // split between LDS and the work buffer, 2 = top-k SVD through
                          // bidiagonalisation: k_svt_bidiag, k_svd_top, k_svd_back)
@@ -184,6 +185,7 @@ int op_variant(const Op& op) {
     const int64_t m = op.i[0], n = op.i[1], k = std::min(m, n);
     if (m <= QRS_MAXM && n <= QRS_MAXN) return 2;   // k_qr_small
     if (!op.c.valid() && m <= QRS_MAXM && n <= QRM_MAXN) return 3;   // k_qr_mid, R only
+    if (m <= 2 * QRS_MAXM && n <= 2 * QRS_MAXN) return 4;   // k_qr_small, 18 rows x 32 columns
     return m * (n + (op.c.valid() ? k : 0)) <= QR_LDS_MAX ? 0 : 1;
   }
   if (op.type == OPK_JACOBI) {
@@ -483,7 +485,9 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
       break;
     case OPK_QR:
       if (r.variant == 2)
-        hipLaunchKernelGGL(k_qr_small, r.grid, dim3(256), 0, stream, (const QrDesc*)d);
+        hipLaunchKernelGGL((k_qr_small<9, 16>), r.grid, dim3(256), 0, stream, (const QrDesc*)d);
+      else if (r.variant == 4)
+        hipLaunchKernelGGL((k_qr_small<18, 32>), r.grid, dim3(512), 0, stream, (const QrDesc*)d);
       else if (r.variant == 3)
         hipLaunchKernelGGL(k_qr_mid, r.grid, dim3(QRM_THREADS), 0, stream, (const QrDesc*)d);
       else if (r.variant)

@@ -594,12 +594,13 @@ __global__ __launch_bounds__(256) void k_qr(const QrDesc* __restrict__ descs) {
     qr_body<false>(d, to_global(d.work), to_global(d.work) + (int64_t)m * n, tau_s, phs, alpha_s, part_s);
 }
 
-// x -= tau v (v^H x) for a vector held as rows gl + 16 t (t < 9) of a
+// x -= tau v (v^H x) for a vector held as rows gl + 16 t (t < T) of a
 // 16-lane group; the dot product is a 16-lane DPP sum
-__device__ __forceinline__ void house_apply(cplx (&x)[9], const cplx (&v)[9], double tau) {
+template <int T>
+__device__ __forceinline__ void house_apply(cplx (&x)[T], const cplx (&v)[T], double tau) {
   double wr0 = 0.0, wi0 = 0.0, wr1 = 0.0, wi1 = 0.0;
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
+  for (int t = 0; t < T; ++t) {
     double& wr = t & 1 ? wr1 : wr0;
     double& wi = t & 1 ? wi1 : wi0;
     wr = fma(v[t].re, x[t].re, wr);
@@ -609,7 +610,7 @@ __device__ __forceinline__ void house_apply(cplx (&x)[9], const cplx (&v)[9], do
   }
   const double wr = tau * group16_sum(wr0 + wr1), wi = tau * group16_sum(wi0 + wi1);
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
+  for (int t = 0; t < T; ++t) {
     x[t].re = fma(-v[t].re, wr, x[t].re);
     x[t].re = fma(v[t].im, wi, x[t].re);
     x[t].im = fma(-v[t].re, wi, x[t].im);
@@ -624,12 +625,13 @@ constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
 // j) goes to Vr[0 .. 143]; lane gl == 0 stores tau, the unit phase of alpha
 // and |alpha| (rescaled back when the column was tiny).  The column's rows
 // from j on may be left rescaled.
-__device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, int lane, cplx* Vr,
+template <int T>
+__device__ __forceinline__ void qr_group_reflector(cplx (&a)[T], int j, int gl, int lane, cplx* Vr,
                                                    double* tau_o, cplx* phs_o, cplx* alpha_o) {
   // three partial sums keep the dependent chain short
   double p3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+  for (int t = 0; t < T; ++t)
     if (gl + 16 * t >= j) p3[t % 3] = fma(a[t].re, a[t].re, fma(a[t].im, a[t].im, p3[t % 3]));
   double part = p3[0] + p3[1] + p3[2];
   double nx2 = group16_sum(part);
@@ -641,7 +643,7 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
   if (sc != 1.0) {
     part = 0.0;
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int t = 0; t < T; ++t)
       if (gl + 16 * t >= j) {
         a[t] = cplx{a[t].re * sc, a[t].im * sc};
         part += a[t].re * a[t].re + a[t].im * a[t].im;
@@ -650,7 +652,7 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
   }
   cplx mine = a[0];
 #pragma unroll
-  for (int t = 1; t < 9; ++t)
+  for (int t = 1; t < T; ++t)
     if (t == (j >> 4)) mine = a[t];
   // only the owner group is active here: its lanes share lane & 48
   const int src = __builtin_amdgcn_readfirstlane(lane & 48) | (j & 15);
@@ -666,9 +668,9 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
     v0 = cplx{x0.re + ph.re * nx, x0.im + ph.im * nx};
   }
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
+  for (int t = 0; t < T; ++t) {
     const int r = gl + 16 * t;
-    if (r < QRS_MAXM) Vr[r] = r < j ? cplx{0.0, 0.0} : r == j ? v0 : a[t];
+    if (r < 16 * T) Vr[r] = r < j ? cplx{0.0, 0.0} : r == j ? v0 : a[t];
   }
   if (gl == 0) {
     // |alpha| = nx and its unit phase is -ph (1 for a zero column)
@@ -678,25 +680,26 @@ __device__ __forceinline__ void qr_group_reflector(cplx (&a)[9], int j, int gl, 
   }
 }
 
-// QR of a block with n <= 16 columns and m <= 144 rows (the reflectors,
+// QR of a block with n <= G columns and m <= 16 T rows (the reflectors,
 // phases and outputs of k_qr): 16-lane group g holds column g in registers
-// (rows lane + 16 t).  Step j: group j forms the reflector with DPP sums and
+// (rows lane + 16 t, t < T).  Step j: group j forms the reflector with DPP sums and
 // stores it in LDS, one barrier, every later group applies it to its column
 // with a 16-lane DPP dot product.  The reflectors stay in LDS, so forming Q
 // (group c applies H_{k-1} .. H_0 to e_c) needs no barrier at all.
-__global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ descs) {
+template <int T, int G>
+__global__ __launch_bounds__(16 * G) void k_qr_small(const QrDesc* __restrict__ descs) {
   const QrDesc d = descs[blockIdx.x];
   const int m = d.m, n = d.n, k = m < n ? m : n;
-  if (m > QRS_MAXM || n > QRS_MAXN) return;            // excluded by the plan compiler
+  if (m > 16 * T || n > G) return;            // excluded by the plan compiler
   const int tid = threadIdx.x, g = tid >> 4, gl = tid & 15, lane = tid & 63;
   const gptr<const cplx> Ain = to_global(d.A);
   const gptr<cplx> Rout = to_global(d.R), Qout = to_global(d.Q);
-  __shared__ cplx V[QRS_MAXN][QRS_MAXM];
-  __shared__ double tau_s[QRS_MAXN];
-  __shared__ cplx phs[QRS_MAXN], alpha_s[QRS_MAXN];
-  cplx a[9];
+  __shared__ cplx V[G][16 * T];
+  __shared__ double tau_s[G];
+  __shared__ cplx phs[G], alpha_s[G];
+  cplx a[T];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
+  for (int t = 0; t < T; ++t) {
     const int r = gl + 16 * t;
     const bool ok = r < m && g < n;
     const int64_t o = !ok ? 0 : d.conjT ? (int64_t)g * d.lda + r : (int64_t)r * d.lda + g;
@@ -709,9 +712,9 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
     __syncthreads();
     const double tau = tau_s[j];
     if (g > j && g < n) {                                   // tau = 0 changes nothing
-      cplx v[9];                                            // zero above row j
+      cplx v[T];                                            // zero above row j
 #pragma unroll
-      for (int t = 0; t < 9; ++t) v[t] = V[j][gl + 16 * t];
+      for (int t = 0; t < T; ++t) v[t] = V[j][gl + 16 * t];
       house_apply(a, v, tau);
     }
   }
@@ -720,7 +723,7 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
   // conj(phase_r); group g writes column g
   if (g < n) {
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
+    for (int t = 0; t < T; ++t) {
       const int r = gl + 16 * t;
       if (r >= k) continue;
       cplx x = {0.0, 0.0};
@@ -735,25 +738,25 @@ __global__ __launch_bounds__(256) void k_qr_small(const QrDesc* __restrict__ des
   }
   if (d.Q == nullptr || g >= k) return;
   // Q = H_0 ... H_{k-1} [I; 0] times the phases, column g
-  cplx q[9];
+  cplx q[T];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) q[t] = cplx{gl + 16 * t == g ? 1.0 : 0.0, 0.0};
+  for (int t = 0; t < T; ++t) q[t] = cplx{gl + 16 * t == g ? 1.0 : 0.0, 0.0};
   // two reflectors per pass, both read before the first is applied (tau = 0
   // changes nothing)
   for (int j = g; j >= 0; j -= 2) {
     const int j1 = j > 0 ? j - 1 : 0;
     const double tau = tau_s[j], tau1 = j > 0 ? tau_s[j1] : 0.0;
-    cplx v[9], w[9];
+    cplx v[T], w[T];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) v[t] = V[j][gl + 16 * t];
+    for (int t = 0; t < T; ++t) v[t] = V[j][gl + 16 * t];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) w[t] = V[j1][gl + 16 * t];
+    for (int t = 0; t < T; ++t) w[t] = V[j1][gl + 16 * t];
     house_apply(q, v, tau);
     house_apply(q, w, tau1);
   }
   const cplx ph = phs[g];
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
+  for (int t = 0; t < T; ++t) {
     const int r = gl + 16 * t;
     if (r >= m) continue;
     const cplx x = {q[t].re * ph.re - q[t].im * ph.im, q[t].re * ph.im + q[t].im * ph.re};
