@@ -176,12 +176,9 @@ def swallow(ch, step, t, chi, trunc="T1", q=2, p=8, keyfn=None, d=2):
     pos, ins, outs = step["pos"], step["in_slots"], step["out_slots"]
     r, s = len(ins), len(outs)
     move_center(ch, pos, pos + r - 1)
-    Th = ch.A[pos]
-    for j in range(1, r):
-        Th = np.tensordot(Th, ch.A[pos + j], axes=([Th.ndim - 1], [0]))
-    a, b = Th.shape[0], Th.shape[-1]
-    # unfuse every leg into (ket, bra, carries...)
-    shape = [a]
+    a, b = ch.A[pos].shape[0], ch.A[pos + r - 1].shape[2]
+    # unfuse every leg into (ket, bra, carries...); consecutive run sites
+    # share their bond label
     labels = [0]
     nxt = [1]
 
@@ -190,18 +187,22 @@ def swallow(ch, step, t, chi, trunc="T1", q=2, p=8, keyfn=None, d=2):
         return nxt[0]
 
     ket_lab, bra_lab, carry_labs, carry_ids = {}, {}, [], []
+    run, run_labels = [], []
+    left = 0
     for j in range(r):
+        A = ch.A[pos + j]
         dims = _unfuse_dims(ch, pos + j)
-        shape += dims
         kl, bl = new(), new()
         ket_lab[ins[j]], bra_lab[ins[j]] = kl, bl
         cl = [new() for _ in ch.carries[pos + j]]
         carry_labs += cl
         carry_ids += ch.carries[pos + j]
+        right = 1 if j == r - 1 else new()
+        run.append(A.reshape([A.shape[0]] + dims + [A.shape[2]]))
+        run_labels.append([left] + [kl, bl] + cl + [right])
         labels += [kl, bl] + cl
-    shape.append(b)
+        left = right
     labels.append(1)
-    Th = Th.reshape(shape)
     nslot = t.ndim - 1
     pl = new()
     ket_t = [pl] + [ket_lab.get(l) for l in range(nslot)]
@@ -225,7 +226,21 @@ def swallow(ch, step, t, chi, trunc="T1", q=2, p=8, keyfn=None, d=2):
         for l in outs[1:]:
             out_labels += [out_k[l], out_b[l]]
         out_labels += [1]
-    R = np.einsum(Th, labels, t, ket_t, t.conj(), bra_t, out_labels, optimize=True)
+    # the sum over every repeated label of (run sites, t, conj t), taken as a
+    # chain of pairwise sums: t with the first run site, each further run
+    # site, then conj t.  Only the order of the pairwise sums differs from
+    # merging the run first; the value is the same and no intermediate holds
+    # the merged run (a D^(2r) chi^2 tensor).
+    def pair(X, xl, Y, yl):
+        shared = set(xl) & set(yl)
+        ol = [x for x in xl if x not in shared] + [y for y in yl if y not in shared]
+        return np.einsum(X, xl, Y, yl, ol), ol
+
+    R, rl = pair(run[0], run_labels[0], t, ket_t)
+    for j in range(1, r):
+        R, rl = pair(R, rl, run[j], run_labels[j])
+    R, rl = pair(R, rl, t.conj(), bra_t)
+    R = np.transpose(R, [rl.index(x) for x in out_labels])
     Qtot = int(np.prod([4] * len(carry_ids))) if carry_ids else 1
     out_dims = [t.shape[1 + l] for l in outs]
     if s == 0:

@@ -104,6 +104,14 @@ def ss_from_rho(rho):
     return float(np.real(np.trace(rho @ H_SS)) / np.real(np.trace(rho)))
 
 
+def expect_op(rho, op):
+    """<O> = Tr(rho O) / Tr(rho) for a two-site operator O given as a
+    d^2 x d^2 matrix in the (p_i p_j) basis (rows bra, columns ket:
+    O[(p_i' p_j'), (p_i p_j)] = <p_i' p_j'| O |p_i p_j>), rho indexed
+    [(p_i p_j), (p_i' p_j')].  Complex for a non-Hermitian O."""
+    return complex(np.trace(rho @ op) / np.trace(rho))
+
+
 def rho_from_carry(R, order, i, j, d=2):
     """R over the carried pairs listed in ``order`` (fused p*d + p' each) ->
     rho[(p_i p_j), (p_i' p_j')]."""

@@ -335,14 +335,14 @@ class Server:
 
 
 PROFILE_KINDS = ["gemm", "transpose", "qr", "jacobi", "sketch", "norm", "pad", "msg_phase",
-                 "split_gauge"]
+                 "split_gauge", "chol"]
 PREC_NAMES = ["fp64", "fp32", "bf16x3"]
 
 
 def profile_sweeps(net, n_sweeps):
     """Per-kernel HIP-event timing of ``n_sweeps`` sweeps: dict slot name ->
     (ms, launches, flops, bytes)."""
-    n = 27
+    n = 30
     ms = np.zeros(n)
     nl = np.zeros(n, np.int64)
     fl = np.zeros(n)

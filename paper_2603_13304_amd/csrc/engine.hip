@@ -182,11 +182,10 @@ size_t push_descs(std::vector<char>* blob, const std::vector<T>& v) {
 int op_variant(const Op& op) {
   if (op.type == OPK_GEMM) return op.i[0] <= 16 ? 1 : op.i[1] <= 16 ? 2 : 0;   // k_gemm tile shape
   if (op.type == OPK_QR) {
-    const int64_t m = op.i[0], n = op.i[1], k = std::min(m, n);
-    if (m <= QRS_MAXM && n <= QRS_MAXN) return 2;   // k_qr_small
-    if (!op.c.valid() && m <= QRS_MAXM && n <= QRM_MAXN) return 3;   // k_qr_mid, R only
-    if (m <= 2 * QRS_MAXM && n <= 2 * QRS_MAXN) return 4;   // k_qr_small, 18 rows x 32 columns
-    return m * (n + (op.c.valid() ? k : 0)) <= QR_LDS_MAX ? 0 : 1;
+    // QRK_CHOL shapes are expanded by the plan compiler; the blocked tall
+    // kernel takes any that reach here
+    const int v = qr_kernel(op.i[0], op.i[1], op.c.valid());
+    return v == QRK_CHOL ? QRK_TALL : v;
   }
   if (op.type == OPK_JACOBI) {
     if (op.i[5]) return 2;   // k_svd_top
@@ -413,6 +412,26 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
           rec.grid = dim3(unsigned(std::min<int64_t>(4096, (mt + 255) / 256)), unsigned(v.size()));
           break;
         }
+        case OPK_CHOL: {
+          std::vector<CholDesc> v;
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
+            CholDesc c;
+            c.G = resolve(h, op->a); c.Rinv = resolve(h, op->b); c.R = resolve(h, op->c);
+            c.S = int(op->i[0]); c.n = int(op->i[1]); c.shift = int(op->i[2]);
+            c.accumulate = int(op->i[3]); c.m = op->i[4];
+            const double n = c.n;
+            // Cholesky, triangular inverse, and the running factor's product
+            // (n^3 / 3 complex multiply-adds each), 8 flops per complex MAC
+            rec.flops += 8.0 * (n * n * n / 3.0) * (c.accumulate ? 3.0 : 2.0);
+            rec.bytes += 16.0 * n * n * (double(c.S) + 2.0 + (c.accumulate ? 2.0 : 0.0));
+            v.push_back(c);
+          }
+          rec.desc_off = push_descs(blob, v);
+          rec.grid = dim3(unsigned(v.size()));
+          break;
+        }
         case OPK_COLPHASE: {
           std::vector<ColPhaseDesc> v;
           for (const auto& ho : ops) {
@@ -527,6 +546,9 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
       break;
     case OPK_COLPHASE:
       hipLaunchKernelGGL(k_colphase, r.grid, blk, 0, stream, (const ColPhaseDesc*)d);
+      break;
+    case OPK_CHOL:
+      hipLaunchKernelGGL(k_chol, r.grid, dim3(CHOL_THREADS), 0, stream, (const CholDesc*)d);
       break;
   }
   return hipGetLastError();

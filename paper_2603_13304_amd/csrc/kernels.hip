@@ -433,7 +433,6 @@ __device__ double block_sum(double v, double* sh) {
 // Qt[c*m+i]) in LDS when m*(n+k) <= QR_LDS_MAX, else in the work buffer
 // (W) and a column-major staging area behind it (Qt).  Column operations use
 // one 16-lane group per column, 16 columns at a time.
-constexpr int QR_LDS_MAX = 8192;   // complex elements (128 KB)
 
 // Householder columns whose squared norm is positive but below 1e-200 are
 // rescaled by this power of two (exact) before the reflector is formed:
@@ -618,7 +617,6 @@ __device__ __forceinline__ void house_apply(cplx (&x)[T], const cplx (&v)[T], do
   }
 }
 
-constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
 
 // Householder step j on a column held by one 16-lane group as rows gl + 16 t
 // (only that group active): the reflector (zero above row j, its head at row
@@ -771,7 +769,7 @@ __global__ __launch_bounds__(16 * G) void k_qr_small(const QrDesc* __restrict__ 
 // reflector into one of two LDS buffers, one barrier, every later column
 // applies it with a 16-lane DPP dot product.  Step j + 1 writes the other
 // buffer, so one barrier per step is enough.
-constexpr int QRM_MAXN = 128, QRM_THREADS = 512;
+constexpr int QRM_THREADS = 512;
 __global__ __launch_bounds__(QRM_THREADS) void k_qr_mid(const QrDesc* __restrict__ descs) {
   const QrDesc d = descs[blockIdx.x];
   const int m = d.m, n = d.n, k = m < n ? m : n;
@@ -1128,6 +1126,136 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qr_tall(const QrDesc* __restric
     const cplx ph = phs[c], x = Qt[(int64_t)c * m + r];
     d.Q[e] = cplx{x.re * ph.re - x.im * ph.im, x.re * ph.im + x.im * ph.re};
   }
+}
+
+// ------------------------------------------------------------ Cholesky QR
+// k_chol: the Cholesky step of the tall QR (see CholDesc).  The Gram matrix
+// sits in LDS (n <= 80: 100 KB).  The right-looking factorisation takes one
+// barrier per step: every thread reads the finished row j and updates its
+// elements of the trailing upper triangle with the unscaled row and the
+// factor 1 / G_jj; the rows of R are scaled once the loop is done.  R^-1 is
+// then formed in place column by column (column j of R^-1 needs R^-1 of the
+// leading block, stored over the finished columns, and column j of R), with
+// a 16-lane group per row.
+constexpr int CHOL_THREADS = 1024;
+constexpr int CHOL_PER_THREAD = (CHOLQR_MAXN * CHOLQR_MAXN + CHOL_THREADS - 1) / CHOL_THREADS;
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol(const CholDesc* __restrict__ descs) {
+  const CholDesc d = descs[blockIdx.x];
+  const int n = d.n, tid = threadIdx.x, nn = n * n;
+  __shared__ cplx A[CHOLQR_MAXN * CHOLQR_MAXN];
+  __shared__ double rd[CHOLQR_MAXN], ird[CHOLQR_MAXN];
+  __shared__ cplx tcol[CHOLQR_MAXN];
+  __shared__ double sc[2];
+  if (n > CHOLQR_MAXN) return;   // excluded by the plan compiler
+  const gptr<const cplx> G = to_global(d.G);
+  // summed upper triangle, partials in order (deterministic)
+  for (int e = tid; e < nn; e += CHOL_THREADS) {
+    const int i = e / n, j = e - i * n;
+    cplx s = {0.0, 0.0};
+    if (i <= j)
+      for (int p = 0; p < d.S; ++p) {
+        const cplx g = G[(int64_t)p * nn + e];
+        s.re += g.re;
+        s.im += g.im;
+      }
+    A[e] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tr = 0.0, mx = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double g = A[i * n + i].re;
+      tr += g;
+      mx = fmax(mx, g);
+    }
+    sc[0] = d.shift ? 11.0 * ((double)d.m * n + (double)n * (n + 1)) * 0x1p-53 * tr : 0.0;
+    sc[1] = 1e-24 * mx;
+  }
+  __syncthreads();
+  const double thr = sc[1];
+  if (tid < n) A[tid * n + tid].re += sc[0];
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double gjj = A[j * n + j].re;
+    // a NaN pivot is kept (it propagates to the outputs)
+    const bool ok = !(gjj <= thr);
+    if (tid == 0) {
+      rd[j] = ok ? sqrt(gjj) : 0.0;
+      ird[j] = ok ? 1.0 / sqrt(gjj) : 0.0;
+    }
+    const int t = n - 1 - j;
+    if (ok && t > 0) {
+      const double inv = 1.0 / gjj;
+      for (int e = tid; e < t * t; e += CHOL_THREADS) {
+        const int a = e / t, b = e - a * t;
+        if (a > b) continue;
+        const int i = j + 1 + a, k = j + 1 + b;
+        const cplx gi = A[j * n + i], gk = A[j * n + k];
+        cplx& x = A[i * n + k];
+        x.re -= (gi.re * gk.re + gi.im * gk.im) * inv;   // conj(g_ji) g_jk / g_jj
+        x.im -= (gi.re * gk.im - gi.im * gk.re) * inv;
+      }
+    }
+    __syncthreads();
+  }
+  // R_new in place: row j scaled by 1 / r_jj, real diagonal, zero below
+  for (int e = tid; e < nn; e += CHOL_THREADS) {
+    const int i = e / n, k = e - i * n;
+    cplx x = {0.0, 0.0};
+    if (k == i) x.re = rd[i];
+    else if (k > i) x = cplx{A[e].re * ird[i], A[e].im * ird[i]};
+    A[e] = x;
+  }
+  __syncthreads();
+  const gptr<cplx> Rg = to_global(d.R);
+  if (d.accumulate) {
+    // R <- R_new R_prev (both upper triangular), read fully before writing
+    cplx acc[CHOL_PER_THREAD];
+#pragma unroll
+    for (int q = 0; q < CHOL_PER_THREAD; ++q) {
+      const int e = tid + q * CHOL_THREADS;
+      cplx s = {0.0, 0.0};
+      if (e < nn) {
+        const int i = e / n, k = e - i * n;
+        for (int l = i; l <= k; ++l) {
+          const cplx a = A[i * n + l], b = Rg[(int64_t)l * n + k];
+          s.re += a.re * b.re - a.im * b.im;
+          s.im += a.re * b.im + a.im * b.re;
+        }
+      }
+      acc[q] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CHOL_PER_THREAD; ++q) {
+      const int e = tid + q * CHOL_THREADS;
+      if (e < nn) Rg[e] = acc[q];
+    }
+  } else {
+    for (int e = tid; e < nn; e += CHOL_THREADS) Rg[e] = A[e];
+  }
+  // R^-1 in place: X[j][j] = 1 / r_jj, X[i][j] = -(sum_{i <= l < j} X[i][l] R[l][j]) / r_jj
+  const int grp = tid >> 4, gl = tid & 15;
+  for (int j = 0; j < n; ++j) {
+    for (int i = grp; i < j; i += CHOL_THREADS / 16) {
+      double sr = 0.0, si = 0.0;
+      for (int l = i + gl; l < j; l += 16) {
+        const cplx x = A[i * n + l], r = A[l * n + j];
+        sr += x.re * r.re - x.im * r.im;
+        si += x.re * r.im + x.im * r.re;
+      }
+      sr = group16_sum(sr);
+      si = group16_sum(si);
+      if (gl == 0) tcol[i] = cplx{-sr * ird[j], -si * ird[j]};
+    }
+    __syncthreads();
+    if (tid < j) A[tid * n + j] = tcol[tid];
+    else if (tid == j) A[j * n + j] = cplx{ird[j], 0.0};
+    __syncthreads();
+  }
+  const gptr<cplx> Xg = to_global(d.Rinv);
+  for (int e = tid; e < nn; e += CHOL_THREADS) Xg[e] = A[e];
 }
 
 // ----------------------------------------------------------------- Jacobi

@@ -64,6 +64,49 @@ struct QrDesc {
   int qh;       // Q written as Q^H (k x m, row-major) instead of Q (m x k)
 };
 
+// Which QR kernel factorises an m x n matrix (the plan compiler and the
+// executor take the same decision):
+//   QRK_SMALL   k_qr_small<9, 16>, m <= 144, n <= 16 (registers)
+//   QRK_MID     k_qr_mid, R only, m <= 144, n <= 128 (registers)
+//   QRK_SMALL2  k_qr_small<18, 32>, m <= 288, n <= 32 (registers)
+//   QRK_LDS     k_qr, working copy m (n + k) <= QR_LDS_MAX in LDS
+//   QRK_CHOL    tall blocks with n <= CHOLQR_MAXN <= m: Cholesky QR on several
+//               workgroups (Gram GEMMs, k_chol, Q GEMMs; three passes, the
+//               first shifted), expanded into those ops by the plan compiler
+//   QRK_TALL    k_qr_tall, one workgroup, blocked panels (everything else)
+constexpr int QR_LDS_MAX = 8192;   // complex elements (128 KB)
+constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
+constexpr int QRM_MAXN = 128;
+constexpr int CHOLQR_MAXN = 80;
+enum QrKernel { QRK_LDS = 0, QRK_TALL = 1, QRK_SMALL = 2, QRK_MID = 3, QRK_SMALL2 = 4, QRK_CHOL = 5 };
+inline int qr_kernel(int64_t m, int64_t n, bool with_q) {
+  const int64_t k = m < n ? m : n;
+  if (m <= QRS_MAXM && n <= QRS_MAXN) return QRK_SMALL;
+  if (!with_q && m <= QRS_MAXM && n <= QRM_MAXN) return QRK_MID;
+  if (m <= 2 * QRS_MAXM && n <= 2 * QRS_MAXN) return QRK_SMALL2;
+  if (m * (n + (with_q ? k : 0)) <= QR_LDS_MAX) return QRK_LDS;
+  if (n <= CHOLQR_MAXN && m >= n) return QRK_CHOL;
+  return QRK_TALL;
+}
+
+// Cholesky step of the tall QR (k_chol, one workgroup per item): the S
+// partial Gram matrices G_s (n x n each, consecutive, row-major; only their
+// upper triangles are read) are summed in order, shifted when `shift` is set
+// (sigma = 11 (m n + n (n + 1)) 2^-53 tr G, the shifted Cholesky QR of
+// Fukaya et al. 2020), and factorised G = R^H R with R upper triangular and
+// real positive diagonal.  A pivot at or below 1e-24 max_i G_ii marks a
+// column inside the span of the previous ones: its row of R and its column of
+// R^-1 are zero (the matching column of Q comes out zero).  Writes R^-1 and,
+// when `accumulate`, R <- R_new R (the running factor of the passes, updated
+// in place), else R <- R_new.  n <= CHOLQR_MAXN.
+struct CholDesc {
+  const cplx* G;
+  cplx* Rinv;
+  cplx* R;
+  int S, n, shift, accumulate;
+  int64_t m;
+};
+
 // One-sided Jacobi SVD of the rows x cols matrix A with element (i, c) at
 // A[i * lda + c], or conj(A[c * lda + i]) with conjT.  Rotating the columns to
 // mutual orthogonality gives A W = U Sigma; the `keep` columns of largest norm

@@ -104,7 +104,17 @@ struct Compiler::Lane {
     if (st != stage || sp != step || ph != phase) counter = 0;
     stage = st; step = sp; phase = ph;
   }
+  // the next op shares the launch of the previous one (independent ops of
+  // one step, e.g. the chunks of a split Gram product)
+  bool join_next = false;
   void push(const Op& op) {
+    if (join_next && !out->ops.empty() && stage == key_stage) {
+      join_next = false;
+      ++counter;
+      out->ops.push_back({out->ops.back().first, op});
+      return;
+    }
+    join_next = false;
     if (stage != key_stage) {
       key_stage = stage;
       svd_seq = 0;
@@ -167,11 +177,60 @@ struct Compiler::Lane {
   // written in place of Q
   void qr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh = false) {
     if (std::min(m, n) > 256) { err = "QR width above 256"; return; }
+    if (qr_kernel(m, n, Q.valid()) == QRK_CHOL) {
+      cholqr(A, m, n, lda, conjT, Q, R, qh);
+      return;
+    }
     Op op;
     op.type = OPK_QR;
     op.a = A; op.b = scratch(m * (n + (Q.valid() ? std::min(m, n) : 0))); op.c = Q; op.d = R;
     op.i[0] = m; op.i[1] = n; op.i[2] = lda; op.i[3] = conjT; op.i[4] = qh ? 1 : 0;
     push(op);
+  }
+  // Tall QR (m >= n, n <= CHOLQR_MAXN) on many workgroups: Cholesky QR in
+  // three passes, the first with the shift of Fukaya et al. (2020), which
+  // keeps it stable for condition numbers up to about 1e12, the other two
+  // restoring orthogonality to rounding (CholeskyQR2).  Each pass: the Gram
+  // matrix Y^H Y as partial products over row chunks (one launch), k_chol
+  // (Cholesky, R^-1, running R), then Y R^-1 (a GEMM).  The last pass's
+  // product is skipped when Q is not wanted, and writes Q^H with qh.
+  void cholqr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh) {
+    int64_t rb = std::max<int64_t>(144, (m + 31) / 32);
+    rb = (rb + 15) / 16 * 16;
+    const int64_t S = (m + rb - 1) / rb;
+    Ref Gp = scratch(S * n * n), Rinv = scratch(n * n);
+    Ref cur = A;
+    int64_t cld = lda;
+    int cT = conjT;
+    for (int pass = 0; pass < 3; ++pass) {
+      for (int64_t s = 0; s < S; ++s) {
+        const int64_t r0 = s * rb, rows = std::min(rb, m - r0);
+        const Ref G{Gp.region, Gp.off + s * n * n};
+        join_next = s > 0;
+        if (!cT) {
+          const Ref X{cur.region, cur.off + r0 * cld};
+          gemm(X, X, G, n, n, rows, cld, cld, n, OP_C, OP_N, PREC_FP64);
+        } else {
+          const Ref X{cur.region, cur.off + r0};
+          gemm(X, X, G, n, n, rows, cld, cld, n, OP_N, OP_C, PREC_FP64);
+        }
+      }
+      Op op;
+      op.type = OPK_CHOL;
+      op.a = Gp; op.b = Rinv; op.c = R;
+      op.i[0] = S; op.i[1] = n; op.i[2] = pass == 0; op.i[3] = pass > 0; op.i[4] = m;
+      push(op);
+      const bool last = pass == 2;
+      if (last && !Q.valid()) break;
+      Ref out = last ? Q : scratch(m * n);
+      if (last && qh)   // Q^H = R^-H Y^H (n x m)
+        gemm(Rinv, cur, out, n, m, n, n, cld, m, OP_C, cT ? OP_N : OP_C, PREC_FP64);
+      else
+        gemm(cur, Rinv, out, m, n, n, cld, n, n, cT ? OP_C : OP_N, OP_N, PREC_FP64);
+      cur = out;
+      cld = n;
+      cT = 0;
+    }
   }
   // leading `keep` left singular vectors U (rows x keep) and values of the
   // rows x cols matrix A (element (i, c) at A[i*lda + c], conj(A[c*lda + i])

@@ -197,6 +197,31 @@ def product_state_patch(Lx, Ly, D, seed, d=2):
     return ts, phis
 
 
+def chain_cell(D, seed, d=2):
+    """Unit cell whose network splits into decoupled horizontal chains.
+    DL and DR carry a random MPS tensor on their horizontal legs (slot 2 to
+    the left, slot 0 to the right) and a fixed random vector on each of their
+    two other legs; U is a product of a random spinor and four random
+    vectors.  Every bond leaving the horizontal chains then contracts two
+    fixed vectors to a scalar, so the infinite lattice is a stack of
+    identical infinite chains ... DL DR DL DR ... times scalars.  Returns
+    (tensors [U, DL, DR], A, B, phi) with A[p, left, right] the DL chain
+    tensor, B the DR one and phi the U spinor."""
+    rng = np.random.default_rng(seed)
+    A = cgauss(rng, (d, D, D))
+    B = cgauss(rng, (d, D, D))
+    phi = cgauss(rng, (d,))
+    phi /= np.linalg.norm(phi)
+    vU = [cgauss(rng, (D,)) for _ in range(4)]
+    w = [cgauss(rng, (D,)) for _ in range(2)]
+    u = [cgauss(rng, (D,)) for _ in range(2)]
+    tU = np.einsum("p,a,b,c,e->pabce", phi, *vU)
+    # t[p, l0 (right), l1, l2 (left), l3]
+    tDL = np.einsum("plr,b,e->prble", A, w[0], w[1])
+    tDR = np.einsum("plr,b,e->prble", B, u[0], u[1])
+    return [tU, tDL, tDR], A, B, phi
+
+
 def rotate_cell_120(ts):
     """Unit cell of the lattice rotated by 120 degrees about the centre of an
     up-triangle: U -> DL -> DR -> U, every bond direction advancing by two
