@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define PEPSNET_ABI_VERSION 1
+#define PEPSNET_ABI_VERSION 2
 
 typedef struct pepsnet_s* pepsnet_t;
 
@@ -66,18 +66,43 @@ typedef struct {
   int32_t hex_N;        /* BBP_KAGOME_INF_HEX: face length N (>= 2), N_T = 3(3N^2-3N+1) */
   int32_t d, D;         /* physical (2) and virtual bond dimension */
   int32_t chi;          /* message bond dimension */
-  int32_t chi_env;      /* boundary-chain truncation; must equal chi */
+  int32_t chi_env;      /* boundary-chain truncation: chi, or 0 for the exact
+                         * contraction of the block (no truncation inside a
+                         * message update; the outgoing message is then
+                         * compressed to chi by exact truncated SVDs; every
+                         * split of the block's chain must then fit the exact
+                         * SVD kernels, at most 144 rows and columns after
+                         * the QR preconditioning, else BBP_EGEOM) */
   int32_t precision;    /* bbp_precision */
   int32_t trunc;        /* bbp_trunc */
   int32_t rsvd_q;       /* T2 power iterations */
   int32_t rsvd_p;       /* T2 oversampling */
   uint64_t seed;        /* T2 sketch seed */
   void* stream;         /* borrowed hipStream_t; NULL: the library creates one */
+  int64_t hbm_budget_bytes; /* > 0: device memory the handle may take (resident
+                             * state plus workspace); create fails with
+                             * BBP_ENOMEM before allocating anything when the
+                             * plans need more.  0: no limit */
+  int32_t swallow_order;    /* order of the sums in a swallow (the same value):
+                             * 0 the cheaper by the plan's cost model, 1 merge
+                             * the in-leg run first, 2 absorb the ket tensor
+                             * site by site along the run */
+  int32_t reserved;         /* 0 */
 } pepsnet_desc;
 
-/* Build the geometry and plans, allocate device memory and copy the site
- * tensors (host pointer, complex128, see tensor order above; `sites_len` in
- * doubles) to the device.  Messages start as vec(I_D)/sqrt(D) on every leg. */
+/* Build the problem the thesis states for BlockBP (the lattice, its blocks
+ * and their faces; Sec. "Defining the Kagome block" for the hexagonal block
+ * of the infinite lattice, Eq. blockBP:DefiningEquation for the finite
+ * patch; free parameters d, D, chi and the block size, Ch. "ITE for Kagome
+ * using BlockBP"), compile the static plans of the message updates and
+ * expectations, allocate device memory and copy the site tensors (host
+ * pointer, complex128, see tensor order above; `sites_len` in doubles) to
+ * the device.  Messages start as vec(I_D)/sqrt(D) on every leg (a positive
+ * semi-definite start).  Inputs are copied; *out receives the handle, which
+ * owns all of its device memory.  Errors: BBP_EINVAL (bad descriptor or
+ * site buffer length; nothing allocated), BBP_EGEOM (the block or sweep
+ * order cannot be built), BBP_ENOMEM (over the HBM budget or allocation
+ * failure), BBP_EDEVICE, BBP_ENUMERIC (non-finite site tensor entry). */
 int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t sites_len,
                        pepsnet_t* out);
 
@@ -86,24 +111,55 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
 int32_t pepsnet_set_sites(pepsnet_t h, const double* sites, int64_t sites_len,
                           int32_t reset_messages);
 
-/* Run Jacobi sweeps: every message is recomputed from the previous sweep's
- * messages.  Stops after max_sweeps or when the largest Frobenius distance
- * between a message and its previous value (both unit norm, real positive
- * trace) is <= tol.  Returns BBP_NOT_CONVERGED if tol was not reached. */
+/* Run BlockBP sweeps (Alg. BlockBP_singleBlock on the infinite lattice: the
+ * message computed toward a face replaces the message on the opposite face;
+ * Eq. blockBP:DefiningEquation on a finite patch).  Each message is the
+ * contraction of its block with the other incoming messages by the
+ * boundary-MPS method, compressed to bond chi (Sec. "The boundary-MPS
+ * method"); every message of a sweep is computed from the previous sweep's
+ * messages (Jacobi).  Stops after max_sweeps or when the largest Frobenius
+ * distance between a message and its previous value (both unit norm, real
+ * positive trace; Eq. bp:convergenceCriterium) is <= tol.  *sweeps_done and
+ * *max_err (may be NULL) receive the sweeps run and the last distance.
+ * Returns BBP_OK, BBP_NOT_CONVERGED (tol not reached; outputs valid),
+ * BBP_EINVAL (max_sweeps < 0, workspace released), BBP_ENUMERIC (a message
+ * became non-finite; the sweep that produced it is counted) or
+ * BBP_EDEVICE. */
 int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
                       double* max_err);
 
-/* Two-site reduced density matrices and <S_i . S_j> for the default bonds:
- * the six unique bonds of the central unit cell (infinite lattice: U-DL,
- * U-DR, DL-DR, DR-DL(a1), U-DL(a2), U-DR(a2-a1)) or every bond of a finite
- * patch (ordered by first site then slot).  rho_out: n_bonds x 4 x 4 complex
- * (row (p_i p_j), column (p_i' p_j'), NULL to skip); ss_out: n_bonds doubles;
- * energy: energy per site ((1/3) sum of the six unique bonds; infinite
- * lattice only, else the mean bond energy).  n_bonds_out receives the count. */
-int32_t blockbp_expect(pepsnet_t h, double* rho_out, double* ss_out, double* energy,
+/* Local expectation values from the current messages: for every requested
+ * bond (i, j) the two-site reduced density matrix rho_ij is contracted from
+ * the block holding the bond with sites i and j left open and every incoming
+ * message absorbed (on a finite patch, the one or two blocks holding i and
+ * j), and <O> = Tr(rho_ij O) / Tr(rho_ij) for each requested operator.  The
+ * default operator is the Heisenberg bond term S_i . S_j with S = sigma / 2
+ * (Eq. res:afm-h:hamiltonian).
+ *   bond_ids: n_bonds indices into the bond table of pepsnet_bonds (the six
+ *             unique bonds of the central unit cell of the infinite lattice:
+ *             U-DL, U-DR, DL-DR, DR-DL(a1), U-DL(a2), U-DR(a2-a1); every
+ *             bond of a finite patch, ordered by first site then slot);
+ *             distinct; NULL: the whole table (n_bonds ignored).
+ *   ops:      n_ops operators, each 4 x 4 complex, row-major, in the basis
+ *             (p_i p_j) with p_i the bond's first site: ops[k][r][c] =
+ *             <r| O_k |c> (r, c = p_i * 2 + p_j); n_ops <= 64.  NULL: one
+ *             operator, S_i . S_j (n_ops ignored).
+ *   out:      n_bonds x n_ops complex <O_k> (NULL to skip).
+ *   rho_out:  n_bonds x 4 x 4 complex rho_ij, row (p_i p_j), column
+ *             (p_i' p_j'), not normalised (NULL to skip).
+ *   energy:   energy per site, (1/3) sum of <S . S> over the six unique bonds
+ *             (infinite lattice) or the mean bond energy (finite patch); only
+ *             with bond_ids NULL (else it must be NULL).
+ *   n_bonds_out: the number of bonds evaluated (may be NULL).
+ * Returns BBP_OK, BBP_EINVAL (bad ids or counts, energy with a bond subset,
+ * workspace released), BBP_ENUMERIC (zero or non-finite trace) or
+ * BBP_EDEVICE.  The first call with a new bond subset compiles its plan and
+ * allocates its descriptors. */
+int32_t blockbp_expect(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids, int32_t n_ops,
+                       const double* ops, double* out, double* rho_out, double* energy,
                        int32_t* n_bonds_out);
 
-/* Number of default bonds and their site pairs (2 ints per bond). */
+/* Number of bonds in the bond table and their site pairs (2 ints per bond). */
 int32_t pepsnet_bonds(pepsnet_t h, int32_t* pairs, int32_t cap, int32_t* n);
 
 /* Copy the current messages to host (complex128, each message's sites in

@@ -159,6 +159,10 @@ def truncated_split(M, chi, trunc="T1", q=2, p=8, key=None):
     return fix_columns(Q @ Ub[:, :keep], S[:keep, None] * Vh[:keep])
 
 
+# largest intermediate (elements) numpy may form inside one swallow's sum
+EINSUM_MAX_ELEMS = 1 << 27
+
+
 def _unfuse_dims(ch, j):
     D = ch.legdim[j]
     return [D, D] + [4] * len(ch.carries[j])
@@ -226,21 +230,15 @@ def swallow(ch, step, t, chi, trunc="T1", q=2, p=8, keyfn=None, d=2):
         for l in outs[1:]:
             out_labels += [out_k[l], out_b[l]]
         out_labels += [1]
-    # the sum over every repeated label of (run sites, t, conj t), taken as a
-    # chain of pairwise sums: t with the first run site, each further run
-    # site, then conj t.  Only the order of the pairwise sums differs from
-    # merging the run first; the value is the same and no intermediate holds
-    # the merged run (a D^(2r) chi^2 tensor).
-    def pair(X, xl, Y, yl):
-        shared = set(xl) & set(yl)
-        ol = [x for x in xl if x not in shared] + [y for y in yl if y not in shared]
-        return np.einsum(X, xl, Y, yl, ol), ol
-
-    R, rl = pair(run[0], run_labels[0], t, ket_t)
-    for j in range(1, r):
-        R, rl = pair(R, rl, run[j], run_labels[j])
-    R, rl = pair(R, rl, t.conj(), bra_t)
-    R = np.transpose(R, [rl.index(x) for x in out_labels])
+    # the sum over every repeated label of (run sites, t, conj t); numpy
+    # picks the order of the pairwise sums (the value does not depend on it),
+    # with intermediates capped at EINSUM_MAX_ELEMS so that no step holds the
+    # merged run (a D^(2r) chi^2 tensor) where that is large
+    ops = []
+    for A, lab in zip(run, run_labels):
+        ops += [A, lab]
+    R = np.einsum(*ops, t, ket_t, t.conj(), bra_t, out_labels,
+                  optimize=("greedy", EINSUM_MAX_ELEMS))
     Qtot = int(np.prod([4] * len(carry_ids))) if carry_ids else 1
     out_dims = [t.shape[1 + l] for l in outs]
     if s == 0:

@@ -15,7 +15,7 @@ BBP_KAGOME_OPEN, BBP_KAGOME_INF_HEX = 1, 2
 BBP_OK, BBP_NOT_CONVERGED, BBP_PENDING = 0, 1, 2
 BBP_FP64, BBP_FP32, BBP_BF16X3 = 0, 1, 2
 BBP_SVD_FULL, BBP_SVD_RAND = 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -33,7 +33,8 @@ class Desc(C.Structure):
                 ("hex_N", C.c_int32), ("d", C.c_int32), ("D", C.c_int32),
                 ("chi", C.c_int32), ("chi_env", C.c_int32), ("precision", C.c_int32),
                 ("trunc", C.c_int32), ("rsvd_q", C.c_int32), ("rsvd_p", C.c_int32),
-                ("seed", C.c_uint64), ("stream", C.c_void_p)]
+                ("seed", C.c_uint64), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_int64),
+                ("swallow_order", C.c_int32), ("reserved", C.c_int32)]
 
 
 def library_path():
@@ -55,7 +56,7 @@ def load_library():
         "pepsnet_create": (i32, [P(Desc), P(dbl), i64, P(vp)]),
         "pepsnet_set_sites": (i32, [vp, P(dbl), i64, i32]),
         "blockbp_sweep": (i32, [vp, i32, dbl, P(i32), P(dbl)]),
-        "blockbp_expect": (i32, [vp, P(dbl), P(dbl), P(dbl), P(i32)]),
+        "blockbp_expect": (i32, [vp, i32, P(i32), i32, P(dbl), P(dbl), P(dbl), P(dbl), P(i32)]),
         "pepsnet_bonds": (i32, [vp, P(i32), i32, P(i32)]),
         "pepsnet_get_messages": (i32, [vp, P(dbl), i64, P(i64)]),
         "pepsnet_set_messages": (i32, [vp, P(dbl), i64]),
@@ -99,10 +100,12 @@ def _check(rc):
 
 
 def make_desc(lattice, D, chi, Lx=0, Ly=0, bLx=0, bLy=0, hex_N=0, chi_env=None,
-              precision=BBP_FP64, trunc=BBP_SVD_FULL, q=2, p=8, seed=0, stream=None, d=2):
+              precision=BBP_FP64, trunc=BBP_SVD_FULL, q=2, p=8, seed=0, stream=None, d=2,
+              hbm_budget_bytes=0, swallow_order=0):
     return Desc(ABI_VERSION, lattice, Lx, Ly, bLx, bLy, hex_N, d, D, chi,
                 chi if chi_env is None else chi_env, precision, trunc, q, p, seed,
-                stream if stream is None else C.c_void_p(stream))
+                stream if stream is None else C.c_void_p(stream), int(hbm_budget_bytes),
+                int(swallow_order), 0)
 
 
 def _dptr(a):
@@ -160,15 +163,32 @@ class PepsNet:
         rc = _check(self.lib.blockbp_sweep(self.h, max_sweeps, tol, C.byref(done), C.byref(err)))
         return done.value, err.value, rc
 
-    def blockbp_expect(self):
+    def blockbp_expect(self, bond_ids=None, ops=None):
+        """(rho [n, 4, 4], values, energy).  values: <S.S> per bond (real)
+        without ``ops``, else an [n, n_ops] complex array of <O_k>; energy is
+        None for a bond subset."""
         n = C.c_int32(0)
         _check(self.lib.pepsnet_bonds(self.h, None, 0, C.byref(n)))
-        nb = n.value
+        ids = None
+        if bond_ids is not None:
+            ids = np.ascontiguousarray(bond_ids, np.int32)
+        nb = n.value if ids is None else ids.size
+        opa = None
+        nops = 1
+        if ops is not None:
+            opa = np.ascontiguousarray(np.asarray(ops, np.complex128).reshape(-1, 4, 4))
+            nops = opa.shape[0]
         rho = np.zeros(nb * 32, np.float64)
-        ss = np.zeros(nb, np.float64)
+        out = np.zeros(nb * nops * 2, np.float64)
         e = C.c_double(0.0)
-        _check(self.lib.blockbp_expect(self.h, _dptr(rho), _dptr(ss), C.byref(e), C.byref(n)))
-        return rho.view(np.complex128).reshape(nb, 4, 4), ss, e.value
+        _check(self.lib.blockbp_expect(
+            self.h, nb, None if ids is None else ids.ctypes.data_as(C.POINTER(C.c_int32)),
+            nops, None if opa is None else _dptr(opa.view(np.float64)), _dptr(out), _dptr(rho),
+            C.byref(e) if ids is None else None, C.byref(n)))
+        vals = out.view(np.complex128).reshape(nb, nops)
+        vals = vals[:, 0].real.copy() if opa is None else vals.copy()
+        return (rho.view(np.complex128).reshape(nb, 4, 4), vals,
+                e.value if ids is None else None)
 
     def bonds(self):
         n = C.c_int32(0)
@@ -176,7 +196,7 @@ class PepsNet:
         buf = np.zeros(2 * n.value, np.int32)
         _check(self.lib.pepsnet_bonds(self.h, buf.ctypes.data_as(C.POINTER(C.c_int32)),
                                       buf.size, C.byref(n)))
-        return [tuple(x) for x in buf.reshape(-1, 2)]
+        return [(int(a), int(b)) for a, b in buf.reshape(-1, 2)]
 
     def num_messages(self):
         return self.lib.pepsnet_num_messages(self.h)

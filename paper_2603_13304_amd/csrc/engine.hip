@@ -63,6 +63,9 @@ struct LaunchRec {
 };
 
 struct Compiled {
+  // device copy of the blob the launches' desc_off index (set when the blob
+  // is uploaded; a list is only ever launched against its own blob)
+  const char* desc = nullptr;
   std::vector<LaunchRec> launches;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -104,7 +107,24 @@ struct pepsnet_s {
   int64_t timed_sweeps = 0;
   int64_t site_len = 0;
   double* pinned = nullptr;   // host pinned: [0] sweep counter, [1..] distances
+  // expectation operators (blockbp_expect): up to kMaxOps 4x4 operators and
+  // their values per bond; the default bond selection (identity)
+  cplx* ops_dev = nullptr;
+  cplx* ops_out = nullptr;
+  const int32_t* sel_default = nullptr;
+  // plans of bond subsets: the default plan's lanes of the chosen bonds
+  // (their regions and rho slots are those of the default plan)
+  struct Subset {
+    Compiled plan[2];
+    std::vector<char> blob;
+    char* desc_dev = nullptr;
+    size_t rho_off[2] = {0, 0};
+    size_t sel_off = 0;
+    int64_t epoch = -1;
+  };
+  std::map<std::vector<int>, Subset> subsets;
 };
+constexpr int kMaxOps = 64;
 
 
 // ---- serving loop
@@ -554,7 +574,9 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
   return hipGetLastError();
 }
 
-int32_t run_launches(const char* desc_dev, hipStream_t stream, Compiled* c, bool graph) {
+int32_t run_launches(hipStream_t stream, Compiled* c, bool graph) {
+  const char* desc_dev = c->desc;
+  if (!desc_dev) return fail(BBP_EDEVICE, "launch list without uploaded descriptors");
   if (graph) {
     if (!c->exec) {
       PN_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -580,7 +602,7 @@ int32_t run_launches(const char* desc_dev, hipStream_t stream, Compiled* c, bool
 }
 
 int32_t run_compiled(pepsnet_s* h, Compiled* c, bool allow_graph) {
-  return run_launches(h->desc_dev, h->stream, c, allow_graph && h->use_graph);
+  return run_launches(h->stream, c, allow_graph && h->use_graph);
 }
 
 std::string build_problem(const pepsnet_desc* d, Problem* P) {
@@ -595,7 +617,10 @@ int32_t check_desc(const pepsnet_desc* d) {
   if (d->d != 2) return fail(BBP_EINVAL, "physical dimension must be 2 (spin 1/2)");
   if (d->D < 1 || d->D > 16) return fail(BBP_EINVAL, "D must be in [1, 16]");
   if (d->chi < 1 || d->chi > 256) return fail(BBP_EINVAL, "chi must be in [1, 256]");
-  if (d->chi_env != d->chi) return fail(BBP_EINVAL, "chi_env must equal chi");
+  if (d->chi_env != d->chi && d->chi_env != 0)
+    return fail(BBP_EINVAL, "chi_env must equal chi, or be 0 (exact contraction of the block)");
+  if (d->hbm_budget_bytes < 0) return fail(BBP_EINVAL, "negative HBM budget");
+  if (d->swallow_order < 0 || d->swallow_order > 2) return fail(BBP_EINVAL, "bad swallow order");
   if (d->precision < 0 || d->precision > 2) return fail(BBP_EINVAL, "bad precision");
   if (d->trunc < 0 || d->trunc > 1) return fail(BBP_EINVAL, "bad truncation mode");
   if (d->rsvd_q < 0 || d->rsvd_q > 8 || d->rsvd_p < 0 || d->rsvd_p > 64)
@@ -715,6 +740,9 @@ int32_t build_launches(pepsnet_s* h) {
     }
     rho_off[par] = push_descs(&h->desc_host, rd);
   }
+  std::vector<int32_t> sel(std::max(nb, 1));
+  for (int b = 0; b < nb; ++b) sel[b] = b;
+  const size_t sel_off = push_descs(&h->desc_host, sel);
   if (h->desc_dev) {
     PN_HIP(hipStreamSynchronize(h->stream));
     hipFree(h->desc_dev);
@@ -724,9 +752,67 @@ int32_t build_launches(pepsnet_s* h) {
     return fail(BBP_ENOMEM, "descriptor allocation failed");
   PN_HIP(hipMemcpyAsync(h->desc_dev, h->desc_host.data(), h->desc_host.size(),
                         hipMemcpyHostToDevice, h->stream));
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep})
+    c->desc = h->desc_dev;
   for (int par = 0; par < 2; ++par)
     h->rho_descs[par] = reinterpret_cast<RhoDesc*>(h->desc_dev + rho_off[par]);
+  h->sel_default = reinterpret_cast<const int32_t*>(h->desc_dev + sel_off);
   PN_HIP(hipStreamSynchronize(h->stream));
+  return BBP_OK;
+}
+
+void free_subsets(pepsnet_s* h) {
+  for (auto& kv : h->subsets) {
+    for (Compiled& c : kv.second.plan) {
+      if (c.exec) hipGraphExecDestroy(c.exec);
+      if (c.graph) hipGraphDestroy(c.graph);
+    }
+    if (kv.second.desc_dev) hipFree(kv.second.desc_dev);
+  }
+  h->subsets.clear();
+}
+
+// Launch list of the expectation of a bond subset (compiled on first use
+// and again after the workspace moved): the default plan's lanes of those
+// bonds, with their rho descriptors and the selection list.
+int32_t subset_plan(pepsnet_s* h, const std::vector<int>& ids, pepsnet_s::Subset** out) {
+  auto it = h->subsets.find(ids);
+  if (it != h->subsets.end() && it->second.epoch == h->work_epoch) {
+    *out = &it->second;
+    return BBP_OK;
+  }
+  if (it != h->subsets.end()) {
+    PN_HIP(hipStreamSynchronize(h->stream));
+    if (it->second.desc_dev) hipFree(it->second.desc_dev);
+    h->subsets.erase(it);
+  }
+  pepsnet_s::Subset S;
+  for (int par = 0; par < 2; ++par) {
+    LaneList lanes;
+    for (int b : ids) lanes.push_back(h->expect_lanes[par][b]);
+    compile_ops({{h, &lanes}}, &S.blob, &S.plan[par]);
+    std::vector<RhoDesc> rd;
+    for (int b : ids) {
+      RhoDesc r;
+      r.R = h->arena + h->region_base[RG_RHO] + h->rho_off[par][b];
+      r.rho = h->rho_mat + 16 * b;
+      r.ss = h->ss_dev + b;
+      r.first_is_i = h->carry_order[par][b][0] == h->bonds[b].first ? 1 : 0;
+      rd.push_back(r);
+    }
+    S.rho_off[par] = push_descs(&S.blob, rd);
+  }
+  std::vector<int32_t> sel(ids.begin(), ids.end());
+  S.sel_off = push_descs(&S.blob, sel);
+  if (hipMalloc(&S.desc_dev, std::max<size_t>(S.blob.size(), 256)) != hipSuccess)
+    return fail(BBP_ENOMEM, "descriptor allocation of a bond subset failed");
+  PN_HIP(hipMemcpyAsync(S.desc_dev, S.blob.data(), S.blob.size(), hipMemcpyHostToDevice, h->stream));
+  for (Compiled& c : S.plan) c.desc = S.desc_dev;
+  PN_HIP(hipStreamSynchronize(h->stream));
+  S.epoch = h->work_epoch;
+  auto& slot = h->subsets[ids];
+  slot = std::move(S);
+  *out = &slot;
   return BBP_OK;
 }
 
@@ -878,6 +964,7 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   h->opt.seed = desc->seed;
   h->opt.d = desc->d;
   h->opt.D = desc->D;
+  h->opt.order = desc->swallow_order;
   h->comp.reset(new Compiler(h->P, h->opt));
   if (!h->comp->error.empty()) return fail(BBP_EGEOM, h->comp->error);
   Plan sp[2], ep[2];
@@ -907,6 +994,17 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   }
   h->arena_len = tot;
   h->work_len = std::max<int64_t>(wtot, 32);
+  {
+    const int64_t nb = int64_t(h->bonds.size());
+    const int64_t need = (tot + h->work_len) * int64_t(sizeof(cplx)) +
+                         int64_t(C.n_scalars) * int64_t(sizeof(double)) +
+                         (17 + kMaxOps) * std::max<int64_t>(nb, 1) * int64_t(sizeof(cplx)) +
+                         16 * kMaxOps * int64_t(sizeof(cplx));
+    if (desc->hbm_budget_bytes > 0 && need > desc->hbm_budget_bytes)
+      return fail(BBP_ENOMEM, "the plans need " + std::to_string(need) +
+                                  " bytes of device memory, over the budget of " +
+                                  std::to_string(desc->hbm_budget_bytes));
+  }
   if (desc->stream) {
     h->stream = (hipStream_t)desc->stream;
   } else {
@@ -939,7 +1037,9 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   }
   int nb = int(h->bonds.size());
   if (hipMalloc(&h->rho_mat, size_t(std::max(nb, 1)) * 16 * sizeof(cplx)) != hipSuccess ||
-      hipMalloc(&h->ss_dev, size_t(std::max(nb, 1)) * sizeof(double)) != hipSuccess)
+      hipMalloc(&h->ss_dev, size_t(std::max(nb, 1)) * sizeof(double)) != hipSuccess ||
+      hipMalloc(&h->ops_dev, size_t(kMaxOps) * 16 * sizeof(cplx)) != hipSuccess ||
+      hipMalloc(&h->ops_out, size_t(std::max(nb, 1)) * kMaxOps * sizeof(cplx)) != hipSuccess)
     return fail(BBP_ENOMEM, "expectation buffers");
   for (int par = 0; par < 2; ++par)
     for (int b = 0; b < nb; ++b)
@@ -1019,29 +1119,83 @@ int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* swee
   return err <= tol ? BBP_OK : BBP_NOT_CONVERGED;
 }
 
-int32_t blockbp_expect(pepsnet_t h, double* rho_out, double* ss_out, double* energy,
+int32_t blockbp_expect(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids, int32_t n_ops,
+                       const double* ops, double* out, double* rho_out, double* energy,
                        int32_t* n_bonds_out) {
   if (!h) return fail(BBP_EINVAL, "null handle");
   if (int32_t rc = need_work(h)) return rc;
-  int nb = int(h->bonds.size());
-  int32_t rc = run_compiled(h, &h->expect[h->parity], false);
+  const int nb = int(h->bonds.size());
+  std::vector<int> ids;
+  if (bond_ids) {
+    if (n_bonds < 1 || n_bonds > nb) return fail(BBP_EINVAL, "bad number of bonds");
+    if (energy) return fail(BBP_EINVAL, "the energy needs the whole bond table (bond_ids NULL)");
+    std::vector<char> seen(nb, 0);
+    for (int b = 0; b < n_bonds; ++b) {
+      const int id = bond_ids[b];
+      if (id < 0 || id >= nb) return fail(BBP_EINVAL, "bond id out of range");
+      if (seen[id]) return fail(BBP_EINVAL, "bond id listed twice");
+      seen[id] = 1;
+      ids.push_back(id);
+    }
+  } else {
+    for (int b = 0; b < nb; ++b) ids.push_back(b);
+  }
+  if (ops && (n_ops < 1 || n_ops > kMaxOps)) return fail(BBP_EINVAL, "n_ops must be in [1, 64]");
+  const int ns = int(ids.size());
+  Compiled* plan = &h->expect[h->parity];
+  const RhoDesc* rdesc = h->rho_descs[h->parity];
+  const int32_t* sel = h->sel_default;
+  if (bond_ids) {
+    pepsnet_s::Subset* S = nullptr;
+    if (int32_t rc = subset_plan(h, ids, &S)) return rc;
+    plan = &S->plan[h->parity];
+    rdesc = reinterpret_cast<const RhoDesc*>(S->desc_dev + S->rho_off[h->parity]);
+    sel = reinterpret_cast<const int32_t*>(S->desc_dev + S->sel_off);
+  }
+  int32_t rc = run_compiled(h, plan, false);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_rho_ss, dim3((nb + 63) / 64), dim3(64), 0, h->stream, h->rho_descs[h->parity], nb);
+  hipLaunchKernelGGL(k_rho_ss, dim3((ns + 63) / 64), dim3(64), 0, h->stream, rdesc, ns);
   PN_HIP(hipGetLastError());
+  std::vector<cplx> vals;
+  if (ops && out) {
+    PN_HIP(hipMemcpyAsync(h->ops_dev, ops, size_t(n_ops) * 16 * sizeof(cplx),
+                          hipMemcpyHostToDevice, h->stream));
+    const int nt = ns * n_ops;
+    hipLaunchKernelGGL(k_rho_ops, dim3((nt + 63) / 64), dim3(64), 0, h->stream,
+                       (const cplx*)h->rho_mat, sel, ns, (const cplx*)h->ops_dev, n_ops, h->ops_out);
+    PN_HIP(hipGetLastError());
+    vals.resize(size_t(nt));
+    PN_HIP(hipMemcpyAsync(vals.data(), h->ops_out, size_t(nt) * sizeof(cplx),
+                          hipMemcpyDeviceToHost, h->stream));
+  }
   std::vector<double> ss(nb);
+  std::vector<cplx> rho;
   PN_HIP(hipMemcpyAsync(ss.data(), h->ss_dev, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  if (rho_out)
-    PN_HIP(hipMemcpyAsync(rho_out, h->rho_mat, size_t(nb) * 16 * sizeof(cplx), hipMemcpyDeviceToHost,
-                          h->stream));
+  if (rho_out) {
+    rho.resize(size_t(nb) * 16);
+    PN_HIP(hipMemcpyAsync(rho.data(), h->rho_mat, size_t(nb) * 16 * sizeof(cplx),
+                          hipMemcpyDeviceToHost, h->stream));
+  }
   PN_HIP(hipStreamSynchronize(h->stream));
   double e = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    if (!std::isfinite(ss[b])) return fail(BBP_ENUMERIC, "non-finite expectation value");
-    if (ss_out) ss_out[b] = ss[b];
-    e += ss[b];
+  for (int k = 0; k < ns; ++k) {
+    const double x = ss[ids[k]];
+    if (!std::isfinite(x)) return fail(BBP_ENUMERIC, "non-finite expectation value");
+    e += x;
   }
+  for (const cplx& v : vals)
+    if (!std::isfinite(v.re) || !std::isfinite(v.im))
+      return fail(BBP_ENUMERIC, "non-finite expectation value");
+  if (out) {
+    if (ops) std::memcpy(out, vals.data(), vals.size() * sizeof(cplx));
+    else
+      for (int k = 0; k < ns; ++k) { out[2 * k] = ss[ids[k]]; out[2 * k + 1] = 0.0; }
+  }
+  if (rho_out)
+    for (int k = 0; k < ns; ++k)
+      std::memcpy(rho_out + 32 * int64_t(k), rho.data() + 16 * int64_t(ids[k]), 16 * sizeof(cplx));
   if (energy) *energy = h->P.kind == 1 ? e / 3.0 : e / std::max(nb, 1);
-  if (n_bonds_out) *n_bonds_out = nb;
+  if (n_bonds_out) *n_bonds_out = ns;
   return BBP_OK;
 }
 
@@ -1160,11 +1314,11 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
       const LaunchRec& r = c.launches[i];
       const bool two = r.type == OPK_JACOBI && r.variant == 2;
       PN_HIP(hipEventRecord(ev[3 * i], h->stream));
-      hipError_t e = launch(h->desc_dev, h->stream, r, two ? 0 : -1);
+      hipError_t e = launch(c.desc, h->stream, r, two ? 0 : -1);
       if (e != hipSuccess) return fail(BBP_EDEVICE, hipGetErrorString(e));
       PN_HIP(hipEventRecord(ev[3 * i + 1], h->stream));
       if (two) {
-        e = launch(h->desc_dev, h->stream, r, 1);
+        e = launch(c.desc, h->stream, r, 1);
         if (e != hipSuccess) return fail(BBP_EDEVICE, hipGetErrorString(e));
       }
       PN_HIP(hipEventRecord(ev[3 * i + 2], h->stream));
@@ -1271,6 +1425,7 @@ int32_t pepsnet_batch_create(const pepsnet_t* hs, int32_t n, void* stream, pepsn
       return fail(BBP_ENOMEM, "batch descriptor allocation failed");
     PN_HIP(hipMemcpyAsync(b->desc_dev[v], b->desc_host[v].data(), b->desc_host[v].size(),
                           hipMemcpyHostToDevice, b->stream));
+    b->sweep[v].desc = b->desc_dev[v];
   }
   PN_HIP(hipEventCreate(&b->ev0));
   PN_HIP(hipEventCreate(&b->ev1));
@@ -1307,7 +1462,7 @@ int32_t blockbp_sweep_batch(pepsnet_batch_t b, int32_t sweeps, double* max_err, 
                             hipMemcpyHostToDevice, b->stream));
     }
     PN_HIP(hipEventRecord(b->ev0, b->stream));
-    int32_t rc = run_launches(b->desc_dev[var], b->stream, &b->sweep[var], b->use_graph);
+    int32_t rc = run_launches(b->stream, &b->sweep[var], b->use_graph);
     if (rc) return rc;
     PN_HIP(hipEventRecord(b->ev1, b->stream));
     for (pepsnet_s* h : b->hs) {
@@ -1464,8 +1619,11 @@ void pepsnet_destroy(pepsnet_t h) {
   if (h->work) hipFree(h->work);
   if (h->scal) hipFree(h->scal);
   if (h->desc_dev) hipFree(h->desc_dev);
+  free_subsets(h);
   if (h->rho_mat) hipFree(h->rho_mat);
   if (h->ss_dev) hipFree(h->ss_dev);
+  if (h->ops_dev) hipFree(h->ops_dev);
+  if (h->ops_out) hipFree(h->ops_out);
   if (h->pinned) hipHostFree(h->pinned);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);

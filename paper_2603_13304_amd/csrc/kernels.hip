@@ -2676,4 +2676,28 @@ __global__ void k_rho_ss(const RhoDesc* __restrict__ descs, int n) {
   for (int e = 0; e < 16; ++e) d.rho[e] = rho[e];
   *d.ss = trh / tr;
 }
+
+// <O_k> = Tr(rho O_k) / Tr(rho) for bond sel[b] (rho_mat holds 16 complex
+// per bond, [(p_i p_j), (p_i' p_j')]; O_k row-major in the (p_i p_j) basis),
+// one thread per (bond, operator), out[b * nops + k]
+__global__ void k_rho_ops(const cplx* __restrict__ rho_mat, const int32_t* __restrict__ sel,
+                          int nsel, const cplx* __restrict__ ops, int nops, cplx* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsel * nops) return;
+  const int b = t / nops, k = t - b * nops;
+  const cplx* r = rho_mat + 16 * sel[b];
+  const cplx* o = ops + 16 * k;
+  double tr = 0.0, ti = 0.0, sr = 0.0, si = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    tr += r[a * 4 + a].re;
+    ti += r[a * 4 + a].im;
+    for (int c = 0; c < 4; ++c) {
+      const cplx x = r[a * 4 + c], y = o[c * 4 + a];
+      sr += x.re * y.re - x.im * y.im;
+      si += x.re * y.im + x.im * y.re;
+    }
+  }
+  const double den = tr * tr + ti * ti;
+  out[t] = cplx{(sr * tr + si * ti) / den, (si * tr - sr * ti) / den};
+}
 }  // namespace pn

@@ -340,13 +340,16 @@ struct Compiler::Lane {
   }
 
   // truncated split of the m x n matrix M: writes L (m x keep) and R (keep x n)
+  // (chi_keep > 0: keep min(chi_keep, m, n) values by the exact SVD, the
+  // compression of an exactly contracted message)
   int split(Ref M, int64_t m, int64_t n, Ref Lout, Ref Rout, uint64_t prefix, bool sweep_tag,
-            int* keep_out) {
+            int* keep_out, int64_t chi_keep = 0) {
     const PlanOptions& o = C->opt;
     int64_t full = std::min(m, n);
-    int64_t keep = o.chi_env > 0 ? std::min<int64_t>(o.chi_env, full) : full;
+    int64_t keep = chi_keep > 0 ? std::min(chi_keep, full)
+                 : o.chi_env > 0 ? std::min<int64_t>(o.chi_env, full) : full;
     *keep_out = int(keep);
-    bool t2 = o.trunc == 1 && o.chi_env > 0 && o.chi_env + o.p < full;
+    bool t2 = chi_keep <= 0 && o.trunc == 1 && o.chi_env > 0 && o.chi_env + o.p < full;
     if (t2) {
       int64_t k = o.chi_env + o.p;
       Ref Om = scratch(n * k);
@@ -467,8 +470,9 @@ struct Compiler::Lane {
         prog_peak = std::max(prog_peak, rest * A.r);
       }
     }
-    const bool progressive = r > 1 && (merged_peak > double(kMergedPeakElems) ||
-                                       prog_cma < merged_cma);
+    const bool progressive =
+        r > 1 && (o.order == 2 || (o.order == 0 && (merged_peak > double(kMergedPeakElems) ||
+                                                    prog_cma < merged_cma)));
     Ref Y;
     if (!progressive) {
       Ref th = ch[pos].buf;
@@ -751,6 +755,30 @@ struct Compiler::Lane {
     move_center(ch, center, 0, 0);
     norm(ch[0].buf, int64_t(ch[0].l) * ch[0].P * ch[0].r, C->logscale_slot(id), -1);
   }
+
+  // Message of an exactly contracted block (no truncation inside the
+  // update), right-canonical with the centre at site 0: truncated to bond
+  // chi left to right by exact SVDs, then brought back to right-canonical
+  // form with unit norm.
+  void compress(std::vector<CSite>& ch, int& center) {
+    const int n = int(ch.size());
+    for (int j = 0; j + 1 < n; ++j) {
+      CSite& A = ch[j];
+      CSite& B = ch[j + 1];
+      const int64_t m = int64_t(A.l) * A.P, cols = A.r;
+      const int64_t keep = std::min<int64_t>(C->opt.chi, std::min(m, cols));
+      Ref Lq = chain_alloc(m * keep), Rq = scratch(keep * cols);
+      int kk = 0;
+      split(A.buf, m, cols, Lq, Rq, 0, false, &kk, C->opt.chi);
+      const int64_t bn = int64_t(B.P) * B.r;
+      Ref NB = chain_alloc(int64_t(kk) * bn);
+      gemm(Rq, B.buf, NB, kk, bn, cols, cols, bn, bn, OP_N, OP_N, PREC_FP64);
+      A.buf = Lq; A.r = kk;
+      B.buf = NB; B.l = kk;
+    }
+    center = n - 1;
+    right_canonical(ch, center);
+  }
 };
 
 // ------------------------------------------------------------- compiler
@@ -999,6 +1027,12 @@ bool Compiler::build_sweep(int parity, Plan* out) {
     }
     L.at(1, 1, 0);
     L.right_canonical(ch, center);
+    bool over = false;
+    for (const CSite& x : ch) over = over || x.r > opt.chi;
+    if (over) {
+      L.at(1, 5, 0);
+      L.compress(ch, center);
+    }
     for (size_t j = 0; j < ch.size(); ++j) {
       if (ch[j].r > msg.br[L.C->prob.stored_slot_of_update(m)][j] && opt.chi_env > 0) {
         error = "bond above the message cap (chi_env > chi is not supported)";

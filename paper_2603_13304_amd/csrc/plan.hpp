@@ -77,6 +77,7 @@ struct PlanOptions {
   uint64_t seed = 0;
   int d = 2;
   int D = 2;
+  int order = 0;       // swallow order: 0 cost model, 1 merged run, 2 progressive
 };
 
 // message storage layout (per slot: sites with cap shapes)

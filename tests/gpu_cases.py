@@ -17,17 +17,20 @@ def problem(kind, **kw):
         desc = pn.binding.make_desc(pn.BBP_KAGOME_OPEN, D=kw["D"], chi=kw["chi"], Lx=kw["Lx"],
                                     Ly=kw["Ly"], bLx=kw["bLx"], bLy=kw["bLy"],
                                     precision=kw.get("prec", 0), trunc=kw.get("trunc", 0),
-                                    q=kw.get("q", 2), p=kw.get("p", 8), seed=kw.get("seed", 0))
+                                    q=kw.get("q", 2), p=kw.get("p", 8), seed=kw.get("seed", 0),
+                                    chi_env=kw.get("chi_env"), swallow_order=kw.get("order", 0))
     else:
         P = geo.HexProblem(kw["N"])
         desc = pn.binding.make_desc(pn.BBP_KAGOME_INF_HEX, D=kw["D"], chi=kw["chi"], hex_N=kw["N"],
                                     precision=kw.get("prec", 0), trunc=kw.get("trunc", 0),
-                                    q=kw.get("q", 2), p=kw.get("p", 8), seed=kw.get("seed", 0))
+                                    q=kw.get("q", 2), p=kw.get("p", 8), seed=kw.get("seed", 0),
+                                    chi_env=kw.get("chi_env"), swallow_order=kw.get("order", 0))
     return P, desc
 
 
-def oracle_for(P, ts, chi, trunc, q, p, seed):
-    return BlockBP(P, ts, chi=chi, chi_env=chi, trunc="T2" if trunc else "T1", q=q, p=p, seed=seed)
+def oracle_for(P, ts, chi, trunc, q, p, seed, chi_env=None):
+    return BlockBP(P, ts, chi=chi, chi_env=chi if chi_env is None else chi_env,
+                   trunc="T2" if trunc else "T1", q=q, p=p, seed=seed)
 
 
 def slot_keys(P):
@@ -52,9 +55,21 @@ def message_diff(g, O, P):
 def oracle_bond_energies(O, bonds):
     """Per-bond <S.S> from the oracle, with None where a truncation in the
     bond's contraction was ambiguous (degenerate singular values at the cut)."""
+    return [None if r is None else ss_from_rho(r) for r in oracle_rhos(O, bonds)]
+
+
+def oracle_rhos(O, bonds):
+    """Per-bond rho_ij from the oracle (not normalised: <S.S> is
+    Re Tr(rho h) / Re Tr(rho), which differs from the value of rho / Tr rho
+    when a non-Hermitian start makes the trace complex), None where a
+    truncation in the bond's contraction was ambiguous."""
     out = []
     for n, (i, j) in enumerate(bonds):
         bb.DEGENERATE.clear()
-        v = ss_from_rho(O.rho(i, j, n))
-        out.append(None if bb.DEGENERATE else v)
+        r = O.rho(i, j, n)
+        out.append(None if bb.DEGENERATE else r)
     return out
+
+
+def unit(r):
+    return r / np.trace(r)

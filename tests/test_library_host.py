@@ -5,9 +5,11 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from oracle import geometry as geo
+from synth import inputs as syn
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pepsnet.h")
@@ -125,3 +127,24 @@ def test_bad_descriptors_are_rejected():
     h = ctypes.c_void_p()
     rc = lib.pepsnet_create(ctypes.byref(desc), None, 0, ctypes.byref(h))
     assert rc == -1 and not h.value
+
+
+def test_hbm_budget_rejects_before_allocating():
+    """pepsnet_create compiles the plans, finds that they need more device
+    memory than the descriptor's budget and fails with BBP_ENOMEM before any
+    device call (so this runs without a GPU)."""
+    lib = _lib()
+    desc = pn.make_desc(pn.BBP_KAGOME_INF_HEX, D=2, chi=4, hex_N=2, hbm_budget_bytes=1 << 16)
+    h = ctypes.c_void_p()
+    ts = syn.random_unit_cell(2, seed=1)
+    flat = np.concatenate([t.reshape(-1) for t in ts]).view(np.float64)
+    rc = lib.pepsnet_create(ctypes.byref(desc), flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            flat.size, ctypes.byref(h))
+    assert rc == -2 and not h.value
+    assert b"budget" in lib.pepsnet_last_error()
+    # exact mode (chi_env = 0) is accepted by the descriptor check; other
+    # chi_env values are not
+    for bad in (3, -1):
+        d2 = pn.make_desc(pn.BBP_KAGOME_INF_HEX, D=2, chi=4, hex_N=2, chi_env=bad)
+        rc = lib.pepsnet_create(ctypes.byref(d2), None, 0, ctypes.byref(h))
+        assert rc == -1
