@@ -1,27 +1,28 @@
 #!/usr/bin/env python3
 """BlockBP message-update throughput on one MI355X.
 
-Sections after the headline line (on by default unless noted): a batched
-sweep of 64 independent blocks of uneven N, D, chi against sweeping them one
-handle at a time; a serving run (Poisson stream of expectation requests on
-resident states) with continuous batching against one request at a time;
-and, with --precision-report, the FP32 / split-BF16 contraction error at
-N=4, D=6, chi=64.
+Headline workload (the largest single-GPU configuration): the infinite
+kagome lattice, hexagonal block of face length N=4 (111 sites), D=6, chi=64,
+site tensors from 20 second-order simple-update imaginary-time steps
+(dtau=0.05, Heisenberg J=1, seed 2), randomized truncation (Halko,
+Martinsson & Tropp 2011, Alg. 4.4; q=2, p=8), contraction GEMMs in FP64
+(complex128, the oracle's arithmetic), QR / SVD / normalisation FP64.
+Messages start from identity; the warmup sweeps bring them to full bond
+dimension.  One step is one Jacobi sweep: all six message updates of the
+block plus the convergence distance.
 
-Workload (the paper's infinite-kagome setting at its benchmark size): a
-hexagonal block of face length N=3 (57 sites) of the infinite kagome PEPS,
-D=3, chi=16, site tensors from 20 second-order simple-update imaginary-time
-steps (dtau=0.05, Heisenberg J=1, seed 2), messages from identity.  One step
-is one Jacobi sweep: all six message updates of the block (boundary-chain
-contraction, QR/truncated SVD, normalisation) plus the convergence distance.
-
-Prints one JSON line: message updates per second over the timed sweeps, the
-dominant kernel's roofline figures (timed live with HIP events on the
-library's stream), expectation-value latency (p50/p99 of blockbp_expect once
-converged to 1e-5), and the FP64 oracle timed on the host cores on a bounded
-sample.
+Printed as one JSON line: message updates per second over the timed sweeps;
+the dominant kernel's roofline figures (timed live with HIP events on the
+library's stream) and the contraction GEMMs' fraction of the FP64 MFMA
+peak; expectation-value latency (p50/p99 of blockbp_expect once the sweep
+has converged or stalled, with the distance reached); the same workload with
+FP32 and split-BF16 contraction GEMMs (throughput and |dE/site| against
+FP64); the FP64 oracle timed on the host cores on one message update; and
+the sections after it (N=3, D=3, chi=16 with exact truncation; a batched
+sweep of 64 independent blocks; the serving loop).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,6 +39,8 @@ PEAKS = {  # MI355X published peaks
     "fp32_tflops": 157.3,
     "bf16_tflops": 2500.0,
 }
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+DTYPE = {"fp64": "c128", "fp32": "c64+f64", "bf16x3": "bf16x3+f64"}
 
 
 def parse():
@@ -45,33 +48,122 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--trunc", choices=["T1", "T2"], default="T1")
-    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default="fp32")
-    ap.add_argument("--N", type=int, default=3)
-    ap.add_argument("--D", type=int, default=3)
-    ap.add_argument("--chi", type=int, default=16)
+    ap.add_argument("--trunc", choices=["T1", "T2"], default="T2")
+    ap.add_argument("--precision", choices=list(PREC), default="fp64")
+    ap.add_argument("--N", type=int, default=4)
+    ap.add_argument("--D", type=int, default=6)
+    ap.add_argument("--chi", type=int, default=64)
     ap.add_argument("--q", type=int, default=2)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--profile-sweeps", type=int, default=3)
-    ap.add_argument("--expect-reps", type=int, default=10)
+    ap.add_argument("--profile-sweeps", type=int, default=2)
+    ap.add_argument("--expect-reps", type=int, default=5)
+    ap.add_argument("--converge-sweeps", type=int, default=20,
+                    help="sweeps toward 1e-5 before the expectation latency")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip the FP32 / split-BF16 runs of the headline workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the N=3, D=3, chi=16 section")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-sweep section")
     ap.add_argument("--batched-blocks", type=int, default=64)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
-    ap.add_argument("--serving-states", type=int, default=8)
-    ap.add_argument("--serving-requests", type=int, default=16)
-    ap.add_argument("--serving-inflight", type=int, default=4)
-    ap.add_argument("--precision-report", action="store_true",
-                    help="add the FP32 / split-BF16 error report at N=4, D=6, chi=64")
+    ap.add_argument("--serving-states", type=int, default=32)
+    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-inflight", type=int, default=8)
     return ap.parse_args()
 
 
+def workload_name(args, precision):
+    nt = 3 * (3 * args.N ** 2 - 3 * args.N + 1)
+    return (f"infinite kagome BlockBP, hexagonal block N={args.N} ({nt} sites), D={args.D}, "
+            f"chi={args.chi}, simple-update tensors (20 steps, dtau=0.05, seed 2), "
+            f"{args.trunc} truncation (q={args.q}, p={args.p}), {precision} contraction GEMMs, "
+            "FP64 QR/SVD/normalisation, messages from identity")
+
+
+def make_net(args, precision, ts):
+    import paper_2603_13304_amd as pn
+    from paper_2603_13304_amd.binding import make_desc
+    desc = make_desc(pn.BBP_KAGOME_INF_HEX, D=args.D, chi=args.chi, hex_N=args.N,
+                     precision=PREC[precision], trunc=1 if args.trunc == "T2" else 0,
+                     q=args.q, p=args.p, seed=7)
+    g = pn.PepsNet(desc, ts)
+    g.use_graph(not args.no_graph)
+    return g
+
+
+def timed_sweeps(g, warmup, steps):
+    g.blockbp_sweep(warmup, 0.0)
+    g.timing(reset=True)
+    t0 = time.perf_counter()
+    done, err, _ = g.blockbp_sweep(steps, 0.0)
+    wall = time.perf_counter() - t0
+    assert done == steps
+    dev_ms, _ = g.timing(reset=True)
+    return wall, dev_ms, err
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary, or None when there is none or kernels.hip changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, "paper_2603_13304_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec.get("kernels_hip_sha256"):
+            return None
+    return rec.get("kernels", {}).get(kernel)
+
+
+KERNEL_NAMES = {"gemm_fp64": "k_gemm", "gemm_fp32": "k_gemm", "gemm_bf16x3": "k_gemm",
+                "chol": "k_chol", "jacobi": "k_jacobi", "qr": "k_qr", "qr_tall": "k_qr_tall",
+                "svd_bidiag": "k_svt_bidiag", "svd_top": "k_svd_top", "norm": "k_norm_apply",
+                "ksum": "k_sum_parts", "transpose": "k_permute", "pad": "k_pad",
+                "split_gauge": "k_colphase", "sketch": "k_omega", "msg_phase": "k_phase"}
+
+
+def roofline(prof, n_sweeps):
+    """Dominant kernel of the profiled sweeps against its bound, and the
+    contraction GEMMs' FP64/FP32/BF16 MFMA fractions."""
+    name, (kms, nl, kfl, kby) = max(prof.items(), key=lambda kv: kv[1][0])
+    avg_s = kms / nl / 1e3
+    if name.startswith("gemm"):
+        bound, unit = "mfma", "TFLOP/s"
+        peak = {"gemm_fp64": PEAKS["fp64_tflops"], "gemm_fp32": PEAKS["fp32_tflops"],
+                "gemm_bf16x3": PEAKS["bf16_tflops"]}[name]
+        achieved = kfl / nl / avg_s / 1e12
+    elif name in ("qr", "qr_tall", "jacobi", "svd_bidiag", "svd_top", "chol"):
+        bound, unit, peak = "alu", "TFLOP/s", PEAKS["fp64_tflops"]
+        achieved = kfl / nl / avg_s / 1e12
+    else:
+        bound, unit, peak = "hbm", "GB/s", PEAKS["hbm_GBs"]
+        achieved = kby / nl / avg_s / 1e9
+    tr = traffic_record(KERNEL_NAMES.get(name, name))
+    out = {"bound": bound, "kernel": name, "achieved": round(achieved, 6), "peak": peak,
+           "unit": unit, "frac": achieved / peak,
+           "traffic": None if tr is None else tr["bytes_per_launch"],
+           "avg_launch_us": round(avg_s * 1e6, 3), "ms_per_sweep": round(kms / n_sweeps, 3)}
+    mfma = {}
+    for k, pk in (("gemm_fp64", "fp64_tflops"), ("gemm_fp32", "fp32_tflops"),
+                  ("gemm_bf16x3", "bf16_tflops")):
+        if k in prof:
+            ms, n, fl, _ = prof[k]
+            tf = fl / (ms / 1e3) / 1e12
+            mfma[k] = {"tflops": round(tf, 3), "frac_of_peak": tf / PEAKS[pk],
+                       "ms_per_sweep": round(ms / n_sweeps, 3), "launches_per_sweep": n // n_sweeps}
+    return out, mfma
+
+
 def cpu_baseline(ts, args):
-    """The FP64 oracle, as it stands, on a bounded sample of the same
-    workload: identity start, sweeps until ~10 s of work (at least one)."""
+    """The FP64 oracle, as it stands, on one message update of the same
+    workload (the first of a sweep's six) from seeded messages in the
+    converged regime's shapes (every bond at its full dimension)."""
     from oracle import geometry as geo
     from oracle.blockbp import BlockBP
+    from synth import inputs as syn
     try:
         from threadpoolctl import threadpool_info
         cores = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
@@ -80,17 +172,56 @@ def cpu_baseline(ts, args):
     P = geo.HexProblem(args.N)
     O = BlockBP(P, ts, chi=args.chi, chi_env=args.chi, trunc=args.trunc, q=args.q, p=args.p,
                 seed=7)
-    n, t0 = 0, time.perf_counter()
-    while True:
-        O.sweep()
-        n += 1
-        if time.perf_counter() - t0 > 10.0 or n >= 5:
-            break
+    keys = list(range(6))
+    shapes = [[x.shape for x in O.msgs[k]] for k in keys]
+    for k, A in zip(keys, syn.random_messages(shapes, 41)):
+        O.msgs[k] = A
+    t0 = time.perf_counter()
+    O.update(P.msg_keys[0])
     dt = time.perf_counter() - t0
-    upd = n * len(P.msg_keys)
-    return {"value": upd / dt, "unit": "msg_updates/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{n} sweeps ({upd} message updates) of the same workload from identity "
-                      f"messages, {args.trunc} truncation, numpy FP64, {dt:.1f} s"}
+    return {"value": 1.0 / dt, "unit": "msg_updates/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"1 message update (one of the 6 in a sweep) of the same workload from "
+                      f"seeded full-rank messages, {args.trunc} truncation, numpy FP64, {dt:.1f} s"}
+
+
+def precision_runs(args, ts, fp64_msgs, e_fp64, err_fp64):
+    """The headline workload with FP32 and split-BF16 contraction GEMMs:
+    throughput over timed sweeps, and the error of one sweep plus the
+    expectation from the same FP64 messages against FP64."""
+    out = {}
+    for prec in ("fp32", "bf16x3"):
+        g = make_net(args, prec, ts)
+        wall, _, _ = timed_sweeps(g, 1, 3)
+        g.set_messages(fp64_msgs)
+        _, err, _ = g.blockbp_sweep(1, 0.0)
+        _, ss, e = g.blockbp_expect()
+        g.close()
+        out[prec] = {"msg_updates_per_s": 6 * 3 / wall, "ms_per_sweep": 1e3 * wall / 3,
+                     "abs_dE_per_site_vs_fp64": abs(e - e_fp64),
+                     "abs_d_convergence_distance_vs_fp64": abs(err - err_fp64)}
+        print(f"[bench] {prec}: {6 * 3 / wall:.2f} updates/s, |dE| {abs(e - e_fp64):.2e}",
+              file=sys.stderr, flush=True)
+    return out
+
+
+def small_section(args):
+    """N=3, D=3, chi=16 with exact truncated SVDs (T1), FP32 contraction: the
+    round-trip-latency-bound end of the method."""
+    from synth import inputs as syn
+    a = argparse.Namespace(**vars(args))
+    a.N, a.D, a.chi, a.trunc = 3, 3, 16, "T1"
+    ts = syn.simple_update_cell(3, seed=2, steps=20, dtau=0.05)
+    g = make_net(a, "fp32", ts)
+    wall, dev_ms, _ = timed_sweeps(g, 5, 20)
+    g.blockbp_sweep(40, 1e-5)
+    lat = []
+    for _ in range(5):
+        t = time.perf_counter()
+        g.blockbp_expect()
+        lat.append(1e3 * (time.perf_counter() - t))
+    g.close()
+    return {"workload": workload_name(a, "fp32"), "msg_updates_per_s": 6 * 20 / wall,
+            "ms_per_sweep": 1e3 * wall / 20, "expect_latency_ms_p50": float(np.median(lat))}
 
 
 def batched_section(args):
@@ -207,47 +338,6 @@ def serving_section(args):
                               "latency_p99_s": float(np.percentile(lat_s, 99))}}
 
 
-def precision_section():
-    """FP32 and split-BF16 contraction against the FP64 path at N=4, D=6,
-    chi=64 (randomized truncation): the same input messages (FP64 after two
-    sweeps) go through one sweep and the expectation in each precision."""
-    import paper_2603_13304_amd as pn
-    from paper_2603_13304_amd.binding import make_desc
-    from synth import inputs as syn
-    ts = syn.simple_update_cell(6, seed=2, steps=20, dtau=0.05)
-    nets = {}
-    for prec in (0, 1, 2):
-        desc = make_desc(pn.BBP_KAGOME_INF_HEX, D=6, chi=64, hex_N=4, precision=prec, trunc=1,
-                         q=2, p=8, seed=7)
-        nets[prec] = pn.PepsNet(desc, ts)
-    nets[0].blockbp_sweep(2, 0.0)
-    start = nets[0].get_messages()
-    out = {}
-    for prec in (0, 1, 2):
-        g = nets[prec]
-        if prec:
-            g.set_messages(start)
-        t0 = time.perf_counter()
-        _, err, _ = g.blockbp_sweep(1, 0.0)
-        dt = time.perf_counter() - t0
-        _, ss, e = g.blockbp_expect()
-        out[prec] = (g.get_messages(), np.array(ss), e, err, dt)
-        print(f"[bench] precision {prec}: sweep {dt:.2f} s, E {e:.12f}", file=sys.stderr, flush=True)
-    rep = {"workload": "infinite kagome, hexagonal block N=4 (111 sites), D=6, chi=64, "
-                       "simple-update tensors, randomized truncation (q=2, p=8); one sweep and "
-                       "the expectation from the same FP64 messages"}
-    for prec, name in ((1, "fp32"), (2, "bf16x3")):
-        m0, ss0, e0, err0, _ = out[0]
-        m1, ss1, e1, err1, dt = out[prec]
-        rep[name] = {"abs_dE_per_site": abs(e1 - e0), "max_abs_d_bond_ss": float(np.abs(ss1 - ss0).max()),
- "abs_d_convergence_distance": abs(err1 - err0),
-                     "sweep_s": dt}
-    rep["fp64_sweep_s"] = out[0][4]
-    for g in nets.values():
-        g.close()
-    return rep
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -255,109 +345,77 @@ def main():
               "(the sweep would shard its six message updates over GPUs with one all-gather "
               "per sweep; not built)", file=sys.stderr)
         sys.exit(2)
-    import paper_2603_13304_amd as pn
-    from paper_2603_13304_amd.binding import make_desc, profile_sweeps
+    from paper_2603_13304_amd.binding import profile_sweeps
     from synth import inputs as syn
 
-    prec = {"fp64": 0, "fp32": 1, "bf16x3": 2}[args.precision]
-    trunc = 1 if args.trunc == "T2" else 0
     ts = syn.simple_update_cell(args.D, seed=2, steps=20, dtau=0.05)
-    desc = make_desc(pn.BBP_KAGOME_INF_HEX, D=args.D, chi=args.chi, hex_N=args.N,
-                     precision=prec, trunc=trunc, q=args.q, p=args.p, seed=7)
-    g = pn.PepsNet(desc, ts)
-    g.use_graph(not args.no_graph)
+    g = make_net(args, args.precision, ts)
     n_msg = g.num_messages()
     print(f"[bench] created N={args.N} D={args.D} chi={args.chi} {args.trunc} {args.precision}",
           file=sys.stderr, flush=True)
-
-    # warmup sweeps (messages reach full bond dimension, graph gets captured)
-    g.blockbp_sweep(args.warmup, 0.0)
-    print(f"[bench] warmup {args.warmup} sweeps done", file=sys.stderr, flush=True)
-    # timed region: exactly K sweeps
-    import ctypes
-    lib = g.lib
-    g.timing(reset=True)
-    t0 = time.perf_counter()
-    done, err, _ = g.blockbp_sweep(args.steps, 0.0)
-    t1 = time.perf_counter()
-    assert done == args.steps
-    dev_ms, _ = g.timing(reset=True)
-    wall = t1 - t0
+    # warmup sweeps (messages reach full bond dimension, graph captured),
+    # then exactly K timed sweeps
+    wall, dev_ms, err_timed = timed_sweeps(g, args.warmup, args.steps)
     ms_per_step = 1e3 * wall / args.steps
     value = n_msg * args.steps / wall
-    print(f"[bench] timed {args.steps} sweeps: {ms_per_step:.3f} ms/sweep, {value:.1f} updates/s",
+    print(f"[bench] timed {args.steps} sweeps: {ms_per_step:.2f} ms/sweep, {value:.3f} updates/s",
           file=sys.stderr, flush=True)
-
     # per-kernel live timing (HIP events on the library's stream)
     prof = profile_sweeps(g, args.profile_sweeps)
-    dom = max(prof.items(), key=lambda kv: kv[1][0])
-    name, (kms, nl, kfl, kby) = dom
-    avg_s = kms / nl / 1e3
-    if name.startswith("gemm"):
-        bound, unit = "mfma", "TFLOP/s"
-        peak = {"gemm_fp64": PEAKS["fp64_tflops"], "gemm_fp32": PEAKS["fp32_tflops"],
-                "gemm_bf16x3": PEAKS["bf16_tflops"]}[name]
-        achieved = kfl / nl / avg_s / 1e12
-    elif name in ("qr", "qr_tall", "jacobi", "svd_bidiag", "svd_top"):
-        bound, unit, peak = "alu", "TFLOP/s", PEAKS["fp64_tflops"]
-        achieved = kfl / nl / avg_s / 1e12
-    else:
-        bound, unit, peak = "hbm", "GB/s", PEAKS["hbm_GBs"]
-        achieved = kby / nl / avg_s / 1e9
-    total_ms = sum(v[0] for v in prof.values()) / args.profile_sweeps
-    breakdown = {k: {"ms_per_sweep": round(v[0] / args.profile_sweeps, 4),
+    roof, mfma = roofline(prof, args.profile_sweeps)
+    breakdown = {k: {"ms_per_sweep": round(v[0] / args.profile_sweeps, 3),
                      "launches_per_sweep": v[1] // args.profile_sweeps,
-                     "avg_us": round(1e3 * v[0] / v[1], 3)} for k, v in sorted(prof.items())}
+                     "avg_us": round(1e3 * v[0] / v[1], 2)} for k, v in sorted(prof.items())}
     cf, gf, nlaunch = g.sweep_stats()
-
-    # expectation latency once converged to 1e-5
-    g.blockbp_sweep(60, 1e-5)
+    # expectation latency once converged to 1e-5 (or after converge_sweeps)
+    sw, err_c, _ = g.blockbp_sweep(args.converge_sweeps, 1e-5)
+    msgs = g.get_messages()
     lat = []
     for _ in range(args.expect_reps):
         t = time.perf_counter()
         _, ss, e = g.blockbp_expect()
         lat.append(1e3 * (time.perf_counter() - t))
-    lat = np.array(lat)
-
+    _, err_next, _ = g.blockbp_sweep(1, 0.0)
+    g.set_messages(msgs)
+    g.close()
     out = {
         "metric": "block msg updates/s + % MFMA peak; p50/p99 expect-value latency at 1e-5",
-        "value": round(value, 3),
+        "value": round(value, 4),
         "unit": "msg_updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "c128", "fp32": "c64+f64", "bf16x3": "bf16x3+f64"}[args.precision],
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"infinite kagome BlockBP, hexagonal block N={args.N} "
-                               f"({3 * (3 * args.N ** 2 - 3 * args.N + 1)} sites), D={args.D}, "
-                               f"chi={args.chi}, simple-update tensors (20 steps, dtau=0.05), "
-                               f"{args.trunc} truncation (q={args.q}, p={args.p}), "
-                               f"{args.precision} contraction GEMMs, FP64 QR/SVD",
+        "config": {"workload": workload_name(args, args.precision),
                    "message_updates_per_step": n_msg, "graph": not args.no_graph},
-        "roofline": {"bound": bound, "kernel": name, "achieved": round(achieved, 6),
-                     "peak": peak, "unit": unit, "frac": achieved / peak, "traffic": None,
-                     "avg_launch_us": round(avg_s * 1e6, 3)},
+        "roofline": roof,
+        "mfma": mfma,
         "expect_latency_ms": {"p50": float(np.percentile(lat, 50)),
                               "p99": float(np.percentile(lat, 99)),
+                              "sweeps_before": sw, "distance_reached": err_c,
+                              "tolerance_reached": bool(err_c <= 1e-5),
                               "energy_per_site": e, "bonds": len(ss)},
-        "sweep": {"device_ms": round(dev_ms, 4), "launches": int(nlaunch),
-                  "contraction_gflop": cf / 1e9, "gemm_gflop": gf / 1e9,
-                  "profiled_kernel_ms": round(total_ms, 4), "kernels": breakdown},
+        "sweep": {"device_ms": round(dev_ms, 3), "launches": int(nlaunch),
+                  "contraction_gflop": cf / 1e9, "gemm_gflop": gf / 1e9, "kernels": breakdown},
     }
-    g.close()
+    if not args.no_precisions and args.precision == "fp64":
+        out["precisions"] = precision_runs(args, ts, msgs, e, err_next)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ts, args)
+        print(f"[bench] oracle: {out['cpu_baseline']['sample']}", file=sys.stderr, flush=True)
+    if not args.no_small:
+        out["small_block"] = small_section(args)
+        print("[bench] small block done", file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = batched_section(args)
     if not args.no_serving:
         out["serving"] = serving_section(args)
-    if args.precision_report:
-        out["precision_report"] = precision_section()
     print(json.dumps(out), flush=True)
 
 

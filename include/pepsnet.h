@@ -192,7 +192,8 @@ int32_t pepsnet_sweep_stats(pepsnet_t h, double* contraction_flops, double* gemm
  * the handle's stream around every launch and accumulate, per kernel slot
  * (slot = kind * 3 + precision for GEMMs, kind * 3 otherwise, kinds: 0 GEMM,
  * 1 transpose, 2 QR, 3 truncated SVD, 4 sketch, 5 norm, 6 pad, 7 message
- * phase, 8 split gauge, 9 Cholesky step of the tall QR; slot 7 is the
+ * phase, 8 split gauge, 9 Cholesky step of the tall QR, 10 sum of split-K
+ * partial products; slot 7 is the
  * blocked QR for working copies that overflow LDS; the truncated SVD is
  * slot 9 through one-sided Jacobi, or slot 10 for its bidiagonalisation
  * kernel and slot 11 for the kernel computing the kept values and vectors),
@@ -200,9 +201,16 @@ int32_t pepsnet_sweep_stats(pepsnet_t h, double* contraction_flops, double* gemm
  * per complex multiply-add) and bytes of the launches.  The Gram and Q
  * products of the tall QR count as GEMMs.  Arrays hold
  * PEPSNET_PROFILE_SLOTS entries; NULL skips an output. */
-#define PEPSNET_PROFILE_SLOTS 30
+#define PEPSNET_PROFILE_SLOTS 33
 int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_t* launches,
                                double* flops, double* bytes);
+
+/* Run one sweep launch by launch with a HIP event after each launch and
+ * report, per launch of the sweep's launch list, 10 doubles: op kind (as
+ * above), precision, kernel variant, items, largest M, N, K (GEMM) or rows,
+ * cols (factorisations), algorithmic flops, algorithmic bytes, milliseconds.
+ * With rec NULL only *n (launches) is set; cap counts doubles. */
+int32_t pepsnet_profile_launches(pepsnet_t h, double* rec, int64_t cap, int64_t* n);
 
 /* ---- batched sweeps (independent blocks of uneven N, D, chi in one launch
  * sequence).  BlockBP message updates of different blocks are independent

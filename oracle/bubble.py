@@ -313,6 +313,30 @@ def compress(A, chi):
     return ch.A
 
 
+def schmidt_spectra(A):
+    """Singular values of every cut of an open MPS (gauge-invariant): a
+    left-to-right QR sweep gives X_j with left part = Q X_j, a right-to-left
+    sweep of QR factorisations of the transposed sites gives Y_j with right
+    part = Y_j Q', and the cut's values are those of X_j Y_j."""
+    n = len(A)
+    X = [None] * n
+    R = np.ones((1, 1), complex)
+    for j in range(n - 1):
+        M = np.tensordot(R, A[j], axes=([1], [0]))
+        l, P, r = M.shape
+        _, R = qr_pos(M.reshape(l * P, r))
+        X[j] = R
+    out = [None] * (n - 1)
+    L = np.ones((1, 1), complex)
+    for j in range(n - 1, 0, -1):
+        M = np.tensordot(A[j], L, axes=([2], [0]))
+        l, P, r = M.shape
+        _, Rt = qr_pos(M.reshape(l, P * r).T)
+        L = Rt.T
+        out[j - 1] = np.linalg.svd(X[j - 1] @ L, compute_uv=False)
+    return out
+
+
 def trace(A, dims):
     """Trace of an MPS message read as an operator (ket legs rows, bra legs
     columns): contract each site's leg with vec(I_D)."""

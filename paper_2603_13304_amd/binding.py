@@ -67,6 +67,7 @@ def load_library():
         "pepsnet_use_graph": (i32, [vp, i32]),
         "pepsnet_sweep_stats": (i32, [vp, P(dbl), P(dbl), P(i64)]),
         "pepsnet_profile_sweeps": (i32, [vp, i32, P(dbl), P(i64), P(dbl), P(dbl)]),
+        "pepsnet_profile_launches": (i32, [vp, P(dbl), i64, P(i64)]),
         "pepsnet_destroy": (None, [vp]),
         "pepsnet_last_error": (C.c_char_p, []),
         "pepsnet_describe": (i32, [P(Desc), i32, i32, i32, i32, P(i32), P(i32), i64, P(i64)]),
@@ -355,14 +356,14 @@ class Server:
 
 
 PROFILE_KINDS = ["gemm", "transpose", "qr", "jacobi", "sketch", "norm", "pad", "msg_phase",
-                 "split_gauge", "chol"]
+                 "split_gauge", "chol", "ksum"]
 PREC_NAMES = ["fp64", "fp32", "bf16x3"]
 
 
 def profile_sweeps(net, n_sweeps):
     """Per-kernel HIP-event timing of ``n_sweeps`` sweeps: dict slot name ->
     (ms, launches, flops, bytes)."""
-    n = 30
+    n = 33
     ms = np.zeros(n)
     nl = np.zeros(n, np.int64)
     fl = np.zeros(n)
@@ -383,3 +384,13 @@ def profile_sweeps(net, n_sweeps):
                 name = "svd_top"
             out[name] = (float(ms[k]), int(nl[k]), float(fl[k]), float(by[k]))
     return out
+
+
+def profile_launches(net):
+    """One sweep timed launch by launch: array [n, 10] of (kind, precision,
+    variant, items, M, N, K, flops, bytes, ms)."""
+    n = C.c_int64(0)
+    _check(net.lib.pepsnet_profile_launches(net.h, None, 0, C.byref(n)))
+    rec = np.zeros(10 * n.value)
+    _check(net.lib.pepsnet_profile_launches(net.h, _dptr(rec), rec.size, C.byref(n)))
+    return rec.reshape(-1, 10)

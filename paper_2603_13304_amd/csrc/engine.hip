@@ -60,6 +60,7 @@ struct LaunchRec {
   double gemm_flops = 0.0, contraction_flops = 0.0;
   double flops = 0.0;    // algorithmic flops of the launch (8 per complex MAC)
   double bytes = 0.0;    // algorithmic bytes moved (operands read once, results written once)
+  int64_t shape[3] = {0, 0, 0};   // GEMM: largest M, N, K of the launch; QR / SVD: rows, cols
 };
 
 struct Compiled {
@@ -200,13 +201,21 @@ size_t push_descs(std::vector<char>* blob, const std::vector<T>& v) {
 // kernel variant an op runs with (part of its bucket key, so that an item
 // runs the same kernel whether it is launched alone or in a batch)
 int op_variant(const Op& op) {
-  if (op.type == OPK_GEMM) return op.i[0] <= 16 ? 1 : op.i[1] <= 16 ? 2 : 0;   // k_gemm tile shape
+  if (op.type == OPK_GEMM) {   // k_gemm tile shape
+    const int64_t M = op.i[0], N = op.i[1];
+    if (M <= 16) return 1;
+    if (N <= 16) return 2;
+    if (N > 64 && N <= 80) return 3;
+    if (M > 64 && M <= 80) return 4;
+    return 0;
+  }
   if (op.type == OPK_QR) {
     // QRK_CHOL shapes are expanded by the plan compiler; the blocked tall
     // kernel takes any that reach here
     const int v = qr_kernel(op.i[0], op.i[1], op.c.valid());
     return v == QRK_CHOL ? QRK_TALL : v;
   }
+  if (op.type == OPK_CHOL) return op.i[1] <= CHB_N ? 1 : 0;   // k_chol_b / k_chol
   if (op.type == OPK_JACOBI) {
     if (op.i[5]) return 2;   // k_svd_top
     const int rows = int(op.i[0]), cols = int(op.i[1]);
@@ -277,6 +286,9 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             }
             mM = std::max<int64_t>(mM, g.M);
             mN = std::max<int64_t>(mN, g.N);
+            rec.shape[0] = mM;
+            rec.shape[1] = mN;
+            rec.shape[2] = std::max<int64_t>(rec.shape[2], g.K);
             double f = 8.0 * double(g.M) * double(g.N) * double(g.K);
             rec.gemm_flops += f;
             rec.flops += f;
@@ -285,7 +297,8 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             v.push_back(g);
           }
           rec.desc_off = push_descs(blob, v);
-          const int tm = rec.variant == 1 ? 16 : 64, tn = rec.variant == 2 ? 16 : 64;
+          const int tm = rec.variant == 1 ? 16 : rec.variant == 4 ? 80 : 64;
+          const int tn = rec.variant == 2 ? 16 : rec.variant == 3 ? 80 : 64;
           rec.grid = dim3(unsigned((mN + tn - 1) / tn),
                           unsigned(std::min<int64_t>(65535, (mM + tm - 1) / tm)), unsigned(v.size()));
           break;
@@ -325,6 +338,8 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             q.Q = resolve(h, op->c); q.R = resolve(h, op->d);
             q.m = int(op->i[0]); q.n = int(op->i[1]); q.lda = int(op->i[2]); q.conjT = int(op->i[3]);
             q.qh = int(op->i[4]);
+            rec.shape[0] = std::max<int64_t>(rec.shape[0], q.m);
+            rec.shape[1] = std::max<int64_t>(rec.shape[1], q.n);
             double m = q.m, n = q.n, k = std::min(q.m, q.n);
             // Householder R (complex: 8 flops per MAC), plus the same again
             // for the explicit Q
@@ -354,6 +369,8 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             jd.sigma = reinterpret_cast<double*>(resolve(h, op->d));
             jd.rows = int(op->i[0]); jd.cols = int(op->i[1]); jd.lda = int(op->i[2]);
             jd.conjT = int(op->i[3]); jd.keep = int(op->i[4]); jd.gauge = int(op->i[6]);
+            rec.shape[0] = std::max<int64_t>(rec.shape[0], jd.rows);
+            rec.shape[1] = std::max<int64_t>(rec.shape[1], jd.cols);
             if (rec.variant == 2) {
               // complex Householder bidiagonalisation, 4 x (4 m n^2 - 4 n^3 / 3)
               const double m = jd.rows, n = jd.cols;
@@ -406,10 +423,11 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             rec.bytes += 32.0 * double(nd.len);
             nd.logscale = op->s0.off >= 0 ? h->scal + op->s0.off : nullptr;
             nd.norm_out = op->s1.off >= 0 ? h->scal + op->s1.off : nullptr;
+            nd.part = reinterpret_cast<double*>(resolve(h, op->b));
             v.push_back(nd);
           }
           rec.desc_off = push_descs(blob, v);
-          rec.grid = dim3(unsigned(v.size()));
+          rec.grid = dim3(unsigned(NORM_CHUNKS), unsigned(v.size()));
           break;
         }
         case OPK_PAD: {
@@ -432,6 +450,25 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
           rec.grid = dim3(unsigned(std::min<int64_t>(4096, (mt + 255) / 256)), unsigned(v.size()));
           break;
         }
+        case OPK_SUM: {
+          std::vector<SumDesc> v;
+          int64_t mt = 1;
+          for (const auto& ho : ops) {
+            pepsnet_s* h = ho.first;
+            const Op* op = ho.second;
+            SumDesc sd;
+            sd.P = resolve(h, op->a); sd.C = resolve(h, op->c);
+            sd.S = int(op->i[0]); sd.M = int(op->i[1]); sd.N = int(op->i[2]);
+            sd.ldc = int(op->i[3]);
+            sd.alpha = cplx{op->x[0], op->x[1]};
+            mt = std::max<int64_t>(mt, int64_t(sd.M) * sd.N);
+            rec.bytes += 16.0 * double(sd.M) * sd.N * (sd.S + 1.0);
+            v.push_back(sd);
+          }
+          rec.desc_off = push_descs(blob, v);
+          rec.grid = dim3(unsigned(std::min<int64_t>(1024, (mt + 255) / 256)), unsigned(v.size()));
+          break;
+        }
         case OPK_CHOL: {
           std::vector<CholDesc> v;
           for (const auto& ho : ops) {
@@ -441,6 +478,8 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             c.G = resolve(h, op->a); c.Rinv = resolve(h, op->b); c.R = resolve(h, op->c);
             c.S = int(op->i[0]); c.n = int(op->i[1]); c.shift = int(op->i[2]);
             c.accumulate = int(op->i[3]); c.m = op->i[4];
+            rec.shape[0] = std::max<int64_t>(rec.shape[0], c.m);
+            rec.shape[1] = std::max<int64_t>(rec.shape[1], c.n);
             const double n = c.n;
             // Cholesky, triangular inverse, and the running factor's product
             // (n^3 / 3 complex multiply-adds each), 8 flops per complex MAC
@@ -454,16 +493,18 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
         }
         case OPK_COLPHASE: {
           std::vector<ColPhaseDesc> v;
+          int kmax = 1;
           for (const auto& ho : ops) {
             pepsnet_s* h = ho.first;
             const Op* op = ho.second;
             ColPhaseDesc c;
             c.L = resolve(h, op->a); c.R = resolve(h, op->b);
             c.m = int(op->i[0]); c.keep = int(op->i[1]); c.n = int(op->i[2]);
+            kmax = std::max(kmax, c.keep);
             v.push_back(c);
           }
           rec.desc_off = push_descs(blob, v);
-          rec.grid = dim3(unsigned(v.size()));
+          rec.grid = dim3(unsigned(v.size()), unsigned((kmax + 3) / 4));
           break;
         }
         case OPK_PHASE: {
@@ -503,11 +544,14 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
   dim3 blk(256);
   switch (r.type) {
     case OPK_GEMM: {
-      // variant = tile shape: 0 64x64, 1 16x64 (M <= 16), 2 64x16 (N <= 16)
+      // variant = tile shape: 0 64x64, 1 16x64 (M <= 16), 2 64x16 (N <= 16),
+      // 3 64x80 (64 < N <= 80), 4 80x64 (64 < M <= 80)
       const GemmDesc* gd = (const GemmDesc*)d;
 #define PN_GEMM(PP)                                                                         \
   if (r.variant == 1) hipLaunchKernelGGL((k_gemm<PP, 1>), r.grid, blk, 0, stream, gd);      \
   else if (r.variant == 2) hipLaunchKernelGGL((k_gemm<PP, 2>), r.grid, blk, 0, stream, gd); \
+  else if (r.variant == 3) hipLaunchKernelGGL((k_gemm<PP, 3>), r.grid, blk, 0, stream, gd); \
+  else if (r.variant == 4) hipLaunchKernelGGL((k_gemm<PP, 4>), r.grid, blk, 0, stream, gd); \
   else hipLaunchKernelGGL((k_gemm<PP, 0>), r.grid, blk, 0, stream, gd);
       if (r.prec == PREC_FP64) {
         PN_GEMM(PREC_FP64)
@@ -556,7 +600,8 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
       hipLaunchKernelGGL(k_omega, r.grid, blk, 0, stream, (const OmegaDesc*)d);
       break;
     case OPK_NORM:
-      hipLaunchKernelGGL(k_normalize, r.grid, blk, 0, stream, (const NormDesc*)d);
+      hipLaunchKernelGGL(k_norm_partial, r.grid, blk, 0, stream, (const NormDesc*)d);
+      hipLaunchKernelGGL(k_norm_apply, r.grid, blk, 0, stream, (const NormDesc*)d);
       break;
     case OPK_PAD:
       hipLaunchKernelGGL(k_pad, r.grid, blk, 0, stream, (const PadDesc*)d);
@@ -568,7 +613,14 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
       hipLaunchKernelGGL(k_colphase, r.grid, blk, 0, stream, (const ColPhaseDesc*)d);
       break;
     case OPK_CHOL:
-      hipLaunchKernelGGL(k_chol, r.grid, dim3(CHOL_THREADS), 0, stream, (const CholDesc*)d);
+      // blocked form up to 80 columns, packed column-by-column form above
+      if (r.variant == 1)
+        hipLaunchKernelGGL(k_chol_b, r.grid, dim3(CHOL_THREADS), 0, stream, (const CholDesc*)d);
+      else
+        hipLaunchKernelGGL(k_chol, r.grid, dim3(CHOL_THREADS), 0, stream, (const CholDesc*)d);
+      break;
+    case OPK_SUM:
+      hipLaunchKernelGGL(k_sum_parts, r.grid, blk, 0, stream, (const SumDesc*)d);
       break;
   }
   return hipGetLastError();
@@ -1355,6 +1407,41 @@ int32_t pepsnet_profile_sweeps(pepsnet_t h, int32_t n_sweeps, double* ms, int64_
     if (flops) flops[k] = tfl[k];
     if (bytes) bytes[k] = tby[k];
   }
+  return BBP_OK;
+}
+
+int32_t pepsnet_profile_launches(pepsnet_t h, double* rec, int64_t cap, int64_t* n) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (int32_t rc = need_work(h)) return rc;
+  Compiled& c = h->sweep[h->parity];
+  const int64_t nl = int64_t(c.launches.size());
+  if (n) *n = nl;
+  if (!rec) return BBP_OK;
+  if (cap < 10 * nl) return fail(BBP_EINVAL, "buffer too small");
+  std::vector<hipEvent_t> ev(nl + 1);
+  for (auto& e : ev) PN_HIP(hipEventCreate(&e));
+  h->pinned[0] = double(h->sweeps_total);
+  PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
+                        hipMemcpyHostToDevice, h->stream));
+  PN_HIP(hipEventRecord(ev[0], h->stream));
+  for (int64_t i = 0; i < nl; ++i) {
+    hipError_t e = launch(c.desc, h->stream, c.launches[i]);
+    if (e != hipSuccess) return fail(BBP_EDEVICE, hipGetErrorString(e));
+    PN_HIP(hipEventRecord(ev[i + 1], h->stream));
+  }
+  PN_HIP(hipStreamSynchronize(h->stream));
+  for (int64_t i = 0; i < nl; ++i) {
+    const LaunchRec& r = c.launches[i];
+    float ms = 0.0f;
+    PN_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    double* o = rec + 10 * i;
+    o[0] = r.type; o[1] = r.prec; o[2] = r.variant; o[3] = r.count;
+    o[4] = double(r.shape[0]); o[5] = double(r.shape[1]); o[6] = double(r.shape[2]);
+    o[7] = r.flops; o[8] = r.bytes; o[9] = ms;
+  }
+  for (auto& e : ev) hipEventDestroy(e);
+  h->parity ^= 1;
+  h->sweeps_total += 1;
   return BBP_OK;
 }
 

@@ -65,11 +65,20 @@ __device__ __forceinline__ cplx ld_op(gptr<const cplx> X, int ld, int op, int r,
 // each; 2 = 64x16 for N <= 16, four waves along M.  The narrow shapes stop
 // the matrix cores from multiplying padding on products with 16 or fewer rows
 // or columns.
+// 3 = 64x80 for 64 < N <= 80, four waves along M, each 16 x 80 (five
+// blocks); 4 = 80x64 for 64 < M <= 80, four waves along N, each 80 x 16.
+// They cover the sketch width chi + p = 72 with 11 % padding instead of 78 %.
 template <int SH>
 struct GemmTile {
-  static constexpr int TM = SH == 1 ? 16 : 64, TN = SH == 2 ? 16 : 64;
-  static constexpr int IB = SH == 0 ? 2 : 1, JB = SH == 0 ? 2 : 1;   // 16x16 blocks per wave
+  static constexpr int TM = SH == 1 ? 16 : SH == 4 ? 80 : 64;
+  static constexpr int TN = SH == 2 ? 16 : SH == 3 ? 80 : 64;
+  static constexpr int IB = SH == 0 ? 2 : SH == 4 ? 5 : 1;   // 16x16 blocks per wave
+  static constexpr int JB = SH == 0 ? 2 : SH == 3 ? 5 : 1;
 };
+// workgroups per CU the register budget is set for (two waves per SIMD
+// for FP64 / FP32; the split-BF16 tiles keep the full budget)
+template <int P>
+struct GemmOcc { static constexpr int value = P == PREC_BF16X3 ? 1 : 2; };
 
 template <int P>
 struct GemmCfg;
@@ -101,14 +110,32 @@ __device__ __forceinline__ int64_t gemm_sc_offset(const GemmDesc* __restrict__ g
   return off + (int64_t)x * g->sc_ds[k0];
 }
 
+// The descriptor's scalar fields are read into a small struct (the
+// scatter-store tables stay behind the pointer and are read only by the
+// tiles that use them).
+struct GemmArgs {
+  const cplx* A;
+  const cplx* B;
+  cplx* C;
+  int M, N, K, lda, ldb, ldc, opA, opB, sc_n, sc_nr, sc_conj;
+  cplx alpha, beta;
+};
+
 template <int P, int SH>
-__global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs) {
+__global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc* __restrict__ descs) {
   constexpr int GT_M = GemmTile<SH>::TM, GT_N = GemmTile<SH>::TN;
   constexpr int IB = GemmTile<SH>::IB, JB = GemmTile<SH>::JB;
   typedef typename GemmCfg<P>::T T;
   constexpr int TK = GemmCfg<P>::TK;
   constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;
-  const GemmDesc g = descs[blockIdx.z];
+  const GemmDesc* const gp0 = descs + blockIdx.z;
+  GemmArgs g;
+  g.A = gp0->A; g.B = gp0->B; g.C = gp0->C;
+  g.M = gp0->M; g.N = gp0->N; g.K = gp0->K;
+  g.lda = gp0->lda; g.ldb = gp0->ldb; g.ldc = gp0->ldc;
+  g.opA = gp0->opA; g.opB = gp0->opB;
+  g.sc_n = gp0->sc_n; g.sc_nr = gp0->sc_nr; g.sc_conj = gp0->sc_conj;
+  g.alpha = gp0->alpha; g.beta = gp0->beta;
   const int n0 = blockIdx.x * GT_N;
   if (n0 >= g.N) return;
   const gptr<const cplx> Ag = to_global(g.A), Bg = to_global(g.B);
@@ -118,8 +145,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   // M tiles are grid-strided (the grid's y extent is capped at 65535)
   for (int m0 = blockIdx.y * GT_M; m0 < g.M; m0 += gridDim.y * GT_M) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = SH == 0 ? (wave >> 1) * 32 : SH == 2 ? wave * 16 : 0;
-  const int wn = SH == 0 ? (wave & 1) * 32 : SH == 1 ? wave * 16 : 0;
+  const int wm = SH == 0 ? (wave >> 1) * 32 : (SH == 2 || SH == 3) ? wave * 16 : 0;
+  const int wn = SH == 0 ? (wave & 1) * 32 : (SH == 1 || SH == 4) ? wave * 16 : 0;
   typedef typename std::conditional<P == PREC_FP64, d4, f4>::type acc_t;
   acc_t accr[IB][JB], acci[IB][JB];
   for (int i = 0; i < IB; ++i)
@@ -127,55 +154,86 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
       accr[i][j] = acc_t{0, 0, 0, 0};
       acci[i][j] = acc_t{0, 0, 0, 0};
     }
-  // op(A)[m0:m0+64, k0:k0+TK] and op(B)[k0:k0+TK, n0:n0+64] pass through
+  // op(A)[m0:m0+TM, k0:k0+TK] and op(B)[k0:k0+TK, n0:n0+TN] pass through
   // registers: with 16-deep slices the next one is loaded while the current
-  // one is used (the 32-deep split-BF16 slices would need too many registers)
+  // one is used (the 32-deep split-BF16 slices would need too many
+  // registers).  Each thread's elements keep their operand pointer (advanced
+  // by one slice per load), their K index, their row / column test and
+  // their LDS slot, set once per output tile.
   constexpr int EA = GT_M * TK / 256, EB = GT_N * TK / 256;
   constexpr bool PF = TK == 16;
+  const bool conjA = g.opA == OP_C, conjB = g.opB == OP_C;
+  const int64_t stA = g.opA == OP_N ? TK : (int64_t)TK * g.lda;
+  const int64_t stB = g.opB == OP_N ? (int64_t)TK * g.ldb : TK;
+  gptr<const cplx> pA[EA], pB[EB];
+  int kA[EA], kB[EB], lA[EA], lB[EB];
+  bool okA[EA], okB[EB];
+#pragma unroll
+  for (int q = 0; q < EA; ++q) {
+    const int e = tid + 256 * q;
+    int mm, kk;
+    if (g.opA == OP_N) { mm = e / TK; kk = e % TK; } else { mm = e % GT_M; kk = e / GT_M; }
+    const int r = m0 + mm;
+    okA[q] = r < g.M;
+    kA[q] = kk;
+    lA[q] = kk * (GT_M + PAD) + mm;
+    pA[q] = Ag + (okA[q] ? (g.opA == OP_N ? (int64_t)r * g.lda + kk : (int64_t)kk * g.lda + r) : 0);
+  }
+#pragma unroll
+  for (int q = 0; q < EB; ++q) {
+    const int e = tid + 256 * q;
+    int nn, kk;
+    if (g.opB == OP_N) { nn = e % GT_N; kk = e / GT_N; } else { kk = e % TK; nn = e / TK; }
+    const int c = n0 + nn;
+    okB[q] = c < g.N;
+    kB[q] = kk;
+    lB[q] = kk * (GT_N + PAD) + nn;
+    pB[q] = Bg + (okB[q] ? (g.opB == OP_N ? (int64_t)kk * g.ldb + c : (int64_t)c * g.ldb + kk) : 0);
+  }
   cplx pa[EA], pb[EB];
-  auto fetch = [&](int k0) {
+  int kload = 0;   // K offset of the next slice to load
+  auto fetch = [&]() {
 #pragma unroll
     for (int q = 0; q < EA; ++q) {
-      const int e = tid + 256 * q;
-      int mm, kk;
-      if (g.opA == OP_N) { mm = e / TK; kk = e % TK; } else { mm = e % GT_M; kk = e / GT_M; }
-      const int r = m0 + mm, c = k0 + kk;
-      pa[q] = (r < g.M && c < g.K) ? ld_op(Ag, g.lda, g.opA, r, c) : cplx{0.0, 0.0};
+      cplx x = {0.0, 0.0};
+      if (okA[q] && kload + kA[q] < g.K) x = pA[q][0];
+      if (conjA) x.im = -x.im;
+      pa[q] = x;
+      pA[q] += stA;
     }
 #pragma unroll
     for (int q = 0; q < EB; ++q) {
-      const int e = tid + 256 * q;
-      int nn, kk;
-      if (g.opB == OP_N) { nn = e % GT_N; kk = e / GT_N; } else { kk = e % TK; nn = e / TK; }
-      const int r = k0 + kk, c = n0 + nn;
-      pb[q] = (r < g.K && c < g.N) ? ld_op(Bg, g.ldb, g.opB, r, c) : cplx{0.0, 0.0};
+      cplx x = {0.0, 0.0};
+      if (okB[q] && kload + kB[q] < g.K) x = pB[q][0];
+      if (conjB) x.im = -x.im;
+      pb[q] = x;
+      pB[q] += stB;
     }
+    kload += TK;
   };
-  if constexpr (PF) fetch(0);
+  T* const Asr = &As_r[0][0];
+  T* const Asi = &As_i[0][0];
+  T* const Bsr = &Bs_r[0][0];
+  T* const Bsi = &Bs_i[0][0];
+  if constexpr (PF) fetch();
   for (int k0 = 0; k0 < g.K; k0 += TK) {
-    if constexpr (!PF) fetch(k0);
+    if constexpr (!PF) fetch();
 #pragma unroll
     for (int q = 0; q < EA; ++q) {
-      const int e = tid + 256 * q;
-      int mm, kk;
-      if (g.opA == OP_N) { mm = e / TK; kk = e % TK; } else { mm = e % GT_M; kk = e / GT_M; }
-      As_r[kk][mm] = (T)pa[q].re;
-      As_i[kk][mm] = (T)pa[q].im;
+      Asr[lA[q]] = (T)pa[q].re;
+      Asi[lA[q]] = (T)pa[q].im;
     }
 #pragma unroll
     for (int q = 0; q < EB; ++q) {
-      const int e = tid + 256 * q;
-      int nn, kk;
-      if (g.opB == OP_N) { nn = e % GT_N; kk = e / GT_N; } else { kk = e % TK; nn = e / TK; }
-      Bs_r[kk][nn] = (T)pb[q].re;
-      Bs_i[kk][nn] = (T)pb[q].im;
+      Bsr[lB[q]] = (T)pb[q].re;
+      Bsi[lB[q]] = (T)pb[q].im;
     }
     if constexpr (PF) {
-      if (k0 + TK < g.K) fetch(k0 + TK);
+      if (k0 + TK < g.K) fetch();
     }
     __syncthreads();
     if constexpr (P == PREC_FP64 || P == PREC_FP32) {
-#pragma unroll
+#pragma unroll 2
       for (int kk = 0; kk < TK; kk += 4) {
         const int kq = kk + (lane >> 4);
         T ar[IB], ai[IB], br[JB], bi[JB];
@@ -322,6 +380,12 @@ template __global__ void k_gemm<PREC_BF16X3, 1>(const GemmDesc*);
 template __global__ void k_gemm<PREC_FP64, 2>(const GemmDesc*);
 template __global__ void k_gemm<PREC_FP32, 2>(const GemmDesc*);
 template __global__ void k_gemm<PREC_BF16X3, 2>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP64, 3>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP32, 3>(const GemmDesc*);
+template __global__ void k_gemm<PREC_BF16X3, 3>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP64, 4>(const GemmDesc*);
+template __global__ void k_gemm<PREC_FP32, 4>(const GemmDesc*);
+template __global__ void k_gemm<PREC_BF16X3, 4>(const GemmDesc*);
 
 // --------------------------------------------------------------- permute
 __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ descs) {
@@ -1129,55 +1193,106 @@ __global__ __launch_bounds__(QRT_THREADS) void k_qr_tall(const QrDesc* __restric
 }
 
 // ------------------------------------------------------------ Cholesky QR
-// k_chol: the Cholesky step of the tall QR (see CholDesc).  The Gram matrix
-// sits in LDS (n <= 80: 100 KB).  The right-looking factorisation takes one
-// barrier per step: every thread reads the finished row j and updates its
-// elements of the trailing upper triangle with the unscaled row and the
-// factor 1 / G_jj; the rows of R are scaled once the loop is done.  R^-1 is
+// k_chol: the Cholesky step of the tall QR (see CholDesc), one workgroup of
+// 16 waves per item (fewer waves cost more in serial updates per step than
+// they save in barriers: 214 against 137 us at n = 72).  The upper triangle is kept packed in LDS (row i
+// from i (2n - i + 1) / 2; n <= 128: 129 KB); when the running factor is
+// updated and the two triangles fit (n <= 92), the previous factor is staged
+// in LDS behind it.  The partial Gram matrices are summed eight elements at
+// a time with their loads in flight together.  The right-looking
+// factorisation takes one barrier per step: every thread reads the finished
+// row j and updates its elements of the trailing triangle with the unscaled
+// row and the factor 1 / G_jj; the rows of R are scaled afterwards.  R^-1 is
 // then formed in place column by column (column j of R^-1 needs R^-1 of the
-// leading block, stored over the finished columns, and column j of R), with
-// a 16-lane group per row.
+// leading block, stored over the finished columns, and column j of R), a
+// 16-lane group per row.
 constexpr int CHOL_THREADS = 1024;
-constexpr int CHOL_PER_THREAD = (CHOLQR_MAXN * CHOLQR_MAXN + CHOL_THREADS - 1) / CHOL_THREADS;
+constexpr int CHOL_PACKED = CHOLQR_MAXN * (CHOLQR_MAXN + 1) / 2;
+constexpr int CHOL_ROUND = 4;   // packed elements per thread per load round
+
+__device__ __forceinline__ int chol_off(int n, int i, int j) { return i * (2 * n - i + 1) / 2 + (j - i); }
+
+// (row, column) of packed index e (row: the largest i with chol_off(i, i) <= e)
+__device__ __forceinline__ void chol_ij(int n, int e, int* i, int* j) {
+  const double b = 2.0 * n + 1.0;
+  int r = (int)((b - sqrt(b * b - 8.0 * e)) * 0.5);
+  r = r < 0 ? 0 : (r > n - 1 ? n - 1 : r);
+  while (r > 0 && chol_off(n, r, r) > e) --r;
+  while (r + 1 < n && chol_off(n, r + 1, r + 1) <= e) ++r;
+  *i = r;
+  *j = r + (e - chol_off(n, r, r));
+}
 
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol(const CholDesc* __restrict__ descs) {
   const CholDesc d = descs[blockIdx.x];
-  const int n = d.n, tid = threadIdx.x, nn = n * n;
-  __shared__ cplx A[CHOLQR_MAXN * CHOLQR_MAXN];
+  const int n = d.n, tid = threadIdx.x, nn = n * n, np = n * (n + 1) / 2;
+  __shared__ cplx A[CHOL_PACKED];
   __shared__ double rd[CHOLQR_MAXN], ird[CHOLQR_MAXN];
   __shared__ cplx tcol[CHOLQR_MAXN];
   __shared__ double sc[2];
   if (n > CHOLQR_MAXN) return;   // excluded by the plan compiler
   const gptr<const cplx> G = to_global(d.G);
-  // summed upper triangle, partials in order (deterministic)
-  for (int e = tid; e < nn; e += CHOL_THREADS) {
-    const int i = e / n, j = e - i * n;
-    cplx s = {0.0, 0.0};
-    if (i <= j)
-      for (int p = 0; p < d.S; ++p) {
-        const cplx g = G[(int64_t)p * nn + e];
-        s.re += g.re;
-        s.im += g.im;
+  const bool want_r = d.R != nullptr;
+  const bool acc_r = want_r && d.accumulate;
+  const bool stage = acc_r && 2 * np <= CHOL_PACKED;   // previous R behind A
+  cplx* const Rs = A + np;
+  const gptr<cplx> Rg = to_global(d.R);
+  // sum of the partials in order (deterministic); the previous R when staged
+  for (int e0 = tid; e0 < np; e0 += CHOL_THREADS * CHOL_ROUND) {
+    int full[CHOL_ROUND];
+    cplx acc[CHOL_ROUND];
+#pragma unroll
+    for (int q = 0; q < CHOL_ROUND; ++q) {
+      const int e = e0 + q * CHOL_THREADS;
+      full[q] = -1;
+      acc[q] = cplx{0.0, 0.0};
+      if (e < np) {
+        int i, j;
+        chol_ij(n, e, &i, &j);
+        full[q] = i * n + j;
       }
-    A[e] = s;
+    }
+    for (int p = 0; p < d.S; ++p) {
+      cplx v[CHOL_ROUND];
+#pragma unroll
+      for (int q = 0; q < CHOL_ROUND; ++q)
+        v[q] = full[q] >= 0 ? cplx(G[(int64_t)p * nn + full[q]]) : cplx{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < CHOL_ROUND; ++q) {
+        acc[q].re += v[q].re;
+        acc[q].im += v[q].im;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CHOL_ROUND; ++q) {
+      if (full[q] < 0) continue;
+      A[e0 + q * CHOL_THREADS] = acc[q];
+      if (stage) Rs[e0 + q * CHOL_THREADS] = Rg[full[q]];
+    }
   }
   __syncthreads();
-  if (tid == 0) {
-    double tr = 0.0, mx = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double g = A[i * n + i].re;
-      tr += g;
+  if (tid < 64) {
+    // trace and largest diagonal entry, one wave
+    double t = 0.0, mx = 0.0;
+    for (int i = tid; i < n; i += 64) {
+      const double g = A[chol_off(n, i, i)].re;
+      t += g;
       mx = fmax(mx, g);
     }
-    sc[0] = d.shift ? 11.0 * ((double)d.m * n + (double)n * (n + 1)) * 0x1p-53 * tr : 0.0;
-    sc[1] = 1e-24 * mx;
+    t = wave_sum(t);
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (tid == 0) {
+      sc[0] = d.shift ? 11.0 * ((double)d.m * n + (double)n * (n + 1)) * 0x1p-53 * t : 0.0;
+      sc[1] = 1e-24 * mx;
+    }
   }
   __syncthreads();
   const double thr = sc[1];
-  if (tid < n) A[tid * n + tid].re += sc[0];
+  if (tid < n) A[chol_off(n, tid, tid)].re += sc[0];
   __syncthreads();
   for (int j = 0; j < n; ++j) {
-    const double gjj = A[j * n + j].re;
+    const int dj = chol_off(n, j, j);
+    const double gjj = A[dj].re;
     // a NaN pivot is kept (it propagates to the outputs)
     const bool ok = !(gjj <= thr);
     if (tid == 0) {
@@ -1187,61 +1302,87 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol(const CholDesc* __restric
     const int t = n - 1 - j;
     if (ok && t > 0) {
       const double inv = 1.0 / gjj;
+      // trailing triangle row by row: row a (i = j + 1 + a) holds t - a
+      // elements starting at packed offset chol_off(n, i, i)
       for (int e = tid; e < t * t; e += CHOL_THREADS) {
         const int a = e / t, b = e - a * t;
         if (a > b) continue;
-        const int i = j + 1 + a, k = j + 1 + b;
-        const cplx gi = A[j * n + i], gk = A[j * n + k];
-        cplx& x = A[i * n + k];
+        const int i = j + 1 + a;
+        const cplx gi = A[dj + 1 + a], gk = A[dj + 1 + b];
+        cplx& x = A[chol_off(n, i, i) + (b - a)];
         x.re -= (gi.re * gk.re + gi.im * gk.im) * inv;   // conj(g_ji) g_jk / g_jj
         x.im -= (gi.re * gk.im - gi.im * gk.re) * inv;
       }
     }
     __syncthreads();
   }
-  // R_new in place: row j scaled by 1 / r_jj, real diagonal, zero below
-  for (int e = tid; e < nn; e += CHOL_THREADS) {
-    const int i = e / n, k = e - i * n;
-    cplx x = {0.0, 0.0};
-    if (k == i) x.re = rd[i];
-    else if (k > i) x = cplx{A[e].re * ird[i], A[e].im * ird[i]};
-    A[e] = x;
+  // R_new in place: row i scaled by 1 / r_ii, real diagonal
+  for (int e = tid; e < np; e += CHOL_THREADS) {
+    int i, k;
+    chol_ij(n, e, &i, &k);
+    A[e] = k == i ? cplx{rd[i], 0.0} : cplx{A[e].re * ird[i], A[e].im * ird[i]};
   }
   __syncthreads();
-  const gptr<cplx> Rg = to_global(d.R);
-  if (d.accumulate) {
-    // R <- R_new R_prev (both upper triangular), read fully before writing
-    cplx acc[CHOL_PER_THREAD];
+  if (acc_r) {
+    // R <- R_new R_prev (both upper triangular).  R_prev comes from LDS when
+    // staged; otherwise from global memory, and the products go to the R^-1
+    // buffer first (R^-1 is written last) and are copied over R once every
+    // thread has read its terms.
+    const gptr<cplx> Tg = stage ? Rg : to_global(d.Rinv);
+    for (int base = 0; base < np; base += CHOL_THREADS * CHOL_ROUND) {
+      cplx acc[CHOL_ROUND];
+      int full[CHOL_ROUND];
 #pragma unroll
-    for (int q = 0; q < CHOL_PER_THREAD; ++q) {
-      const int e = tid + q * CHOL_THREADS;
-      cplx s = {0.0, 0.0};
-      if (e < nn) {
-        const int i = e / n, k = e - i * n;
-        for (int l = i; l <= k; ++l) {
-          const cplx a = A[i * n + l], b = Rg[(int64_t)l * n + k];
-          s.re += a.re * b.re - a.im * b.im;
-          s.im += a.re * b.im + a.im * b.re;
+      for (int q = 0; q < CHOL_ROUND; ++q) {
+        const int e = base + tid + q * CHOL_THREADS;
+        cplx s = {0.0, 0.0};
+        full[q] = -1;
+        if (e < np) {
+          int i, k;
+          chol_ij(n, e, &i, &k);
+          full[q] = i * n + k;
+          const int row = chol_off(n, i, i) - i;   // A[row + l] = R_new[i][l]
+          for (int l = i; l <= k; ++l) {
+            const cplx a = A[row + l];
+            const cplx b = stage ? Rs[chol_off(n, l, k)] : cplx(Rg[(int64_t)l * n + k]);
+            s.re += a.re * b.re - a.im * b.im;
+            s.im += a.re * b.im + a.im * b.re;
+          }
         }
+        acc[q] = s;
       }
-      acc[q] = s;
-    }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < CHOL_PER_THREAD; ++q) {
-      const int e = tid + q * CHOL_THREADS;
-      if (e < nn) Rg[e] = acc[q];
+      for (int q = 0; q < CHOL_ROUND; ++q)
+        if (full[q] >= 0) Tg[full[q]] = acc[q];
     }
-  } else {
-    for (int e = tid; e < nn; e += CHOL_THREADS) Rg[e] = A[e];
+    if (!stage) {
+      __syncthreads();
+      for (int e = tid; e < np; e += CHOL_THREADS) {
+        int i, k;
+        chol_ij(n, e, &i, &k);
+        Rg[i * n + k] = Tg[i * n + k];
+      }
+    }
+  } else if (want_r) {
+    for (int e = tid; e < np; e += CHOL_THREADS) {
+      int i, k;
+      chol_ij(n, e, &i, &k);
+      Rg[i * n + k] = A[e];
+    }
   }
+  if (want_r)
+    for (int e = tid; e < nn; e += CHOL_THREADS) {
+      const int i = e / n, k = e - i * n;
+      if (k < i) Rg[e] = cplx{0.0, 0.0};
+    }
   // R^-1 in place: X[j][j] = 1 / r_jj, X[i][j] = -(sum_{i <= l < j} X[i][l] R[l][j]) / r_jj
   const int grp = tid >> 4, gl = tid & 15;
   for (int j = 0; j < n; ++j) {
     for (int i = grp; i < j; i += CHOL_THREADS / 16) {
+      const int row = chol_off(n, i, i) - i;
       double sr = 0.0, si = 0.0;
       for (int l = i + gl; l < j; l += 16) {
-        const cplx x = A[i * n + l], r = A[l * n + j];
+        const cplx x = A[row + l], r = A[chol_off(n, l, j)];
         sr += x.re * r.re - x.im * r.im;
         si += x.re * r.im + x.im * r.re;
       }
@@ -1250,12 +1391,276 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol(const CholDesc* __restric
       if (gl == 0) tcol[i] = cplx{-sr * ird[j], -si * ird[j]};
     }
     __syncthreads();
-    if (tid < j) A[tid * n + j] = tcol[tid];
-    else if (tid == j) A[j * n + j] = cplx{ird[j], 0.0};
+    for (int i = tid; i <= j; i += CHOL_THREADS)
+      A[chol_off(n, i, j)] = i < j ? tcol[i] : cplx{ird[j], 0.0};
     __syncthreads();
   }
   const gptr<cplx> Xg = to_global(d.Rinv);
-  for (int e = tid; e < nn; e += CHOL_THREADS) Xg[e] = A[e];
+  for (int e = tid; e < nn; e += CHOL_THREADS) {
+    const int i = e / n, k = e - i * n;
+    Xg[e] = k >= i ? A[chol_off(n, i, k)] : cplx{0.0, 0.0};
+  }
+}
+
+// k_chol_b: the same step for n <= 80 by 16-wide blocks (far fewer barriers
+// than the column-by-column form).  Full storage in LDS (row stride 80).
+//   Cholesky, per diagonal block k: (1) one wave factors the diagonal block
+//   in registers, lane (r mod 4, c) holding rows r of column c, the pivot
+//   row broadcast by lane shuffles; (2) the block row right of it is solved
+//   with the block's conjugate transpose, one lane per column; (3) the
+//   trailing triangle gets the rank-16 update.
+//   R^-1 in place: every diagonal block inverted by one 16-lane group (back
+//   substitution, one lane per column), then block column j from the
+//   inverted leading block: X[0:j, j] = -(X[0:j, 0:j] R[0:j, j]) X[j, j].
+// The previous running factor is staged packed behind the matrix; the same
+// space holds the inverse's block products.
+constexpr int CHB_N = 80, CHB_LD = 80;
+
+__device__ __forceinline__ cplx shfl_c(cplx v, int src) {
+  return cplx{__shfl(v.re, src), __shfl(v.im, src)};
+}
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restrict__ descs) {
+  const CholDesc d = descs[blockIdx.x];
+  const int n = d.n, tid = threadIdx.x, nn = n * n;
+  const int lane = tid & 63, wave = tid >> 6;
+  __shared__ cplx A[CHB_N * CHB_LD];
+  __shared__ cplx W[CHB_N * (CHB_N + 1) / 2];
+  __shared__ double rd[CHB_N], ird[CHB_N];
+  __shared__ double sc[2];
+  if (n > CHB_N) return;   // excluded by the executor
+  const gptr<const cplx> G = to_global(d.G);
+  const bool want_r = d.R != nullptr;
+  const bool acc_r = want_r && d.accumulate;
+  const gptr<cplx> Rg = to_global(d.R);
+  // sum of the partials in order (deterministic), upper triangle; the
+  // previous factor staged packed
+  for (int base = 0; base < nn; base += CHOL_THREADS * CHOL_ROUND) {
+    cplx acc[CHOL_ROUND];
+    bool up[CHOL_ROUND];
+#pragma unroll
+    for (int q = 0; q < CHOL_ROUND; ++q) {
+      const int e = base + tid + q * CHOL_THREADS;
+      up[q] = e < nn && (e / n) <= (e % n);
+      acc[q] = cplx{0.0, 0.0};
+    }
+    for (int p = 0; p < d.S; ++p) {
+      cplx v[CHOL_ROUND];
+#pragma unroll
+      for (int q = 0; q < CHOL_ROUND; ++q)
+        v[q] = up[q] ? cplx(G[(int64_t)p * nn + base + tid + q * CHOL_THREADS]) : cplx{0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < CHOL_ROUND; ++q) {
+        acc[q].re += v[q].re;
+        acc[q].im += v[q].im;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CHOL_ROUND; ++q) {
+      const int e = base + tid + q * CHOL_THREADS;
+      if (e >= nn) continue;
+      const int i = e / n, j = e - i * n;
+      A[i * CHB_LD + j] = acc[q];   // zero below the diagonal
+      if (acc_r && up[q]) W[chol_off(n, i, j)] = Rg[e];
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double t = 0.0, mx = 0.0;
+    for (int i = tid; i < n; i += 64) {
+      const double g = A[i * CHB_LD + i].re;
+      t += g;
+      mx = fmax(mx, g);
+    }
+    t = wave_sum(t);
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+    if (tid == 0) {
+      sc[0] = d.shift ? 11.0 * ((double)d.m * n + (double)n * (n + 1)) * 0x1p-53 * t : 0.0;
+      sc[1] = 1e-24 * mx;
+    }
+  }
+  __syncthreads();
+  const double thr = sc[1];
+  if (tid < n) A[tid * CHB_LD + tid].re += sc[0];
+  __syncthreads();
+  const int nb = (n + 15) / 16;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = 16 * kb, kw = n - k0 < 16 ? n - k0 : 16, c1 = k0 + kw;
+    // (1) diagonal block, one wave
+    if (wave == 0) {
+      const int c = lane & 15, rg = lane >> 4;
+      cplx a[4];
+      double myr[4], myi[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = rg + 4 * t;
+        a[t] = (r <= c && c < kw) ? A[(k0 + r) * CHB_LD + k0 + c] : cplx{0.0, 0.0};
+        myr[t] = 0.0;
+        myi[t] = 0.0;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (j < kw) {
+          const int src = (j & 3) * 16;   // lanes holding row j (register j / 4)
+          const cplx gjj = shfl_c(a[j >> 2], src + j);
+          const bool ok = !(gjj.re <= thr);
+          const double r = ok ? sqrt(gjj.re) : 0.0, ir = ok ? 1.0 / r : 0.0;
+          if (lane == 0) {
+            rd[k0 + j] = r;
+            ird[k0 + j] = ir;
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (rg + 4 * t == j) { myr[t] = r; myi[t] = ir; }
+          const double inv = ok ? 1.0 / gjj.re : 0.0;
+          const cplx gc = shfl_c(a[j >> 2], src + c);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int rr = rg + 4 * t;
+            const cplx gr = shfl_c(a[j >> 2], src + rr);
+            if (ok && rr > j && rr <= c && c < kw) {
+              a[t].re -= (gr.re * gc.re + gr.im * gc.im) * inv;   // conj(g_jr) g_jc / g_jj
+              a[t].im -= (gr.re * gc.im - gr.im * gc.re) * inv;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = rg + 4 * t;
+        if (r <= c && c < kw)
+          A[(k0 + r) * CHB_LD + k0 + c] =
+              r == c ? cplx{myr[t], 0.0} : cplx{a[t].re * myi[t], a[t].im * myi[t]};
+      }
+    }
+    __syncthreads();
+    // (2) block row right of the diagonal block: R_kk^H X = G, one lane per column
+    for (int cc = tid; cc < n - c1; cc += CHOL_THREADS) {
+      const int c = c1 + cc;
+      cplx x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        x[i] = cplx{0.0, 0.0};
+        if (i < kw) {
+          cplx s = A[(k0 + i) * CHB_LD + c];
+#pragma unroll
+          for (int l = 0; l < 16; ++l)
+            if (l < i) {
+              const cplx r = A[(k0 + l) * CHB_LD + k0 + i];   // conj(R[l][i]) x[l]
+              s.re -= r.re * x[l].re + r.im * x[l].im;
+              s.im -= r.re * x[l].im - r.im * x[l].re;
+            }
+          const double ir = ird[k0 + i];
+          x[i] = cplx{s.re * ir, s.im * ir};
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (i < kw) A[(k0 + i) * CHB_LD + c] = x[i];
+    }
+    __syncthreads();
+    // (3) trailing triangle: G[i][c] -= sum_l conj(R[l][i]) R[l][c]
+    const int t = n - c1;
+    for (int e = tid; e < t * t; e += CHOL_THREADS) {
+      const int a = e / t, b = e - a * t;
+      if (a > b) continue;
+      const int i = c1 + a, c = c1 + b;
+      cplx s = A[i * CHB_LD + c];
+      for (int l = 0; l < kw; ++l) {
+        const cplx ri = A[(k0 + l) * CHB_LD + i], rc = A[(k0 + l) * CHB_LD + c];
+        s.re -= ri.re * rc.re + ri.im * rc.im;
+        s.im -= ri.re * rc.im - ri.im * rc.re;
+      }
+      A[i * CHB_LD + c] = s;
+    }
+    __syncthreads();
+  }
+  // running factor R <- R_new R_prev (R_prev staged packed in W)
+  if (want_r) {
+    for (int e = tid; e < nn; e += CHOL_THREADS) {
+      const int i = e / n, k = e - i * n;
+      cplx s = {0.0, 0.0};
+      if (k >= i) {
+        if (acc_r) {
+          for (int l = i; l <= k; ++l) {
+            const cplx a = A[i * CHB_LD + l], b = W[chol_off(n, l, k)];
+            s.re += a.re * b.re - a.im * b.im;
+            s.im += a.re * b.im + a.im * b.re;
+          }
+        } else {
+          s = A[i * CHB_LD + k];
+        }
+      }
+      Rg[e] = s;
+    }
+  }
+  __syncthreads();   // W is reused below
+  // (I1) diagonal blocks inverted in place, a 16-lane group per block
+  {
+    const int grp = tid >> 4, c = tid & 15;
+    if (grp < nb) {
+      const int k0 = 16 * grp, kw = n - k0 < 16 ? n - k0 : 16;
+      cplx x[16];
+#pragma unroll
+      for (int ii = 15; ii >= 0; --ii) {
+        x[ii] = cplx{0.0, 0.0};
+        if (ii < kw && c < kw && ii <= c) {
+          if (ii == c) {
+            x[ii] = cplx{ird[k0 + c], 0.0};
+          } else {
+            cplx s = {0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < 16; ++l)
+              if (l > ii && l <= c) {
+                const cplx r = A[(k0 + ii) * CHB_LD + k0 + l];
+                s.re += r.re * x[l].re - r.im * x[l].im;
+                s.im += r.re * x[l].im + r.im * x[l].re;
+              }
+            const double ir = ird[k0 + ii];
+            x[ii] = cplx{-s.re * ir, -s.im * ir};
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii)
+        if (ii < kw && c < kw && ii <= c) A[(k0 + ii) * CHB_LD + k0 + c] = x[ii];
+    }
+  }
+  __syncthreads();
+  // (I2) block columns: T = X[0:j0, 0:j0] R[0:j0, jb], then X[0:j0, jb] = -T X_jj
+  for (int jb = 1; jb < nb; ++jb) {
+    const int j0 = 16 * jb, jw = n - j0 < 16 ? n - j0 : 16;
+    for (int e = tid; e < j0 * 16; e += CHOL_THREADS) {
+      const int i = e >> 4, c = e & 15;
+      cplx s = {0.0, 0.0};
+      if (c < jw)
+        for (int l = i; l < j0; ++l) {
+          const cplx x = A[i * CHB_LD + l], r = A[l * CHB_LD + j0 + c];
+          s.re += x.re * r.re - x.im * r.im;
+          s.im += x.re * r.im + x.im * r.re;
+        }
+      W[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < j0 * 16; e += CHOL_THREADS) {
+      const int i = e >> 4, c = e & 15;
+      if (c >= jw) continue;
+      cplx s = {0.0, 0.0};
+      for (int l = 0; l <= c; ++l) {
+        const cplx tt = W[i * 16 + l], x = A[(j0 + l) * CHB_LD + j0 + c];
+        s.re += tt.re * x.re - tt.im * x.im;
+        s.im += tt.re * x.im + tt.im * x.re;
+      }
+      A[i * CHB_LD + j0 + c] = cplx{-s.re, -s.im};
+    }
+    __syncthreads();
+  }
+  const gptr<cplx> Xg = to_global(d.Rinv);
+  for (int e = tid; e < nn; e += CHOL_THREADS) {
+    const int i = e / n, k = e - i * n;
+    Xg[e] = k >= i ? A[i * CHB_LD + k] : cplx{0.0, 0.0};
+  }
 }
 
 // ----------------------------------------------------------------- Jacobi
@@ -2516,7 +2921,8 @@ __global__ __launch_bounds__(256) void k_svd_back(const JacobiDesc* __restrict__
 __global__ __launch_bounds__(256) void k_colphase(const ColPhaseDesc* __restrict__ descs) {
   const ColPhaseDesc d = descs[blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = wave; j < d.keep; j += 4) {
+  // four columns per workgroup (one per wave), column groups over blockIdx.y
+  for (int j = blockIdx.y * 4 + wave; j < d.keep; j += 4 * gridDim.y) {
     double best = -1.0;
     int bi = 0;
     for (int i = lane; i < d.m; i += 64) {
@@ -2566,21 +2972,58 @@ __global__ __launch_bounds__(256) void k_omega(const OmegaDesc* __restrict__ des
   }
 }
 
-__global__ __launch_bounds__(256) void k_normalize(const NormDesc* __restrict__ descs) {
-  const NormDesc d = descs[blockIdx.x];
+// C = alpha * sum_s P_s (see SumDesc); grid (element blocks, items)
+__global__ __launch_bounds__(256) void k_sum_parts(const SumDesc* __restrict__ descs) {
+  const SumDesc d = descs[blockIdx.y];
+  const int64_t mn = (int64_t)d.M * d.N;
+  const gptr<const cplx> P = to_global(d.P);
+  const gptr<cplx> C = to_global(d.C);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mn; e += (int64_t)gridDim.x * 256) {
+    double r = 0.0, i = 0.0;
+    for (int s = 0; s < d.S; ++s) {
+      const cplx v = P[s * mn + e];
+      r += v.re;
+      i += v.im;
+    }
+    const int64_t row = e / d.N, col = e - row * d.N;
+    C[row * d.ldc + col] = cplx{d.alpha.re * r - d.alpha.im * i, d.alpha.re * i + d.alpha.im * r};
+  }
+}
+
+// chunk c of an item covers elements [c * step, min(len, (c + 1) * step)),
+// step a multiple of 256 (blockIdx.x: chunk, blockIdx.y: item)
+__device__ __forceinline__ int64_t norm_step(int64_t len) {
+  return ((len + NORM_CHUNKS - 1) / NORM_CHUNKS + 255) / 256 * 256;
+}
+
+__global__ __launch_bounds__(256) void k_norm_partial(const NormDesc* __restrict__ descs) {
+  const NormDesc d = descs[blockIdx.y];
   __shared__ double sh[8];
+  const int64_t step = norm_step(d.len), lo = blockIdx.x * step;
+  const int64_t hi = lo + step < d.len ? lo + step : d.len;
+  const gptr<const cplx> x = to_global((const cplx*)d.x);
   double part = 0.0;
-  for (int64_t e = threadIdx.x; e < d.len; e += 256) {
-    cplx x = d.x[e];
-    part += x.re * x.re + x.im * x.im;
+  for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+    const cplx v = x[e];
+    part += v.re * v.re + v.im * v.im;
   }
-  double nrm = sqrt(block_sum<256>(part, sh));
-  double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int64_t e = threadIdx.x; e < d.len; e += 256) {
-    cplx x = d.x[e];
-    d.x[e] = cplx{x.re * inv, x.im * inv};
+  part = block_sum<256>(part, sh);
+  if (threadIdx.x == 0) d.part[blockIdx.x] = part;
+}
+
+__global__ __launch_bounds__(256) void k_norm_apply(const NormDesc* __restrict__ descs) {
+  const NormDesc d = descs[blockIdx.y];
+  double t = 0.0;
+  for (int c = 0; c < NORM_CHUNKS; ++c) t += d.part[c];   // same order in every chunk
+  const double nrm = sqrt(t), inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  const int64_t step = norm_step(d.len), lo = blockIdx.x * step;
+  const int64_t hi = lo + step < d.len ? lo + step : d.len;
+  const gptr<cplx> x = to_global(d.x);
+  for (int64_t e = lo + threadIdx.x; e < hi; e += 256) {
+    const cplx v = x[e];
+    x[e] = cplx{v.re * inv, v.im * inv};
   }
-  if (threadIdx.x == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (d.logscale && nrm > 0.0) *d.logscale += log10(nrm);
     if (d.norm_out) *d.norm_out = nrm;
   }

@@ -70,14 +70,14 @@ struct QrDesc {
 //   QRK_MID     k_qr_mid, R only, m <= 144, n <= 128 (registers)
 //   QRK_SMALL2  k_qr_small<18, 32>, m <= 288, n <= 32 (registers)
 //   QRK_LDS     k_qr, working copy m (n + k) <= QR_LDS_MAX in LDS
-//   QRK_CHOL    tall blocks with n <= CHOLQR_MAXN <= m: Cholesky QR on several
+//   QRK_CHOL    tall blocks with n <= CHOLQR_MAXN, n <= m: Cholesky QR on several
 //               workgroups (Gram GEMMs, k_chol, Q GEMMs; three passes, the
 //               first shifted), expanded into those ops by the plan compiler
 //   QRK_TALL    k_qr_tall, one workgroup, blocked panels (everything else)
 constexpr int QR_LDS_MAX = 8192;   // complex elements (128 KB)
 constexpr int QRS_MAXM = 144, QRS_MAXN = 16;
 constexpr int QRM_MAXN = 128;
-constexpr int CHOLQR_MAXN = 80;
+constexpr int CHOLQR_MAXN = 128;
 enum QrKernel { QRK_LDS = 0, QRK_TALL = 1, QRK_SMALL = 2, QRK_MID = 3, QRK_SMALL2 = 4, QRK_CHOL = 5 };
 inline int qr_kernel(int64_t m, int64_t n, bool with_q) {
   const int64_t k = m < n ? m : n;
@@ -88,6 +88,15 @@ inline int qr_kernel(int64_t m, int64_t n, bool with_q) {
   if (n <= CHOLQR_MAXN && m >= n) return QRK_CHOL;
   return QRK_TALL;
 }
+
+// Split-K GEMM: C (M x N, ldc) = alpha * sum_s P_s, P_s the S partial
+// products (M x N each, consecutive, row-major), summed in order.
+struct SumDesc {
+  const cplx* P;
+  cplx* C;
+  int S, M, N, ldc;
+  cplx alpha;
+};
 
 // Cholesky step of the tall QR (k_chol, one workgroup per item): the S
 // partial Gram matrices G_s (n x n each, consecutive, row-major; only their
@@ -148,11 +157,16 @@ struct OmegaDesc {
 };
 
 // x /= ||x||_F, logscale += log10 ||x||_F
+// (two launches over NORM_CHUNKS workgroups per item: partial sums of
+// |x|^2 per chunk into part[], then every chunk sums the partials in order
+// and scales its elements; the first chunk updates the log-scale)
+constexpr int NORM_CHUNKS = 64;
 struct NormDesc {
   cplx* x;
   int64_t len;
   double* logscale;
   double* norm_out;   // optional: stores ||x||
+  double* part;       // NORM_CHUNKS doubles of scratch
 };
 
 // Block copy between [l, P, r] tensors: dst[l, p, r] <- sign * src[l - off_l,

