@@ -75,7 +75,11 @@ struct Compiler::Lane {
   Compiler* C;
   int id;
   LaneOps* out;
-  int64_t chain_top = 0, scratch_top = 0, scratch_max = 0;
+  // Every buffer of the lane gets a fresh offset in one virtual space while
+  // the plan is built (so each reference names exactly one buffer); once
+  // the lane's ops are final, pack_lane() places the buffers by liveness.
+  int64_t vtop = 0;
+  std::vector<std::pair<int64_t, int64_t>> vallocs;   // (virtual offset, size)
   int stage = 0, step = 0, phase = 0, counter = 0;
   // launch keys: within a stage the lanes are independent, so each lane's
   // ops are keyed by (stage, SVDs emitted so far in the stage, index since
@@ -87,19 +91,18 @@ struct Compiler::Lane {
   Lane(Compiler* c, int lane, LaneOps* o) : C(c), id(lane), out(o) {}
 
   int rg_chain() const { return RG_LANE0 + 2 * id; }
-  int rg_scratch() const { return RG_LANE0 + 2 * id + 1; }
-  Ref chain_alloc(int64_t n) {
-    Ref r{rg_chain(), chain_top};
-    chain_top += (n + 7) / 8 * 8;
+  Ref valloc(int64_t n) {
+    const int64_t sz = std::max<int64_t>((n + 7) / 8 * 8, 8);
+    Ref r{rg_chain(), vtop};
+    vallocs.push_back({vtop, sz});
+    vtop += sz;
     return r;
   }
-  Ref scratch(int64_t n) {
-    Ref r{rg_scratch(), scratch_top};
-    scratch_top += (n + 7) / 8 * 8;
-    scratch_max = std::max(scratch_max, scratch_top);
-    return r;
-  }
-  void reset_scratch() { scratch_top = 0; }
+  // chain tensors and per-swallow temporaries differ only in lifetime,
+  // which the packing reads from the ops
+  Ref chain_alloc(int64_t n) { return valloc(n); }
+  Ref scratch(int64_t n) { return valloc(n); }
+  void reset_scratch() {}
   void at(int st, int sp, int ph) {
     if (st != stage || sp != step || ph != phase) counter = 0;
     stage = st; step = sp; phase = ph;
@@ -1036,6 +1039,105 @@ void fuse_gemm_perm(LaneOps& L) {
   ops.resize(w);
 }
 
+// Place the lane's buffers (virtual offsets in `region`, allocations
+// `va` in increasing order) by liveness and rewrite every reference;
+// returns the region size.  Time runs over the lane's ops in order, ops of a
+// joined group (same wave key, launched together) sharing one time step; a
+// buffer's memory is reused by a buffer first touched strictly after the
+// last op touching it (best fit from the freed blocks, else the top); the
+// region size is the high-water mark of the placement.
+int64_t pack_lane(LaneOps& L, const std::vector<std::pair<int64_t, int64_t>>& va, int region) {
+  const size_t na = va.size();
+  if (na == 0) return 0;
+  std::vector<int64_t> first(na, -1), last(na, -1);
+  auto find = [&](int64_t off) {
+    size_t lo = 0, hi = na;
+    while (hi - lo > 1) {
+      const size_t mid = (lo + hi) / 2;
+      if (va[mid].first <= off) lo = mid; else hi = mid;
+    }
+    return lo;
+  };
+  std::vector<int64_t> tstep(L.ops.size());
+  int64_t t = -1;
+  for (size_t p = 0; p < L.ops.size(); ++p) {
+    if (p == 0 || L.ops[p].first < L.ops[p - 1].first || L.ops[p - 1].first < L.ops[p].first) ++t;
+    tstep[p] = t;
+    const Op& op = L.ops[p].second;
+    auto touch = [&](const Ref& r) {
+      if (r.region != region) return;
+      const size_t a = find(r.off);
+      if (first[a] < 0) first[a] = t;
+      last[a] = t;
+    };
+    touch(op.a); touch(op.b); touch(op.c); touch(op.d);
+    for (const Ref& r : op.refs) touch(r);
+  }
+  std::vector<size_t> order;
+  for (size_t a = 0; a < na; ++a)
+    if (first[a] >= 0) order.push_back(a);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](size_t x, size_t y) { return first[x] < first[y]; });
+  std::vector<int64_t> real(na, 0);
+  std::map<int64_t, int64_t> freeb;                     // offset -> size
+  std::multimap<int64_t, size_t> active;               // last time -> allocation
+  int64_t top = 0, high = 0;   // current top of the used space, its high-water mark
+  for (size_t a : order) {
+    while (!active.empty() && active.begin()->first < first[a]) {
+      const size_t b = active.begin()->second;
+      active.erase(active.begin());
+      int64_t off = real[b], sz = va[b].second;
+      auto nx = freeb.lower_bound(off);
+      if (nx != freeb.end() && nx->first == off + sz) { sz += nx->second; freeb.erase(nx); }
+      auto pv = freeb.lower_bound(off);
+      if (pv != freeb.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) { off = pv->first; sz += pv->second; freeb.erase(pv); }
+      }
+      if (off + sz == top) top = off;   // a freed block at the top lowers it
+      else freeb[off] = sz;
+    }
+    const int64_t sz = va[a].second;
+    auto best = freeb.end();
+    for (auto it = freeb.begin(); it != freeb.end(); ++it)
+      if (it->second >= sz && (best == freeb.end() || it->second < best->second)) best = it;
+    if (best != freeb.end()) {
+      const int64_t off = best->first, bsz = best->second;
+      freeb.erase(best);
+      if (bsz > sz) freeb[off + sz] = bsz - sz;
+      real[a] = off;
+    } else {
+      real[a] = top;
+      top += sz;
+      high = std::max(high, top);
+    }
+    active.insert({last[a], a});
+  }
+  // self-check: buffers sharing memory never share a time step
+  {
+    std::vector<size_t> byoff(order);
+    std::sort(byoff.begin(), byoff.end(), [&](size_t x, size_t y) { return real[x] < real[y]; });
+    for (size_t i = 0; i < byoff.size(); ++i) {
+      const size_t a = byoff[i];
+      for (size_t j = i + 1; j < byoff.size() && real[byoff[j]] < real[a] + va[a].second; ++j) {
+        const size_t b = byoff[j];
+        if (!(last[a] < first[b] || last[b] < first[a])) return -1;
+      }
+    }
+  }
+  for (auto& pr : L.ops) {
+    Op& op = pr.second;
+    auto moved = [&](Ref& r) {
+      if (r.region != region) return;
+      const size_t a = find(r.off);
+      r.off = real[a] + (r.off - va[a].first);
+    };
+    moved(op.a); moved(op.b); moved(op.c); moved(op.d);
+    for (Ref& r : op.refs) moved(r);
+  }
+  return high;
+}
+
 }  // namespace
 
 bool Compiler::build_sweep(int parity, Plan* out) {
@@ -1141,8 +1243,9 @@ bool Compiler::build_sweep(int parity, Plan* out) {
     }
     if (!L.err.empty()) { error = L.err; return false; }
     fuse_gemm_perm(out->lanes[m]);
-    lane_size[2 * m] = std::max(lane_size[2 * m], L.chain_top);
-    lane_size[2 * m + 1] = std::max(lane_size[2 * m + 1], L.scratch_max);
+    const int64_t sz = pack_lane(out->lanes[m], L.vallocs, L.rg_chain());
+    if (sz < 0) { error = "internal error: overlapping workspace buffers"; return false; }
+    lane_size[2 * m] = std::max(lane_size[2 * m], sz);
   }
   return true;
 }
@@ -1269,8 +1372,9 @@ bool Compiler::build_expect(int parity, const std::vector<std::pair<int, int>>& 
     (*rho_off)[bi] = roff;
     if (!L.err.empty()) { error = L.err; return false; }
     fuse_gemm_perm(out->lanes[bi]);
-    lane_size[2 * bi] = std::max(lane_size[2 * bi], L.chain_top);
-    lane_size[2 * bi + 1] = std::max(lane_size[2 * bi + 1], L.scratch_max);
+    const int64_t sz = pack_lane(out->lanes[bi], L.vallocs, L.rg_chain());
+    if (sz < 0) { error = "internal error: overlapping workspace buffers"; return false; }
+    lane_size[2 * bi] = std::max(lane_size[2 * bi], sz);
   }
   return true;
 }
