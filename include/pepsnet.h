@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define PEPSNET_ABI_VERSION 2
+#define PEPSNET_ABI_VERSION 3
 
 typedef struct pepsnet_s* pepsnet_t;
 
@@ -127,6 +127,7 @@ int32_t pepsnet_set_sites(pepsnet_t h, const double* sites, int64_t sites_len,
  * BBP_EDEVICE. */
 int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
                       double* max_err);
+
 
 /* Local expectation values from the current messages: for every requested
  * bond (i, j) the two-site reduced density matrix rho_ij is contracted from
@@ -250,14 +251,19 @@ int32_t pepsnet_acquire_workspace(pepsnet_t h);
  * tensors (an imaginary-time step: messages are kept, a warm start as in the
  * thesis's ITE algorithm), sweeps to tol or max_sweeps and evaluates the
  * default bonds' <S_i . S_j> and the energy per site.  A worker thread admits
- * queued requests in arrival order whenever an in-flight slot is free and the
- * state's workspace fits in the HBM budget (a request that does not fit lets
- * later ones pass; one request per state at a time), acquires the workspace
- * for the request's duration, and advances every in-flight request on its
- * state's own stream, so requests overlap on the device.  Results are those
- * of running the request alone.  States must not be used by the caller while
- * they have requests in the server; give each state its own stream (desc
- * stream NULL) for overlap.  submit and poll are thread-safe. */
+ * queued requests in arrival order whenever an in-flight slot is free and a
+ * workspace slot fits (a request that does not fit lets later ones pass; one
+ * request per state at a time) and advances every in-flight request on its
+ * state's own stream, so requests overlap on the device.  A state whose
+ * workspace is released borrows a server workspace slot for the request's
+ * duration; the server allocates at most max_inflight slots within
+ * hbm_budget_bytes as its pool grows and keeps them until it is destroyed,
+ * and a state that gets back the slot it held last keeps its resolved launch
+ * descriptors, so steady-state admission and completion allocate and free no
+ * device memory (slots are freed only to fit a larger state).  Results are
+ * those of running the request alone.  States must not be used by the caller
+ * while they have requests in the server; give each state its own stream
+ * (desc stream NULL) for overlap.  submit and poll are thread-safe. */
 typedef struct bbp_server_s* bbp_server_t;
 int32_t bbp_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, bbp_server_t* out);
 /* new_sites: NULL (unchanged) or sites_len doubles as for pepsnet_set_sites. */
@@ -266,15 +272,19 @@ int32_t bbp_server_submit(bbp_server_t s, pepsnet_t state, const double* new_sit
 /* Collect a request: BBP_PENDING if not finished and wait == 0; otherwise the
  * request's code (BBP_OK, BBP_NOT_CONVERGED or an error) with the outputs:
  * energy per site, up to cap bond values (*n_bonds gets the count), sweeps
- * run, last message distance and the submit-to-completion latency in
- * seconds.  A ticket is collected once. */
+ * run, last message distance, the submit-to-completion latency in seconds
+ * and gpu_window_ms[2], the device-side start and end of the request's work
+ * in ms since the server was created (from events on the state's stream; NaN
+ * if the request failed early).  Every output pointer may be NULL.  A ticket
+ * is collected once. */
 int32_t bbp_server_poll(bbp_server_t s, uint64_t ticket, int32_t wait, double* energy_per_site,
                         double* bond_ss, int32_t cap, int32_t* n_bonds, int32_t* sweeps_done,
-                        double* max_err, double* latency_s);
-/* Peak workspace bytes held and peak in-flight requests so far, requests
- * completed and requests still queued. */
+                        double* max_err, double* latency_s, double* gpu_window_ms);
+/* Peak bytes of workspace slots held and peak in-flight requests so far,
+ * requests completed, requests still queued, and the number of workspace
+ * slot allocations made (it stops growing once the pool is warm). */
 int32_t bbp_server_stats(bbp_server_t s, int64_t* peak_bytes, int32_t* peak_inflight,
-                         int64_t* completed, int32_t* queued);
+                         int64_t* completed, int32_t* queued, int64_t* slot_allocations);
 /* Finishes queued and in-flight requests, then stops the worker. */
 void bbp_server_destroy(bbp_server_t s);
 

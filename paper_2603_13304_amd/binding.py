@@ -13,9 +13,10 @@ import numpy as np
 
 BBP_KAGOME_OPEN, BBP_KAGOME_INF_HEX = 1, 2
 BBP_OK, BBP_NOT_CONVERGED, BBP_PENDING = 0, 1, 2
+BBP_EINVAL, BBP_ENOMEM, BBP_EDEVICE = -1, -2, -3
 BBP_FP64, BBP_FP32, BBP_BF16X3 = 0, 1, 2
 BBP_SVD_FULL, BBP_SVD_RAND = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -82,8 +83,8 @@ def load_library():
         "bbp_server_create": (i32, [i64, i32, P(vp)]),
         "bbp_server_submit": (i32, [vp, vp, P(dbl), i64, dbl, i32, P(C.c_uint64)]),
         "bbp_server_poll": (i32, [vp, C.c_uint64, i32, P(dbl), P(dbl), i32, P(i32), P(i32),
-                                  P(dbl), P(dbl)]),
-        "bbp_server_stats": (i32, [vp, P(i64), P(i32), P(i64), P(i32)]),
+                                  P(dbl), P(dbl), P(dbl)]),
+        "bbp_server_stats": (i32, [vp, P(i64), P(i32), P(i64), P(i32), P(i64)]),
         "bbp_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -328,20 +329,25 @@ class Server:
         e, err, lat = C.c_double(0.0), C.c_double(0.0), C.c_double(0.0)
         nb, sw = C.c_int32(0), C.c_int32(0)
         ss = np.zeros(256)
+        win = np.zeros(2)
         rc = self.lib.bbp_server_poll(self.h, C.c_uint64(ticket), int(wait), C.byref(e), _dptr(ss),
-                                      ss.size, C.byref(nb), C.byref(sw), C.byref(err), C.byref(lat))
+                                      ss.size, C.byref(nb), C.byref(sw), C.byref(err), C.byref(lat),
+                                      _dptr(win))
         if rc == BBP_PENDING:
             return None
         self._keep.pop(ticket, None)
         _check(rc)
         return {"rc": rc, "energy": e.value, "ss": ss[:nb.value].copy(), "sweeps": sw.value,
-                "err": err.value, "latency_s": lat.value}
+                "err": err.value, "latency_s": lat.value,
+                "gpu_window_ms": (float(win[0]), float(win[1]))}
 
     def stats(self):
         pb, pi, done, q = C.c_int64(0), C.c_int32(0), C.c_int64(0), C.c_int32(0)
-        _check(self.lib.bbp_server_stats(self.h, C.byref(pb), C.byref(pi), C.byref(done), C.byref(q)))
+        na = C.c_int64(0)
+        _check(self.lib.bbp_server_stats(self.h, C.byref(pb), C.byref(pi), C.byref(done), C.byref(q),
+                                         C.byref(na)))
         return {"peak_bytes": pb.value, "peak_inflight": pi.value, "completed": done.value,
-                "queued": q.value}
+                "queued": q.value, "slot_allocations": na.value}
 
     def close(self):
         if getattr(self, "h", None):

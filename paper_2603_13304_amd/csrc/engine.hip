@@ -15,6 +15,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <atomic>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -25,6 +26,7 @@
 #include "geometry.hpp"
 #include "kernels.hip"
 #include "plan.hpp"
+#include "sweep_count.hpp"
 
 namespace {
 
@@ -86,9 +88,11 @@ struct pepsnet_s {
   cplx* work = nullptr;       // workspace: the lanes' chain and scratch regions
   int64_t work_len = 0;
   int64_t work_epoch = 0;     // bumped whenever the workspace moves
+  const void* desc_work = nullptr;   // workspace address the descriptors were resolved against
   double* scal = nullptr;
   std::vector<int64_t> region_base;
   char* desc_dev = nullptr;
+  size_t desc_cap = 0;
   std::vector<char> desc_host;
   Compiled prep, sweep[2], expect[2];
   // the plans' ops per lane, kept for batches and for re-resolving
@@ -140,12 +144,26 @@ struct SrvReq {
   int phase = 0;               // 0 queued, 1 sweeping, 2 expectation, 3 done (worker only)
   bool ready = false;          // finished and retired (guarded by the server mutex)
   int32_t rc = BBP_OK;
-  bool own_work = false;       // workspace acquired by the server for this request
-  int64_t ws_bytes = 0;
+  bool own_work = false;       // a server slot is bound to the state for this request
   std::vector<double> ss;
   double energy = 0.0;
   std::chrono::steady_clock::time_point t_submit, t_done;
   hipEvent_t ev = nullptr;
+  struct SrvSlot* slot = nullptr;   // server workspace slot bound for the request
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;   // the request's device-side window
+  double window_ms[2] = {NAN, NAN};
+};
+
+// A workspace buffer of the serving loop.  Slots are allocated while the
+// pool grows (at most max_inflight of them within the HBM budget) and then
+// kept: admitting a request binds a free slot to the state, which re-resolves
+// the state's launch descriptors only if they point at another address, so
+// steady-state admission and completion allocate and free nothing.
+struct SrvSlot {
+  cplx* ptr = nullptr;
+  int64_t bytes = 0;
+  bool busy = false;
+  const void* last = nullptr;   // state it was last bound to (compared, never dereferenced)
 };
 
 struct bbp_server_s {
@@ -157,9 +175,12 @@ struct bbp_server_s {
   std::vector<SrvReq*> inflight;
   std::map<uint64_t, SrvReq*> reqs;   // submitted and not yet collected
   uint64_t next_ticket = 1;
-  int64_t in_use = 0, peak_in_use = 0;
+  int64_t in_use = 0, peak_in_use = 0;   // bytes of workspace slots held
   int peak_inflight = 0;
   int64_t completed = 0;
+  std::atomic<int64_t> slot_allocs{0};
+  std::vector<std::unique_ptr<SrvSlot>> slots;   // touched by the worker thread only
+  hipEvent_t ev_ref = nullptr;   // origin of the requests' device windows
   bool stop = false;
   std::thread worker;
 };
@@ -635,13 +656,22 @@ int32_t run_launches(hipStream_t stream, Compiled* c, bool graph) {
       for (const LaunchRec& r : c->launches) {
         hipError_t e = launch(desc_dev, stream, r);
         if (e != hipSuccess) {
-          hipGraph_t g;
-          hipStreamEndCapture(stream, &g);
+          // end the capture (the stream must leave capture mode) and drop
+          // the partial graph it returns
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(stream, &g);
+          if (g) (void)hipGraphDestroy(g);
           return fail(BBP_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
         }
       }
-      PN_HIP(hipStreamEndCapture(stream, &c->graph));
-      PN_HIP(hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+      hipError_t e = hipStreamEndCapture(stream, &c->graph);
+      if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+        c->exec = nullptr;
+        return fail(BBP_EDEVICE, std::string("graph: ") + hipGetErrorString(e));
+      }
     }
     PN_HIP(hipGraphLaunch(c->exec, stream));
     return BBP_OK;
@@ -729,14 +759,8 @@ int32_t enqueue_sweep(pepsnet_s* h, hipEvent_t ev) {
 
 int32_t finish_sweep(pepsnet_s* h, double* err) {
   const int nm = int(h->P.msg_keys.size());
-  double e = 0.0;
-  for (int m = 0; m < nm; ++m) {
-    if (!std::isfinite(h->pinned[1 + m])) return fail(BBP_ENUMERIC, "non-finite message after a sweep");
-    e = std::max(e, h->pinned[1 + m]);
-  }
-  h->parity ^= 1;
-  h->sweeps_total += 1;
-  *err = e;
+  if (!close_sweep(&h->parity, &h->sweeps_total, h->pinned + 1, nm, err))
+    return fail(BBP_ENUMERIC, "non-finite message after a sweep");
   return BBP_OK;
 }
 
@@ -795,15 +819,20 @@ int32_t build_launches(pepsnet_s* h) {
   std::vector<int32_t> sel(std::max(nb, 1));
   for (int b = 0; b < nb; ++b) sel[b] = b;
   const size_t sel_off = push_descs(&h->desc_host, sel);
-  if (h->desc_dev) {
-    PN_HIP(hipStreamSynchronize(h->stream));
-    hipFree(h->desc_dev);
+  // the plans' shapes never change, so the descriptor buffer keeps its size
+  // after the first build; work still queued may read the old descriptors
+  PN_HIP(hipStreamSynchronize(h->stream));
+  if (h->desc_cap < h->desc_host.size()) {
+    if (h->desc_dev) hipFree(h->desc_dev);
     h->desc_dev = nullptr;
+    h->desc_cap = 0;
+    if (hipMalloc(&h->desc_dev, std::max<size_t>(h->desc_host.size(), 256)) != hipSuccess)
+      return fail(BBP_ENOMEM, "descriptor allocation failed");
+    h->desc_cap = std::max<size_t>(h->desc_host.size(), 256);
   }
-  if (hipMalloc(&h->desc_dev, std::max<size_t>(h->desc_host.size(), 256)) != hipSuccess)
-    return fail(BBP_ENOMEM, "descriptor allocation failed");
   PN_HIP(hipMemcpyAsync(h->desc_dev, h->desc_host.data(), h->desc_host.size(),
                         hipMemcpyHostToDevice, h->stream));
+  h->desc_work = h->work;
   for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep})
     c->desc = h->desc_dev;
   for (int par = 0; par < 2; ++par)
@@ -873,19 +902,56 @@ int32_t need_work(pepsnet_s* h) {
   return BBP_OK;
 }
 
+// Lend a server workspace slot to a handle whose own workspace is released.
+// Descriptors already resolved against this address (the state held the
+// same slot last time) are kept with their captured graphs.
+int32_t bind_slot(pepsnet_s* h, SrvSlot* slot) {
+  h->work = slot->ptr;
+  slot->last = h;
+  if (h->desc_work == h->work) return BBP_OK;
+  h->work_epoch += 1;
+  return build_launches(h);
+}
+
+// Take the slot back once the request's work has drained from the stream.
+void unbind_slot(pepsnet_s* h, SrvSlot* slot) {
+  hipStreamSynchronize(h->stream);
+  h->work = nullptr;
+  slot->busy = false;
+}
+
 
 // Start an admitted request: workspace, new sites (messages kept: a warm
 // start), then its first sweep (or the expectation when max_sweeps == 0).
-void srv_start(SrvReq* r) {
+void srv_start(bbp_server_s* S, SrvReq* r) {
   pepsnet_s* h = r->h;
   int32_t rc = BBP_OK;
-  if (!h->work) {
-    rc = pepsnet_acquire_workspace(h);
-    if (rc == BBP_OK) r->own_work = true;
+  if (r->slot) {
+    SrvSlot* slot = r->slot;
+    if (!slot->ptr) {   // the pool grows: the only allocation of the loop
+      if (hipMalloc(&slot->ptr, size_t(slot->bytes)) != hipSuccess) {
+        slot->ptr = nullptr;
+        rc = fail(BBP_ENOMEM, "workspace slot allocation of " + std::to_string(slot->bytes) +
+                                  " bytes failed");
+      } else {
+        S->slot_allocs += 1;
+      }
+    }
+    if (rc == BBP_OK) rc = bind_slot(h, slot);
+    if (rc == BBP_OK) {
+      r->own_work = true;
+    } else {
+      if (h->work == slot->ptr) h->work = nullptr;
+      slot->busy = false;
+    }
   }
-  if (rc == BBP_OK && !r->sites.empty()) rc = upload_sites(h, r->sites.data(), int64_t(r->sites.size()));
-  if (rc == BBP_OK && hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess)
+  if (rc == BBP_OK && (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreate(&r->ev_begin) != hipSuccess ||
+                       hipEventCreate(&r->ev_end) != hipSuccess))
     rc = fail(BBP_EDEVICE, "event creation failed");
+  if (rc == BBP_OK && hipEventRecord(r->ev_begin, h->stream) != hipSuccess)
+    rc = fail(BBP_EDEVICE, "event record failed");
+  if (rc == BBP_OK && !r->sites.empty()) rc = upload_sites(h, r->sites.data(), int64_t(r->sites.size()));
   if (rc == BBP_OK) {
     if (r->max_sweeps > 0) {
       r->phase = 1;
@@ -893,6 +959,7 @@ void srv_start(SrvReq* r) {
     } else {
       r->phase = 2;
       rc = enqueue_expect(h, r->ev);
+      if (rc == BBP_OK) hipEventRecord(r->ev_end, h->stream);
     }
   }
   if (rc != BBP_OK) {
@@ -914,6 +981,7 @@ bool srv_progress(SrvReq* r) {
       if (r->err <= r->tol || r->sweeps >= r->max_sweeps) {
         r->phase = 2;
         rc = enqueue_expect(h, r->ev);
+        if (rc == BBP_OK) hipEventRecord(r->ev_end, h->stream);
       } else {
         rc = enqueue_sweep(h, r->ev);
       }
@@ -930,7 +998,47 @@ bool srv_progress(SrvReq* r) {
   return true;
 }
 
+// A free slot for a state whose workspace is released (server mutex held):
+// the slot it held last if free, else the smallest free one that fits, else
+// a new one while the pool is below max_inflight slots and within the
+// budget; as a last resort free slots are given up (queued in *evict, freed
+// after the mutex is dropped) until a new one fits.  nullptr: wait.
+SrvSlot* srv_pick_slot(bbp_server_s* S, const pepsnet_s* h, std::vector<cplx*>* evict) {
+  const int64_t need = h->work_len * int64_t(sizeof(cplx));
+  SrvSlot* best = nullptr;
+  for (auto& sp : S->slots) {
+    SrvSlot* sl = sp.get();
+    if (sl->busy || sl->bytes < need) continue;
+    if (sl->last == h && sl->ptr && sl->ptr == h->desc_work) {
+      best = sl;
+      break;
+    }
+    if (!best || sl->bytes < best->bytes) best = sl;
+  }
+  if (!best) {
+    auto room = [&] {
+      return int(S->slots.size()) < S->max_inflight && S->in_use + need <= S->budget;
+    };
+    while (!room()) {   // give up the smallest free slot, if any
+      auto victim = S->slots.end();
+      for (auto it = S->slots.begin(); it != S->slots.end(); ++it)
+        if (!(*it)->busy && (victim == S->slots.end() || (*it)->bytes < (*victim)->bytes)) victim = it;
+      if (victim == S->slots.end()) return nullptr;
+      if ((*victim)->ptr) evict->push_back((*victim)->ptr);
+      S->in_use -= (*victim)->bytes;
+      S->slots.erase(victim);
+    }
+    S->slots.push_back(std::unique_ptr<SrvSlot>(new SrvSlot()));
+    best = S->slots.back().get();
+    best->bytes = need;   // allocated by srv_start, outside the mutex
+    S->in_use += need;
+  }
+  best->busy = true;
+  return best;
+}
+
 void srv_loop(bbp_server_s* S) {
+  std::vector<cplx*> evict;
   for (;;) {
     std::vector<SrvReq*> admitted;
     {
@@ -945,10 +1053,12 @@ void srv_loop(bbp_server_s* S) {
         SrvReq* r = *it;
         bool busy = false;
         for (SrvReq* o : S->inflight) busy = busy || o->h == r->h;
-        const int64_t need = r->h->work ? 0 : r->h->work_len * int64_t(sizeof(cplx));
-        if (!busy && S->in_use + need <= S->budget) {
-          r->ws_bytes = need;
-          S->in_use += need;
+        bool ok = !busy;
+        if (ok && !r->h->work) {
+          r->slot = srv_pick_slot(S, r->h, &evict);
+          ok = r->slot != nullptr;
+        }
+        if (ok) {
           S->inflight.push_back(r);
           admitted.push_back(r);
           it = S->queue.erase(it);
@@ -959,7 +1069,10 @@ void srv_loop(bbp_server_s* S) {
       S->peak_in_use = std::max(S->peak_in_use, S->in_use);
       S->peak_inflight = std::max(S->peak_inflight, int(S->inflight.size()));
     }
-    for (SrvReq* r : admitted) srv_start(r);
+    // slots given up to make room for a larger one (mixed state sizes only)
+    for (cplx* p : evict) hipFree(p);
+    evict.clear();
+    for (SrvReq* r : admitted) srv_start(S, r);
     bool progressed = !admitted.empty();
     std::vector<SrvReq*> snapshot;
     {
@@ -972,16 +1085,25 @@ void srv_loop(bbp_server_s* S) {
       if (r->phase == 3) done.push_back(r);
     for (SrvReq* r : done) {
       if (r->h->stream) hipStreamSynchronize(r->h->stream);
-      if (r->own_work) pepsnet_release_workspace(r->h);
-      if (r->ev) hipEventDestroy(r->ev);
-      r->ev = nullptr;
+      if (r->ev_begin && r->ev_end && hipEventQuery(r->ev_end) == hipSuccess) {
+        float a = 0.0f, b = 0.0f;
+        if (hipEventElapsedTime(&a, S->ev_ref, r->ev_begin) == hipSuccess &&
+            hipEventElapsedTime(&b, S->ev_ref, r->ev_end) == hipSuccess) {
+          r->window_ms[0] = a;
+          r->window_ms[1] = b;
+        }
+      }
+      if (r->own_work) unbind_slot(r->h, r->slot);
+      for (hipEvent_t* e : {&r->ev, &r->ev_begin, &r->ev_end}) {
+        if (*e) hipEventDestroy(*e);
+        *e = nullptr;
+      }
       r->sites.clear();
       r->t_done = std::chrono::steady_clock::now();
     }
     if (!done.empty()) {
       std::lock_guard<std::mutex> lk(S->mu);
       for (SrvReq* r : done) {
-        S->in_use -= r->ws_bytes;
         S->inflight.erase(std::find(S->inflight.begin(), S->inflight.end(), r));
         S->completed += 1;
         r->ready = true;
@@ -990,6 +1112,41 @@ void srv_loop(bbp_server_s* S) {
     }
     if (!progressed && done.empty()) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
+}
+
+// Sweeps with plans[parity] until the largest message distance is <= tol
+// or max_sweeps ran (graph: replay captured graphs when the handle allows).
+int32_t sweep_until(pepsnet_s* h, Compiled* plans, bool graph, int32_t max_sweeps, double tol,
+                    int32_t* sweeps_done, double* max_err) {
+  const int nm = int(h->P.msg_keys.size());
+  double err = INFINITY;
+  int s = 0;
+  for (; s < max_sweeps;) {
+    h->pinned[0] = double(h->sweeps_total);
+    PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
+    PN_HIP(hipEventRecord(h->ev0, h->stream));
+    int32_t rc = run_compiled(h, &plans[h->parity], graph);
+    if (rc) return rc;
+    PN_HIP(hipEventRecord(h->ev1, h->stream));
+    PN_HIP(hipMemcpyAsync(h->pinned + 1, h->scal + h->comp->err_slot(0), nm * sizeof(double),
+                          hipMemcpyDeviceToHost, h->stream));
+    PN_HIP(hipStreamSynchronize(h->stream));
+    float ms = 0.0f;
+    PN_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
+    h->timed_ms += ms;
+    h->timed_sweeps += 1;
+    ++s;
+    if (!close_sweep(&h->parity, &h->sweeps_total, h->pinned + 1, nm, &err)) {
+      if (sweeps_done) *sweeps_done = s;
+      if (max_err) *max_err = err;
+      return fail(BBP_ENUMERIC, "non-finite message after a sweep");
+    }
+    if (err <= tol) break;
+  }
+  if (sweeps_done) *sweeps_done = s;
+  if (max_err) *max_err = err;
+  return err <= tol ? BBP_OK : BBP_NOT_CONVERGED;
 }
 
 }  // namespace
@@ -1133,42 +1290,7 @@ int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* swee
                       double* max_err) {
   if (!h || max_sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
   if (int32_t rc = need_work(h)) return rc;
-  const int nm = int(h->P.msg_keys.size());
-  std::vector<double> errs(nm);
-  double err = INFINITY;
-  int s = 0;
-  for (; s < max_sweeps;) {
-    h->pinned[0] = double(h->sweeps_total);
-    PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
-                          hipMemcpyHostToDevice, h->stream));
-    PN_HIP(hipEventRecord(h->ev0, h->stream));
-    int32_t rc = run_compiled(h, &h->sweep[h->parity], true);
-    if (rc) return rc;
-    PN_HIP(hipEventRecord(h->ev1, h->stream));
-    PN_HIP(hipMemcpyAsync(h->pinned + 1, h->scal + h->comp->err_slot(0), nm * sizeof(double),
-                          hipMemcpyDeviceToHost, h->stream));
-    PN_HIP(hipStreamSynchronize(h->stream));
-    for (int m = 0; m < nm; ++m) errs[m] = h->pinned[1 + m];
-    float ms = 0.0f;
-    PN_HIP(hipEventElapsedTime(&ms, h->ev0, h->ev1));
-    h->timed_ms += ms;
-    h->timed_sweeps += 1;
-    h->parity ^= 1;
-    h->sweeps_total += 1;
-    ++s;
-    err = 0.0;
-    for (double x : errs) {
-      if (!std::isfinite(x)) {
-        if (sweeps_done) *sweeps_done = s;
-        return fail(BBP_ENUMERIC, "non-finite message after a sweep");
-      }
-      err = std::max(err, x);
-    }
-    if (err <= tol) break;
-  }
-  if (sweeps_done) *sweeps_done = s;
-  if (max_err) *max_err = err;
-  return err <= tol ? BBP_OK : BBP_NOT_CONVERGED;
+  return sweep_until(h, h->sweep, true, max_sweeps, tol, sweeps_done, max_err);
 }
 
 int32_t blockbp_expect(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids, int32_t n_ops,
@@ -1561,17 +1683,19 @@ int32_t blockbp_sweep_batch(pepsnet_batch_t b, int32_t sweeps, double* max_err, 
     float e_ms = 0.0f;
     PN_HIP(hipEventElapsedTime(&e_ms, b->ev0, b->ev1));
     total_ms += e_ms;
+    // every handle was swept: advance all of them, then report
+    bool finite = true;
     for (int i = 0; i < n; ++i) {
       pepsnet_s* h = b->hs[i];
       const int nm = int(h->P.msg_keys.size());
-      double e = 0.0;
-      for (int m = 0; m < nm; ++m) {
-        if (!std::isfinite(h->pinned[1 + m])) return fail(BBP_ENUMERIC, "non-finite message after a sweep");
-        e = std::max(e, h->pinned[1 + m]);
-      }
-      errs[i] = e;
-      h->parity ^= 1;
-      h->sweeps_total += 1;
+      finite = close_sweep(&h->parity, &h->sweeps_total, h->pinned + 1, nm, &errs[i]) && finite;
+    }
+    if (!finite) {
+      b->last_ms = total_ms;
+      if (max_err)
+        for (int i = 0; i < n; ++i) max_err[i] = errs[i];
+      if (ms) *ms = total_ms;
+      return fail(BBP_ENUMERIC, "non-finite message after a sweep");
     }
   }
   b->last_ms = total_ms;
@@ -1608,6 +1732,12 @@ int32_t bbp_server_create(int64_t hbm_budget_bytes, int32_t max_inflight, bbp_se
   bbp_server_s* S = new bbp_server_s();
   S->budget = hbm_budget_bytes;
   S->max_inflight = max_inflight;
+  if (hipEventCreate(&S->ev_ref) != hipSuccess || hipEventRecord(S->ev_ref, nullptr) != hipSuccess ||
+      hipEventSynchronize(S->ev_ref) != hipSuccess) {
+    if (S->ev_ref) hipEventDestroy(S->ev_ref);
+    delete S;
+    return fail(BBP_EDEVICE, "server clock event failed");
+  }
   S->worker = std::thread(srv_loop, S);
   *out = S;
   return BBP_OK;
@@ -1643,7 +1773,7 @@ int32_t bbp_server_submit(bbp_server_t S, pepsnet_t state, const double* new_sit
 
 int32_t bbp_server_poll(bbp_server_t S, uint64_t ticket, int32_t wait, double* energy_per_site,
                         double* bond_ss, int32_t cap, int32_t* n_bonds, int32_t* sweeps_done,
-                        double* max_err, double* latency_s) {
+                        double* max_err, double* latency_s, double* gpu_window_ms) {
   if (!S) return fail(BBP_EINVAL, "null server");
   SrvReq* r = nullptr;
   {
@@ -1668,14 +1798,19 @@ int32_t bbp_server_poll(bbp_server_t S, uint64_t ticket, int32_t wait, double* e
   if (max_err) *max_err = r->err;
   if (latency_s)
     *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+  if (gpu_window_ms) {
+    gpu_window_ms[0] = r->window_ms[0];
+    gpu_window_ms[1] = r->window_ms[1];
+  }
   if (r->rc < 0) return fail(r->rc, "request failed");
   return r->rc;
 }
 
 int32_t bbp_server_stats(bbp_server_t S, int64_t* peak_bytes, int32_t* peak_inflight,
-                         int64_t* completed, int32_t* queued) {
+                         int64_t* completed, int32_t* queued, int64_t* slot_allocations) {
   if (!S) return fail(BBP_EINVAL, "null server");
   std::lock_guard<std::mutex> lk(S->mu);
+  if (slot_allocations) *slot_allocations = S->slot_allocs.load();
   if (peak_bytes) *peak_bytes = S->peak_in_use;
   if (peak_inflight) *peak_inflight = S->peak_inflight;
   if (completed) *completed = S->completed;
@@ -1692,6 +1827,9 @@ void bbp_server_destroy(bbp_server_t S) {
   S->cv_work.notify_all();
   if (S->worker.joinable()) S->worker.join();
   for (auto& kv : S->reqs) delete kv.second;
+  for (auto& sl : S->slots)
+    if (sl->ptr) hipFree(sl->ptr);
+  if (S->ev_ref) hipEventDestroy(S->ev_ref);
   delete S;
 }
 

@@ -110,3 +110,30 @@ def test_server_poll_pending_then_done():
     assert first is None or first["sweeps"] == 8
     assert nets[1].memory()[1] > 0
     nets[1].blockbp_sweep(1, 0.0)           # the state's own workspace was kept
+
+
+def test_server_slots_reused_and_requests_overlap():
+    """Workspace slots are allocated while the pool grows and then reused: a
+    second round of requests on the same states allocates nothing (each
+    state gets back the slot it held, with its resolved descriptors), and
+    the device-side windows of requests in flight together intersect."""
+    nets, _ = _states(release=True)
+    srv = pn.Server(1 << 40, 4)
+    warm = [srv.poll(t) for t in [srv.submit(g, None, tol=0.0, max_sweeps=3) for g in nets]]
+    n_alloc = srv.stats()["slot_allocations"]
+    res = [srv.poll(t) for t in [srv.submit(g, None, tol=0.0, max_sweeps=3) for g in nets]]
+    st = srv.stats()
+    srv.close()
+    print("stats", st, "windows", [r["gpu_window_ms"] for r in res], flush=True)
+    assert 1 <= n_alloc <= len(nets)
+    assert st["slot_allocations"] == n_alloc
+    assert all(r["sweeps"] == 3 for r in warm + res)
+    wins = [r["gpu_window_ms"] for r in res]
+    assert all(np.isfinite(w).all() and w[1] > w[0] for w in wins)
+    pairs = [(i, j) for i in range(len(wins)) for j in range(i + 1, len(wins))
+             if max(wins[i][0], wins[j][0]) < min(wins[i][1], wins[j][1])]
+    assert pairs, wins
+    for g in nets:                            # states left with their workspace released
+        assert g.memory()[1] > 0
+        with pytest.raises(pn.PepsnetError):
+            g.blockbp_sweep(1, 0.0)
