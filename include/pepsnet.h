@@ -128,6 +128,21 @@ int32_t pepsnet_set_sites(pepsnet_t h, const double* sites, int64_t sites_len,
 int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
                       double* max_err);
 
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc): blockbp_sweep without any allocation.
+ * The sweep's workspace and launch descriptors live in a fixed device array
+ * of the library, PEPSNET_NOALLOC_MAX_BYTES (128 MiB) on each device it runs
+ * on, held until the process ends, instead of in the handle's workspace
+ * (which may be released).  Arguments, results and messages as for
+ * blockbp_sweep; launches are direct (no graph).  BBP_ENOMEM if the handle's
+ * workspace (pepsnet_memory) plus its descriptors exceed the array;
+ * BBP_EDEVICE if the array's address could not be resolved when the handle
+ * was created.  Every call on a device shares that device's array and
+ * rewrites it (descriptors uploaded, workspace cleared) on entry: calls that
+ * overlap in time on one device race, from any stream or thread. */
+#define PEPSNET_NOALLOC_MAX_BYTES (128LL << 20)
+int32_t blockbp_sweep_noalloc(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
+                              double* max_err);
 
 /* Local expectation values from the current messages: for every requested
  * bond (i, j) the two-site reduced density matrix rho_ij is contracted from

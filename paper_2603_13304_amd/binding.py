@@ -14,6 +14,7 @@ import numpy as np
 BBP_KAGOME_OPEN, BBP_KAGOME_INF_HEX = 1, 2
 BBP_OK, BBP_NOT_CONVERGED, BBP_PENDING = 0, 1, 2
 BBP_EINVAL, BBP_ENOMEM, BBP_EDEVICE = -1, -2, -3
+NOALLOC_MAX_BYTES = 128 << 20   # PEPSNET_NOALLOC_MAX_BYTES
 BBP_FP64, BBP_FP32, BBP_BF16X3 = 0, 1, 2
 BBP_SVD_FULL, BBP_SVD_RAND = 0, 1
 ABI_VERSION = 3
@@ -57,6 +58,7 @@ def load_library():
         "pepsnet_create": (i32, [P(Desc), P(dbl), i64, P(vp)]),
         "pepsnet_set_sites": (i32, [vp, P(dbl), i64, i32]),
         "blockbp_sweep": (i32, [vp, i32, dbl, P(i32), P(dbl)]),
+        "blockbp_sweep_noalloc": (i32, [vp, i32, dbl, P(i32), P(dbl)]),
         "blockbp_expect": (i32, [vp, i32, P(i32), i32, P(dbl), P(dbl), P(dbl), P(dbl), P(i32)]),
         "pepsnet_bonds": (i32, [vp, P(i32), i32, P(i32)]),
         "pepsnet_get_messages": (i32, [vp, P(dbl), i64, P(i64)]),
@@ -163,6 +165,14 @@ class PepsNet:
     def blockbp_sweep(self, max_sweeps, tol=0.0):
         done, err = C.c_int32(0), C.c_double(0.0)
         rc = _check(self.lib.blockbp_sweep(self.h, max_sweeps, tol, C.byref(done), C.byref(err)))
+        return done.value, err.value, rc
+
+    def blockbp_sweep_noalloc(self, max_sweeps, tol=0.0):
+        """blockbp_sweep through the library's fixed device workspace (no
+        allocation; the handle's own workspace may be released)."""
+        done, err = C.c_int32(0), C.c_double(0.0)
+        rc = _check(self.lib.blockbp_sweep_noalloc(self.h, max_sweeps, tol, C.byref(done),
+                                                   C.byref(err)))
         return done.value, err.value, rc
 
     def blockbp_expect(self, bond_ids=None, ops=None):

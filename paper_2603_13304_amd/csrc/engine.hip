@@ -128,8 +128,48 @@ struct pepsnet_s {
     int64_t epoch = -1;
   };
   std::map<std::vector<int>, Subset> subsets;
+  // blockbp_sweep_noalloc: the sweep plans resolved against the device's
+  // fixed workspace (compiled on its first call) and their descriptors
+  int device = 0;
+  Compiled sweep_fixed[2];
+  char* blob_fixed = nullptr;   // pinned host copy of their descriptors
+  size_t blob_fixed_len = 0;
+  size_t fixed_need = 0;        // bytes of the array the sweep would use
+  bool fixed_ready = false;
 };
 constexpr int kMaxOps = 64;
+
+// ---- fixed workspace of blockbp_sweep_noalloc: a device array of the code
+// object, so that a sweep through it allocates nothing.  It holds one
+// sweep's workspace followed by that sweep's launch descriptors.  Each
+// device has its own copy at its own address, looked up with
+// hipGetSymbolAddress while the device is current: in host code the array's
+// name is not a device address and is never passed to a kernel.
+constexpr size_t kFixedBytes = size_t(PEPSNET_NOALLOC_MAX_BYTES);
+static __device__ __align__(256) char scratch[kFixedBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+char* g_fixed_ptr[kMaxDevices] = {};
+
+// Once per device, with that device current (called by pepsnet_create).
+int32_t resolve_fixed(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(BBP_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (g_fixed_ptr[dev]) return BBP_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(BBP_EDEVICE, std::string("fixed workspace address: ") + hipGetErrorString(e));
+  g_fixed_ptr[dev] = static_cast<char*>(p);
+  return BBP_OK;
+}
+
+__global__ void k_fill_zero(uint4* p, int64_t n) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = z;
+}
 
 
 // ---- serving loop
@@ -1114,6 +1154,37 @@ void srv_loop(bbp_server_s* S) {
   }
 }
 
+// At create: when the workspace and the descriptors fit in the device's
+// fixed array, resolve the sweep plans against it (host-side compilation)
+// and keep a pinned copy of their descriptors for blockbp_sweep_noalloc.
+int32_t prepare_fixed(pepsnet_s* h) {
+  h->fixed_need = 0;
+  if (h->device < 0 || h->device >= kMaxDevices || !g_fixed_ptr[h->device]) return BBP_OK;
+  char* base = g_fixed_ptr[h->device];
+  const size_t ws_bytes = (size_t(h->work_len) * sizeof(cplx) + 255) / 256 * 256;
+  h->fixed_need = ws_bytes;
+  if (ws_bytes > kFixedBytes) return BBP_OK;
+  std::vector<char> blob;
+  cplx* own = h->work;
+  h->work = reinterpret_cast<cplx*>(base);
+  for (int par = 0; par < 2; ++par) {
+    h->sweep_fixed[par] = Compiled();
+    compile_ops({{h, &h->sweep_lanes[par]}}, &blob, &h->sweep_fixed[par]);
+    h->sweep_fixed[par].desc = base + ws_bytes;
+  }
+  h->work = own;
+  h->fixed_need = ws_bytes + blob.size();
+  if (h->fixed_need > kFixedBytes) return BBP_OK;
+  if (hipHostMalloc(&h->blob_fixed, std::max<size_t>(blob.size(), 1), 0) != hipSuccess) {
+    h->blob_fixed = nullptr;
+    return fail(BBP_ENOMEM, "pinned descriptor buffer");
+  }
+  std::memcpy(h->blob_fixed, blob.data(), blob.size());
+  h->blob_fixed_len = blob.size();
+  h->fixed_ready = true;
+  return BBP_OK;
+}
+
 // Sweeps with plans[parity] until the largest message distance is <= tol
 // or max_sweeps ran (graph: replay captured graphs when the handle allows).
 int32_t sweep_until(pepsnet_s* h, Compiled* plans, bool graph, int32_t max_sweeps, double tol,
@@ -1220,6 +1291,9 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
     PN_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
     h->own_stream = true;
   }
+  PN_HIP(hipGetDevice(&h->device));
+  // the no-allocation sweep reports a failure here when it is called
+  if (resolve_fixed(h->device) != BBP_OK) g_last_error.clear();
   if (hipMalloc(&h->arena, size_t(tot) * sizeof(cplx)) != hipSuccess)
     return fail(BBP_ENOMEM, "device allocation of " + std::to_string(tot * 16) + " bytes failed");
   if (hipMalloc(&h->work, size_t(h->work_len) * sizeof(cplx)) != hipSuccess)
@@ -1256,6 +1330,8 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
         return fail(BBP_EGEOM, "expectation carries two open sites");
   rc = build_launches(h.get());
   if (rc) return rc;
+  rc = prepare_fixed(h.get());
+  if (rc) return rc;
   if (hipHostMalloc(&h->pinned, size_t(C.msg.off.size() + h->bonds.size() + 8) * sizeof(double),
                     0) != hipSuccess)
     return fail(BBP_ENOMEM, "pinned host buffer");
@@ -1291,6 +1367,28 @@ int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* swee
   if (!h || max_sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
   if (int32_t rc = need_work(h)) return rc;
   return sweep_until(h, h->sweep, true, max_sweeps, tol, sweeps_done, max_err);
+}
+
+int32_t blockbp_sweep_noalloc(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
+                              double* max_err) {
+  if (!h || max_sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
+  if (h->device < 0 || h->device >= kMaxDevices || !g_fixed_ptr[h->device])
+    return fail(BBP_EDEVICE, "the fixed workspace is not available on this device");
+  if (!h->fixed_ready)
+    return fail(BBP_ENOMEM, "the sweep needs " + std::to_string(h->fixed_need) +
+                                " bytes of workspace and descriptors; the fixed workspace holds " +
+                                std::to_string(kFixedBytes));
+  char* base = g_fixed_ptr[h->device];
+  const size_t ws_bytes = (size_t(h->work_len) * sizeof(cplx) + 255) / 256 * 256;
+  // the array keeps whatever the last call on this device left: put this
+  // handle's descriptors back and clear its workspace part
+  PN_HIP(hipMemcpyAsync(base + ws_bytes, h->blob_fixed, h->blob_fixed_len, hipMemcpyHostToDevice,
+                        h->stream));
+  const int64_t n16 = int64_t(ws_bytes / sizeof(uint4));
+  hipLaunchKernelGGL(k_fill_zero, dim3(unsigned(std::min<int64_t>((n16 + 255) / 256, 4096))),
+                     dim3(256), 0, h->stream, reinterpret_cast<uint4*>(base), n16);
+  PN_HIP(hipGetLastError());
+  return sweep_until(h, h->sweep_fixed, false, max_sweeps, tol, sweeps_done, max_err);
 }
 
 int32_t blockbp_expect(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids, int32_t n_ops,
@@ -1850,6 +1948,7 @@ void pepsnet_destroy(pepsnet_t h) {
   if (h->ops_dev) hipFree(h->ops_dev);
   if (h->ops_out) hipFree(h->ops_out);
   if (h->pinned) hipHostFree(h->pinned);
+  if (h->blob_fixed) hipHostFree(h->blob_fixed);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
   if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
