@@ -204,6 +204,19 @@ def test_scale_invariance():
 
 
 # ----------------------------------------------------- P10: message invariants
+def _dense_to_mps(M):
+    """Exact MPS (sites [l, P, r], boundary bonds 1) of a dense message by
+    successive QR factorisations, with no truncation."""
+    legs = M.shape
+    sites, X, l = [], M.reshape(1, -1), 1
+    for P in legs[:-1]:
+        Q, X = np.linalg.qr(X.reshape(l * P, -1))
+        sites.append(Q.reshape(l, P, Q.shape[1]))
+        l = Q.shape[1]
+    sites.append(X.reshape(l, legs[-1], 1))
+    return sites
+
+
 def test_exact_messages_are_hermitian_psd_unit_norm():
     """Exact-mode messages are unit-norm Hermitian positive semi-definite
     operators (ket legs rows, bra legs columns), as the PSD start of
@@ -211,7 +224,12 @@ def test_exact_messages_are_hermitian_psd_unit_norm():
     H = geo.HexProblem(2)
     ts = syn.random_unit_cell(2, seed=12)
     Bd = DenseBlockBP(H, ts)
-    for _ in range(3):
+    Bb = BlockBP(H, ts, chi=16, chi_env=0)
+    Bd.sweep()
+    Bb.sweep()
+    for k, A in Bb.msgs.items():
+        assert np.linalg.norm(bb.mps_dense(A) - Bd.msgs[k]) < 1e-12
+    for _ in range(2):
         Bd.sweep()
     for M in Bd.msgs.values():
         X = message_operator(M, 2)
@@ -219,25 +237,24 @@ def test_exact_messages_are_hermitian_psd_unit_norm():
         assert np.linalg.norm(X - X.conj().T) < 1e-13
         ev = np.linalg.eigvalsh(0.5 * (X + X.conj().T))
         assert ev.min() >= -1e-12 * ev.max()
-    Bb = BlockBP(H, ts, chi=16, chi_env=0)
-    for _ in range(3):
-        Bb.sweep()
-    for k, A in Bb.msgs.items():
-        assert np.linalg.norm(bb.mps_dense(A) - Bd.msgs[k]) < 1e-12
 
 
 def test_fixed_point_residual():
-    """P2: at a converged boundary-chain fixed point the exact dense update
-    map leaves the messages unchanged to the convergence tolerance."""
+    """P2: the exact dense update and the exact boundary-chain update share
+    their fixed point: at the dense map's converged messages, written as
+    exact MPS, one chain sweep leaves every message unchanged."""
     H = geo.HexProblem(2)
     ts = syn.simple_update_cell(2, seed=2, steps=5)
-    Bb = BlockBP(H, ts, chi=16, chi_env=0)
-    sweeps, err = Bb.run(tol=1e-11, max_sweeps=40)
-    assert err <= 1e-11
     Bd = DenseBlockBP(H, ts)
-    Bd.msgs = {k: bb.mps_dense(A) for k, A in Bb.msgs.items()}
-    new = {H.store_key(k): Bd.update(k) for k in H.msg_keys}
-    assert max(np.linalg.norm(new[k] - Bd.msgs[k]) for k in new) < 1e-10
+    err = np.inf
+    for _ in range(60):
+        err = Bd.sweep()
+        if err < 1e-12:
+            break
+    assert err < 1e-12
+    Bb = BlockBP(H, ts, chi=16, chi_env=0)
+    Bb.msgs = {k: _dense_to_mps(Bd.msgs[k]) for k in Bb.msgs}
+    assert Bb.sweep() < 1e-10
 
 
 # ----------------------------------------------------- P11: truncation semantics
