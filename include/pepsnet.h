@@ -261,6 +261,20 @@ int32_t pepsnet_memory(pepsnet_t h, int64_t* resident_bytes, int64_t* workspace_
 int32_t pepsnet_release_workspace(pepsnet_t h);
 int32_t pepsnet_acquire_workspace(pepsnet_t h);
 
+/* GEMM tile autotuner.  Times every tile shape of k_gemm (64x64, 16x64,
+ * 64x16, 64x80, 80x64) on one launch of each distinct GEMM shape (precision,
+ * M, N, K, operand ops, scattered store) of the handle's sweep plans, with
+ * the outputs redirected to a temporary buffer so the handle's state is not
+ * touched, keeps the fastest per shape and recompiles the plans with it
+ * (batches made afterwards use it too).  Results are bit-identical to the
+ * untuned plans: the tile shape never changes the order of any element's
+ * sum.  cache_path (NULL: none) is a text file of earlier choices, one line
+ * per shape; shapes found there are not timed, and the file is rewritten
+ * with the union.  *n_timed / *n_shapes (may be NULL) get the shapes timed
+ * now and the shapes tuned in all.  Needs the workspace (BBP_EINVAL when
+ * released); allocates a temporary output buffer for the timing. */
+int32_t pepsnet_autotune(pepsnet_t h, const char* cache_path, int32_t* n_timed, int32_t* n_shapes);
+
 /* ---- serving loop (continuous batching of expectation requests on
  * resident states).  A request on a state optionally replaces its site
  * tensors (an imaginary-time step: messages are kept, a warm start as in the

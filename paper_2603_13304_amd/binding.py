@@ -80,6 +80,7 @@ def load_library():
         "pepsnet_batch_stats": (i32, [vp, P(dbl), P(i64)]),
         "pepsnet_batch_destroy": (None, [vp]),
         "pepsnet_memory": (i32, [vp, P(i64), P(i64)]),
+        "pepsnet_autotune": (i32, [vp, C.c_char_p, P(i32), P(i32)]),
         "pepsnet_release_workspace": (i32, [vp]),
         "pepsnet_acquire_workspace": (i32, [vp]),
         "bbp_server_create": (i32, [i64, i32, P(vp)]),
@@ -260,6 +261,14 @@ class PepsNet:
         r, w = C.c_int64(0), C.c_int64(0)
         _check(self.lib.pepsnet_memory(self.h, C.byref(r), C.byref(w)))
         return r.value, w.value
+
+    def autotune(self, cache_path=None):
+        """Pick the fastest GEMM tile shape per GEMM shape of the sweep plans
+        (cached in ``cache_path``); returns (shapes timed now, shapes tuned)."""
+        nt, ns = C.c_int32(0), C.c_int32(0)
+        _check(self.lib.pepsnet_autotune(self.h, None if cache_path is None else
+                                         os.fsencode(cache_path), C.byref(nt), C.byref(ns)))
+        return nt.value, ns.value
 
     def release_workspace(self):
         _check(self.lib.pepsnet_release_workspace(self.h))

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -128,6 +129,9 @@ struct pepsnet_s {
     int64_t epoch = -1;
   };
   std::map<std::vector<int>, Subset> subsets;
+  // tile shape chosen by pepsnet_autotune per GEMM shape (prec, M, N, K,
+  // opA, opB, scatter store); shapes not in it use the fixed rule
+  std::map<std::array<int, 7>, int> gemm_tiles;
   // blockbp_sweep_noalloc: the sweep plans resolved against the device's
   // fixed workspace (compiled on its first call) and their descriptors
   int device = 0;
@@ -261,8 +265,17 @@ size_t push_descs(std::vector<char>* blob, const std::vector<T>& v) {
 
 // kernel variant an op runs with (part of its bucket key, so that an item
 // runs the same kernel whether it is launched alone or in a batch)
-int op_variant(const Op& op) {
-  if (op.type == OPK_GEMM) {   // k_gemm tile shape
+std::array<int, 7> gemm_key(const Op& op) {
+  return {int(op.i[8]), int(op.i[0]), int(op.i[1]), int(op.i[2]), int(op.i[6]), int(op.i[7]),
+          op.i[10] > 0 ? 1 : 0};
+}
+
+int op_variant(const pepsnet_s* h, const Op& op) {
+  if (op.type == OPK_GEMM) {   // k_gemm tile shape: the tuned one, else by M and N
+    if (h && !h->gemm_tiles.empty()) {
+      auto it = h->gemm_tiles.find(gemm_key(op));
+      if (it != h->gemm_tiles.end()) return it->second;
+    }
     const int64_t M = op.i[0], N = op.i[1];
     if (M <= 16) return 1;
     if (N <= 16) return 2;
@@ -316,7 +329,7 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
       const OpSource& src = srcs[std::get<1>(all[t])];
       const Op& op = (*src.lanes)[std::get<2>(all[t])][std::get<3>(all[t])].second;
       int prec = op.type == OPK_GEMM ? int(op.i[8]) : 0;
-      buckets[{op.type, prec, op_variant(op)}].push_back({src.h, &op});
+      buckets[{op.type, prec, op_variant(src.h, op)}].push_back({src.h, &op});
     }
     for (auto& bk : buckets) {
       LaunchRec rec;
@@ -1154,6 +1167,60 @@ void srv_loop(bbp_server_s* S) {
   }
 }
 
+// ---- GEMM tile autotuner (pepsnet_autotune)
+// Grid of a GEMM launch of `items` descriptors for tile shape v.
+dim3 gemm_grid(int v, int64_t M, int64_t N, int items) {
+  const int tm = v == 1 ? 16 : v == 4 ? 80 : 64;
+  const int tn = v == 2 ? 16 : v == 3 ? 80 : 64;
+  return dim3(unsigned((N + tn - 1) / tn), unsigned(std::min<int64_t>(65535, (M + tm - 1) / tm)),
+              unsigned(items));
+}
+
+// Elements a GEMM descriptor writes past its C pointer (the extent of the
+// output, scattered or row-major).
+int64_t gemm_out_extent(const GemmDesc& g) {
+  if (g.sc_n > 0) {
+    int64_t e = 1;
+    for (int k = 0; k < g.sc_n; ++k) e += int64_t(g.sc_dim[k] - 1) * g.sc_ds[k];
+    return e;
+  }
+  return int64_t(g.M - 1) * g.ldc + g.N;
+}
+
+bool load_tile_cache(const char* path, std::map<std::array<int, 7>, int>* t) {
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') continue;
+    std::array<int, 7> k;
+    int v;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5],
+                    &k[6], &v) == 8 && v >= 0 && v <= 4)
+      (*t)[k] = v;
+  }
+  std::fclose(f);
+  return true;
+}
+
+bool save_tile_cache(const char* path, const std::map<std::array<int, 7>, int>& t) {
+  if (!path || !*path) return true;
+  std::map<std::array<int, 7>, int> all;
+  load_tile_cache(path, &all);
+  for (const auto& kv : t) all[kv.first] = kv.second;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fprintf(f, "# pepsnet k_gemm tile shapes, gfx950: prec M N K opA opB scatter tile\n");
+  for (const auto& kv : all) {
+    const auto& k = kv.first;
+    std::fprintf(f, "%d %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], k[4], k[5], k[6], kv.second);
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
 // At create: when the workspace and the descriptors fit in the device's
 // fixed array, resolve the sweep plans against it (host-side compilation)
 // and keep a pinned copy of their descriptors for blockbp_sweep_noalloc.
@@ -1663,6 +1730,113 @@ int32_t pepsnet_profile_launches(pepsnet_t h, double* rec, int64_t cap, int64_t*
   h->parity ^= 1;
   h->sweeps_total += 1;
   return BBP_OK;
+}
+
+int32_t pepsnet_autotune(pepsnet_t h, const char* cache_path, int32_t* n_timed, int32_t* n_shapes) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (int32_t rc = need_work(h)) return rc;
+  std::map<std::array<int, 7>, int> cache;
+  load_tile_cache(cache_path, &cache);
+  // one representative launch per GEMM shape of the sweep plans
+  std::map<std::array<int, 7>, std::pair<const LaunchRec*, const GemmDesc*>> shapes;
+  for (int par = 0; par < 2; ++par)
+    for (const LaunchRec& r : h->sweep[par].launches) {
+      if (r.type != OPK_GEMM) continue;
+      const GemmDesc* gd = reinterpret_cast<const GemmDesc*>(h->desc_host.data() + r.desc_off);
+      Op probe;
+      probe.i[8] = r.prec; probe.i[0] = gd->M; probe.i[1] = gd->N; probe.i[2] = gd->K;
+      probe.i[6] = gd->opA; probe.i[7] = gd->opB; probe.i[10] = gd->sc_n;
+      shapes.emplace(gemm_key(probe), std::make_pair(&r, gd));
+    }
+  int timed = 0;
+  std::map<std::array<int, 7>, int> chosen;
+  cplx* tmp = nullptr;
+  size_t tmp_len = 0;
+  char* ddev = nullptr;
+  size_t ddev_len = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int32_t rc = BBP_OK;
+  auto cleanup = [&]() {
+    if (tmp) hipFree(tmp);
+    if (ddev) hipFree(ddev);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+  };
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(BBP_EDEVICE, "autotune events");
+  }
+  for (const auto& kv : shapes) {
+    auto hit = cache.find(kv.first);
+    if (hit != cache.end()) {
+      chosen[kv.first] = hit->second;
+      continue;
+    }
+    const LaunchRec& r = *kv.second.first;
+    // the launch's descriptors with every output redirected to a private
+    // buffer (operands are only read), so timing leaves the state untouched
+    std::vector<GemmDesc> d(kv.second.second, kv.second.second + r.count);
+    int64_t ext = 0, mM = 1, mN = 1;
+    for (const GemmDesc& g : d) {
+      ext = std::max(ext, gemm_out_extent(g));
+      mM = std::max<int64_t>(mM, g.M);
+      mN = std::max<int64_t>(mN, g.N);
+    }
+    const size_t need = size_t(ext) * d.size();
+    if (need > tmp_len) {
+      if (tmp) hipFree(tmp);
+      tmp = nullptr;
+      if (hipMalloc(&tmp, need * sizeof(cplx)) != hipSuccess) { rc = fail(BBP_ENOMEM, "autotune buffer"); break; }
+      tmp_len = need;
+    }
+    for (size_t i = 0; i < d.size(); ++i) d[i].C = tmp + int64_t(i) * ext;
+    if (d.size() * sizeof(GemmDesc) > ddev_len) {
+      if (ddev) hipFree(ddev);
+      ddev = nullptr;
+      if (hipMalloc(&ddev, d.size() * sizeof(GemmDesc)) != hipSuccess) { rc = fail(BBP_ENOMEM, "autotune descriptors"); break; }
+      ddev_len = d.size() * sizeof(GemmDesc);
+    }
+    if (hipMemcpyAsync(ddev, d.data(), d.size() * sizeof(GemmDesc), hipMemcpyHostToDevice, h->stream) != hipSuccess) {
+      rc = fail(BBP_EDEVICE, "autotune upload");
+      break;
+    }
+    int best = -1;
+    float best_ms = 0.0f;
+    for (int v = 0; v <= 4 && rc == BBP_OK; ++v) {
+      LaunchRec t = r;
+      t.variant = v;
+      t.desc_off = 0;
+      t.grid = gemm_grid(v, mM, mN, int(d.size()));
+      float ms = 0.0f;
+      hipError_t e = launch(ddev, h->stream, t);   // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+      for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch(ddev, h->stream, t);
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) { rc = fail(BBP_EDEVICE, std::string("autotune: ") + hipGetErrorString(e)); break; }
+      if (best < 0 || ms < best_ms) { best = v; best_ms = ms; }
+    }
+    if (rc != BBP_OK) break;
+    chosen[kv.first] = best;
+    timed += 1;
+  }
+  if (rc == BBP_OK) rc = hipStreamSynchronize(h->stream) == hipSuccess ? BBP_OK : fail(BBP_EDEVICE, "autotune sync");
+  cleanup();
+  if (rc != BBP_OK) return rc;
+  h->gemm_tiles = chosen;
+  if (!save_tile_cache(cache_path, chosen)) return fail(BBP_EINVAL, "cannot write the tile cache");
+  if (n_timed) *n_timed = timed;
+  if (n_shapes) *n_shapes = int32_t(chosen.size());
+  // recompile every plan with the chosen tiles (results are unchanged: a
+  // tile shape does not change any element's sum order)
+  free_subsets(h);
+  rc = build_launches(h);
+  if (rc) return rc;
+  if (h->blob_fixed) hipHostFree(h->blob_fixed);
+  h->blob_fixed = nullptr;
+  h->fixed_ready = false;
+  return prepare_fixed(h);
 }
 
 int32_t pepsnet_memory(pepsnet_t h, int64_t* resident_bytes, int64_t* workspace_bytes) {
