@@ -3,10 +3,17 @@ block N=4 (111 sites), D=6, chi=64, simple-update tensors, randomized
 truncation (q=2, p=8), one sweep from seeded messages and the expectation,
 against the FP64 oracle's values stored by tests/golden/make_cfg4_fixture.py.
 
-Compared: each message's distance to its start (the sweep's convergence
-distance) and the Schmidt values of every cut of every new message
-(gauge-invariant) to 1e-10; rho_ij / Tr rho_ij entry by entry, <S.S> per
-bond and the energy per site to 1e-10 in FP64.  FP32 contraction GEMMs
+Compared in FP64: each message's distance to its start (the sweep's
+convergence distance), rho_ij / Tr rho_ij entry by entry, <S.S> per bond and
+the energy per site to 1e-10; the Schmidt values of every cut of every new
+message (gauge-invariant fingerprints of the messages themselves) to 1e-9.
+The messages are intermediates whose rounding sensitivity is set by the
+truncations: the smallest gap between kept and dropped singular values of
+the 2304 x 2304 randomized splits of a message update is 7.7e-6 sigma_1
+(kept value 2.4e-3 sigma_1), so a kept subspace moves by about u sigma_1 /
+gap ~ 1e-11 per unit of accumulated rounding, over about a hundred
+truncating splits per message; the GPU and the oracle differ by up to
+4e-10 there, while every observable agrees to 1e-14.  FP32 contraction GEMMs
 reach 1e-5 on the energy (every bond from warm messages); split-BF16 (three
 bf16 products, about 16 significant bits per operand) is held to the bound
 it reaches, 5e-4, and its errors are printed."""
@@ -25,8 +32,9 @@ pytestmark = pytest.mark.gpu
 pn = pytest.importorskip("paper_2603_13304_amd")
 
 FIX = os.path.join(os.path.dirname(__file__), "golden", "cfg4_one_sweep.json")
-# unique bonds whose oracle contraction meets a degenerate cut (fixture)
-N_DEGENERATE_BONDS = None
+# unique bonds whose oracle contraction meets a degenerate cut (the fixture
+# records one such cut per bond: the first split after the open site)
+N_DEGENERATE_BONDS = 6
 
 
 def _fixture():
@@ -65,7 +73,7 @@ def test_cfg4_fp64_one_sweep_against_fixture():
         for got, ref in zip(bb.schmidt_spectra(msgs[m]), fx["schmidt"][m]):
             worst = max(worst, np.abs(got - np.array(ref)).max())
     print("schmidt", worst)
-    assert worst < 1e-10
+    assert worst < 1e-9
     assert [list(b) for b in bonds] == fx["bonds"]
     # bonds whose contraction meets a degenerate cut in the oracle have no
     # unique truncation: their values are printed, not compared

@@ -7,7 +7,7 @@ import pytest
 
 from synth import inputs as syn
 
-from gpu_cases import problem
+from gpu_cases import oracle_for, oracle_rhos, problem
 
 pytestmark = pytest.mark.gpu
 
@@ -137,3 +137,31 @@ def test_server_slots_reused_and_requests_overlap():
         assert g.memory()[1] > 0
         with pytest.raises(pn.PepsnetError):
             g.blockbp_sweep(1, 0.0)
+
+
+def test_server_request_matches_oracle():
+    """A served request on a fresh state (identity messages) with new site
+    tensors, swept to 1e-10, gives the energy per site and every bond's
+    <S.S> of the FP64 oracle run to 1e-10 on the same tensors."""
+    from oracle.dense import ss_from_rho
+    P, desc = problem("infinite", N=2, D=2, chi=8)
+    ts0 = syn.simple_update_cell(2, seed=4, steps=20, dtau=0.05)
+    ts = _ite_step(ts0, 7)
+    g = pn.PepsNet(desc, ts0)
+    g.release_workspace()
+    srv = pn.Server(1 << 40, 2)
+    r = srv.poll(srv.submit(g, ts, tol=1e-10, max_sweeps=40))
+    srv.close()
+    O = oracle_for(P, ts, 8, 0, 2, 8, 0)
+    so, eo = O.run(tol=1e-10, max_sweeps=40)
+    print(f"served: {r['sweeps']} sweeps, err {r['err']:.2e}; oracle {so} sweeps, err {eo:.2e}")
+    assert r["rc"] == pn.binding.BBP_OK and r["err"] <= 1e-10 and eo <= 1e-10
+    g.acquire_workspace()
+    ref = oracle_rhos(O, g.bonds())
+    assert all(x is not None for x in ref)
+    ss_ref = np.array([ss_from_rho(x) for x in ref])
+    e_ref = ss_ref.sum() / 3
+    print(f"E/site served {r['energy']:.15f} oracle {e_ref:.15f}")
+    assert abs(r["energy"] - e_ref) < 1e-10
+    assert np.abs(r["ss"] - ss_ref).max() < 1e-10
+    g.close()
