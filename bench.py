@@ -57,10 +57,14 @@ def parse():
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the fixed GEMM tile rule")
+    ap.add_argument("--tile-cache", default=None,
+                    help="GEMM tile cache file (shapes found there are not timed again)")
     ap.add_argument("--profile-sweeps", type=int, default=2)
     ap.add_argument("--expect-reps", type=int, default=5)
-    ap.add_argument("--converge-sweeps", type=int, default=20,
-                    help="sweeps toward 1e-5 before the expectation latency")
+    ap.add_argument("--converge-sweeps", type=int, default=8,
+                    help="sweeps toward 1e-5 before the expectation latency (the randomized "
+                         "split stops at a distance floor of about 3e-2 here)")
     ap.add_argument("--no-precisions", action="store_true",
                     help="skip the FP32 / split-BF16 runs of the headline workload")
     ap.add_argument("--no-small", action="store_true", help="skip the N=3, D=3, chi=16 section")
@@ -68,8 +72,19 @@ def parse():
     ap.add_argument("--batched-blocks", type=int, default=64)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving section")
     ap.add_argument("--serving-states", type=int, default=32)
-    ap.add_argument("--serving-requests", type=int, default=64)
+    ap.add_argument("--serving-requests", type=int, default=48)
     ap.add_argument("--serving-inflight", type=int, default=8)
+    ap.add_argument("--serving-max-sweeps", type=int, default=3)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (for the HBM counter scale)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="only summarise four rocprofv3 --pmc counter CSVs into "
+                         "profiles/hbm_traffic.json and exit")
+    ap.add_argument("--traffic-command", default="", help="commands recorded with --traffic-from")
+    ap.add_argument("--copy-mib", type=int, default=256, help="size of the calibration copy")
+    ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+    ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
+                    help="only print a per-kernel table of a rocprofv3 --stats CSV and exit")
     return ap.parse_args()
 
 
@@ -191,6 +206,8 @@ def precision_runs(args, ts, fp64_msgs, e_fp64, err_fp64):
     out = {}
     for prec in ("fp32", "bf16x3"):
         g = make_net(args, prec, ts)
+        if not args.no_autotune:
+            g.autotune(args.tile_cache)
         wall, _, _ = timed_sweeps(g, 1, 3)
         g.set_messages(fp64_msgs)
         _, err, _ = g.blockbp_sweep(1, 0.0)
@@ -206,22 +223,29 @@ def precision_runs(args, ts, fp64_msgs, e_fp64, err_fp64):
 
 def small_section(args):
     """N=3, D=3, chi=16 with exact truncated SVDs (T1), FP32 contraction: the
-    round-trip-latency-bound end of the method."""
+    round-trip-latency-bound end of the method, and the workload on which the
+    sweeps reach 1e-5 (the expectation latency at that tolerance)."""
     from synth import inputs as syn
     a = argparse.Namespace(**vars(args))
     a.N, a.D, a.chi, a.trunc = 3, 3, 16, "T1"
     ts = syn.simple_update_cell(3, seed=2, steps=20, dtau=0.05)
     g = make_net(a, "fp32", ts)
     wall, dev_ms, _ = timed_sweeps(g, 5, 20)
-    g.blockbp_sweep(40, 1e-5)
+    g.set_sites(ts, reset_messages=True)       # identity messages again
+    sw, err, _ = g.blockbp_sweep(60, 1e-5)
     lat = []
-    for _ in range(5):
+    for _ in range(args.expect_reps * 4):
         t = time.perf_counter()
-        g.blockbp_expect()
+        _, ss, e = g.blockbp_expect()
         lat.append(1e3 * (time.perf_counter() - t))
     g.close()
     return {"workload": workload_name(a, "fp32"), "msg_updates_per_s": 6 * 20 / wall,
-            "ms_per_sweep": 1e3 * wall / 20, "expect_latency_ms_p50": float(np.median(lat))}
+            "ms_per_sweep": 1e3 * wall / 20,
+            "expect_latency_ms": {"p50": float(np.percentile(lat, 50)),
+                                  "p99": float(np.percentile(lat, 99)), "reps": len(lat),
+                                  "sweeps_from_identity": sw, "distance_reached": err,
+                                  "tolerance_reached": bool(err <= 1e-5),
+                                  "energy_per_site": e}}
 
 
 def batched_section(args):
@@ -239,6 +263,17 @@ def batched_section(args):
         desc = make_desc(pn.BBP_KAGOME_INF_HEX, D=D, chi=chi, hex_N=N, precision=1, trunc=1,
                          q=2, p=8, seed=7)
         nets.append(pn.PepsNet(desc, ts))
+    # tile shapes per GEMM shape, timed once per shape across the blocks
+    import tempfile
+    t0 = time.perf_counter()
+    n_timed = 0
+    with tempfile.TemporaryDirectory() as tmp:
+        cache = os.path.join(tmp, "tiles.txt")
+        for g in nets:
+            n_timed += g.autotune(cache)[0]
+    tune_s = time.perf_counter() - t0
+    print(f"[bench] batched: autotuned {n_timed} GEMM shapes in {tune_s:.1f} s", file=sys.stderr,
+          flush=True)
     b = pn.Batch(nets)
     b.use_graph(True)
     gf, nl = b.stats()
@@ -262,7 +297,8 @@ def batched_section(args):
         g.close()
     return {"workload": f"{len(nets)} infinite-kagome blocks, N in 2..5, D in 2..4, chi in "
                         "8..64 (seeded), unit-norm random tensors, randomized truncation "
-                        "(q=2, p=8), fp32 contraction GEMMs",
+                        "(q=2, p=8), fp32 contraction GEMMs, autotuned GEMM tiles",
+            "autotuned_gemm_shapes": n_timed, "autotune_seconds": tune_s,
             "updates_per_sweep": upd, "launches_per_sweep": int(nl), "gemm_flop_per_sweep": gf,
             "batched_msg_updates_per_s": upd / wall_b, "batched_device_ms": dev_ms,
             "per_block_msg_updates_per_s": upd / wall_s,
@@ -272,74 +308,203 @@ def batched_section(args):
 def serving_section(args):
     """Poisson stream of expectation requests on resident states (each an
     imaginary-time-step perturbation of its state, messages warm-started),
-    continuous batching vs one request at a time on the same stream."""
+    continuous batching against one request at a time.  Half the states are
+    N=3, D=3, chi=16 with exact truncation (T1), on which sweeps converge to
+    1e-5; the others draw D in 3..5, chi in 16..64 with the randomized split
+    (q=2, p=8), whose sweeps stop at a distance floor of 1e-3..3e-2 (the
+    sketch's truncation error) and therefore run max_sweeps.  Reported: how
+    many requests reached the tolerance, latency over all requests and over
+    those that reached it."""
     import paper_2603_13304_amd as pn
     from paper_2603_13304_amd.binding import make_desc
     from synth import inputs as syn
     rng = np.random.default_rng(5)
+    others = [(3, 32), (3, 64), (4, 16), (4, 32), (4, 64), (5, 16), (5, 32), (5, 64)]
+    tol, max_sweeps = 1e-5, args.serving_max_sweeps
     states = []
     for i in range(args.serving_states):
-        D, chi = int(rng.choice([3, 4, 5])), int(rng.choice([16, 32, 64]))
-        ts = [t / np.linalg.norm(t) for t in syn.random_unit_cell(D, seed=300 + i)]
-        desc = make_desc(pn.BBP_KAGOME_INF_HEX, D=D, chi=chi, hex_N=3, precision=1, trunc=1,
+        if i % 2 == 0:
+            D, chi, trunc = 3, 16, 0
+        else:
+            D, chi = others[int(rng.integers(0, len(others)))]
+            trunc = 1
+        ts = syn.simple_update_cell(D, seed=300 + i, steps=20, dtau=0.05)
+        desc = make_desc(pn.BBP_KAGOME_INF_HEX, D=D, chi=chi, hex_N=3, precision=1, trunc=trunc,
                          q=2, p=8, seed=7)
         g = pn.PepsNet(desc, ts)
-        g.blockbp_sweep(2, 0.0)                  # resident, partly converged messages
+        # resident, warm messages: converged (T1) or at the sketch's floor (T2)
+        g.blockbp_sweep(30 if trunc == 0 else 3, tol)
         g.release_workspace()
-        states.append((g, ts))
-    ws = [g.memory()[1] for g, _ in states]
-    res_bytes = sum(g.memory()[0] for g, _ in states)
+        states.append((g, ts, f"D{D}chi{chi}{'T1' if trunc == 0 else 'T2'}", trunc))
+    print(f"[bench] serving: {len(states)} states resident", file=sys.stderr, flush=True)
+    ws = [g.memory()[1] for g, _, _, _ in states]
+    res_bytes = sum(g.memory()[0] for g, _, _, _ in states)
     budget = int(64e9)
     arrivals = np.cumsum(rng.exponential(1.0 / 200.0, size=args.serving_requests))
     reqs = []
     for k in range(args.serving_requests):
         si = int(rng.integers(0, len(states)))
-        g, ts = states[si]
+        g, ts, cls, trunc = states[si]
         prng = np.random.default_rng(1000 + k)
         new = [t + 1e-3 * (prng.standard_normal(t.shape) + 1j * prng.standard_normal(t.shape))
                for t in ts]
-        reqs.append((arrivals[k], g, new))
+        # exact-truncation states converge: enough sweeps to reach tol from
+        # the warm start; randomized ones stop at their floor within a few
+        reqs.append((arrivals[k], g, new, cls, 4 * max_sweeps if trunc == 0 else max_sweeps))
 
     def run(inflight):
         srv = pn.Server(budget, inflight)
         t0 = time.perf_counter()
         tickets = []
-        for at, g, new in reqs:
+        for at, g, new, _, ms in reqs:
             now = time.perf_counter() - t0
             if at > now:
                 time.sleep(at - now)
-            tickets.append(srv.submit(g, new, tol=1e-5, max_sweeps=3))
-        lat = [srv.poll(t)["latency_s"] for t in tickets]
+            tickets.append(srv.submit(g, new, tol=tol, max_sweeps=ms))
+        res = [srv.poll(t) for t in tickets]
         wall = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        return np.array(lat), wall, st
+        return res, wall, st
 
-    lat_b, wall_b, st_b = run(args.serving_inflight)
+    def summary(res, wall):
+        lat = np.array([r["latency_s"] for r in res])
+        ok = np.array([r["err"] <= tol for r in res])
+        out = {"throughput_req_per_s": len(res) / wall,
+               "latency_p50_s": float(np.percentile(lat, 50)),
+               "latency_p99_s": float(np.percentile(lat, 99)),
+               "reached_tol": int(ok.sum())}
+        if ok.any():
+            out["reached_latency_p50_s"] = float(np.percentile(lat[ok], 50))
+            out["reached_latency_p99_s"] = float(np.percentile(lat[ok], 99))
+        return out
+
+    res_b, wall_b, st_b = run(args.serving_inflight)
     print(f"[bench] serving: {len(reqs)} requests, continuous batching {wall_b:.2f} s",
           file=sys.stderr, flush=True)
-    lat_s, wall_s, st_s = run(1)
+    res_s, wall_s, _ = run(1)
     print(f"[bench] serving: one at a time {wall_s:.2f} s", file=sys.stderr, flush=True)
-    for g, _ in states:
+    for g, _, _, _ in states:
         g.close()
     n = len(reqs)
-    return {"workload": f"{len(states)} resident infinite-kagome states (N=3, D in 3..5, chi in "
-                        "16..64, fp32 contraction GEMMs, randomized truncation), Poisson arrivals "
-                        f"at 200 req/s, {n} requests, each an ITE-step perturbation + warm-started "
-                        "sweeps to 1e-5 (at most 3) + expectation",
-            "hbm_budget_bytes": budget, "resident_bytes": int(res_bytes),
-            "max_workspace_bytes": int(max(ws)), "peak_workspace_bytes": int(st_b["peak_bytes"]),
-            "max_inflight": args.serving_inflight, "peak_inflight": int(st_b["peak_inflight"]),
-            "throughput_req_per_s": n / wall_b,
-            "latency_p50_s": float(np.percentile(lat_b, 50)),
-            "latency_p99_s": float(np.percentile(lat_b, 99)),
-            "one_at_a_time": {"throughput_req_per_s": n / wall_s,
-                              "latency_p50_s": float(np.percentile(lat_s, 50)),
-                              "latency_p99_s": float(np.percentile(lat_s, 99))}}
+    by_cls = {}
+    for (_, _, _, cls, _), r in zip(reqs, res_b):
+        c = by_cls.setdefault(cls, {"requests": 0, "reached_tol": 0, "max_final_distance": 0.0})
+        c["requests"] += 1
+        c["reached_tol"] += int(r["err"] <= tol)
+        c["max_final_distance"] = max(c["max_final_distance"], float(r["err"]))
+    out = {"workload": f"{len(states)} resident infinite-kagome states N=3 (half D=3, chi=16 "
+                       "exact truncation; half D in 3..5, chi in 16..64 randomized truncation), "
+                       "simple-update tensors, fp32 contraction GEMMs; Poisson arrivals at 200 "
+                       f"req/s, {n} requests, each an ITE-step perturbation + warm-started "
+                       f"sweeps to {tol:g} (at most {4 * max_sweeps} exact, {max_sweeps} "
+                       "randomized) + expectation",
+           "tolerance": tol, "max_sweeps": max_sweeps,
+           "hbm_budget_bytes": budget, "resident_bytes": int(res_bytes),
+           "max_workspace_bytes": int(max(ws)), "peak_workspace_bytes": int(st_b["peak_bytes"]),
+           "slot_allocations": int(st_b["slot_allocations"]),
+           "max_inflight": args.serving_inflight, "peak_inflight": int(st_b["peak_inflight"]),
+           "by_state_class": by_cls,
+           "one_at_a_time": summary(res_s, wall_s)}
+    out.update(summary(res_b, wall_b))
+    return out
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of a known size, for scaling the HBM
+    counters (FETCH_SIZE, WRITE_SIZE) of the kernels."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n, "launches": 3}), flush=True)
+
+
+def _counter_means(path, counter):
+    """Mean value of ``counter`` per dispatch, per kernel name, from a
+    rocprofv3 counter-collection CSV."""
+    import csv
+    acc = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row["Kernel_Name"]
+            base = name.split("(")[0].split("<")[0].replace("void ", "").strip()
+            base = base.split("::")[-1]
+            a = acc.setdefault(base, [0.0, 0])
+            a[0] += float(row["Counter_Value"])
+            a[1] += 1
+    return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
+
+
+def traffic_from(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, command, copy_mib, out):
+    """HBM bytes per launch for each kernel: FETCH_SIZE and WRITE_SIZE (KiB
+    per dispatch) scaled by what the same counters read for a plain copy of
+    known size (bench.py --copy-calibration)."""
+    fetch, write = _counter_means(fetch_csv, "FETCH_SIZE"), _counter_means(write_csv, "WRITE_SIZE")
+    cf, cw = _counter_means(copy_fetch_csv, "FETCH_SIZE"), _counter_means(copy_write_csv, "WRITE_SIZE")
+    # the copy kernel: the kernel of the calibration run with the largest
+    # mean counter value (the copy of copy_mib MiB)
+    kf = max(cf.items(), key=lambda kv: kv[1][0])
+    kw = max(cw.items(), key=lambda kv: kv[1][0])
+    copy_bytes = float(copy_mib << 20)
+    scale_f = kf[1][0] * 1024.0 / copy_bytes
+    scale_w = kw[1][0] * 1024.0 / copy_bytes
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        fb = fetch[k][0] * 1024.0 / scale_f
+        wb = write[k][0] * 1024.0 / scale_w
+        kernels[k] = {"bytes_per_launch": fb + wb, "fetch_bytes_per_launch": fb,
+                      "write_bytes_per_launch": wb, "dispatches": fetch[k][1]}
+    src = os.path.join(ROOT, "paper_2603_13304_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    rec = {"command": command, "copy_kernel": kf[0], "copy_bytes": copy_bytes,
+           "fetch_scale": scale_f, "write_scale": scale_w, "kernels_hip_sha256": sha,
+           "kernels": kernels}
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(out)
+
+
+def stats_summary(path):
+    """Per-kernel table (template instances of k_gemm grouped by precision)
+    of a rocprofv3 kernel_stats.csv: calls, total and average duration."""
+    import csv
+    agg = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row["Name"].replace("void ", "")
+            base = name.split("(")[0]
+            key = base.split("<")[0].split("::")[-1]
+            if key == "k_gemm":   # k_gemm<precision, tile shape>
+                key += "<" + base.split("<")[1].split(",")[0] + ">"
+            a = agg.setdefault(key, [0, 0.0])
+            a[0] += int(row["Calls"])
+            a[1] += float(row["TotalDurationNs"])
+    tot = sum(v[1] for v in agg.values())
+    print("| kernel | calls | total ms | avg us | share |")
+    print("|---|---|---|---|---|")
+    for k, (n, ns) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        print(f"| {k} | {n} | {ns / 1e6:.2f} | {ns / n / 1e3:.2f} | {100 * ns / tot:.1f} % |")
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.traffic_from:
+        traffic_from(*args.traffic_from, args.traffic_command, args.copy_mib, args.traffic_out)
+        return
+    if args.stats_summary:
+        stats_summary(args.stats_summary)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(the sweep would shard its six message updates over GPUs with one all-gather "
@@ -351,6 +516,9 @@ def main():
     ts = syn.simple_update_cell(args.D, seed=2, steps=20, dtau=0.05)
     g = make_net(args, args.precision, ts)
     n_msg = g.num_messages()
+    t0 = time.perf_counter()
+    n_tuned = 0 if args.no_autotune else g.autotune(args.tile_cache)[1]
+    tune_s = time.perf_counter() - t0
     print(f"[bench] created N={args.N} D={args.D} chi={args.chi} {args.trunc} {args.precision}",
           file=sys.stderr, flush=True)
     # warmup sweeps (messages reach full bond dimension, graph captured),
@@ -370,13 +538,17 @@ def main():
     # expectation latency once converged to 1e-5 (or after converge_sweeps)
     sw, err_c, _ = g.blockbp_sweep(args.converge_sweeps, 1e-5)
     msgs = g.get_messages()
-    lat = []
+    lat, ss, e = [], [], float("nan")
     for _ in range(args.expect_reps):
         t = time.perf_counter()
         _, ss, e = g.blockbp_expect()
         lat.append(1e3 * (time.perf_counter() - t))
-    _, err_next, _ = g.blockbp_sweep(1, 0.0)
-    g.set_messages(msgs)
+    # the FP64 reference of the precision runs: one more sweep from the same
+    # messages, then the expectation
+    err_next, e_next = float("nan"), float("nan")
+    if not args.no_precisions and args.precision == "fp64":
+        _, err_next, _ = g.blockbp_sweep(1, 0.0)
+        _, _, e_next = g.blockbp_expect()
     g.close()
     out = {
         "metric": "block msg updates/s + % MFMA peak; p50/p99 expect-value latency at 1e-5",
@@ -392,11 +564,12 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": workload_name(args, args.precision),
-                   "message_updates_per_step": n_msg, "graph": not args.no_graph},
+                   "message_updates_per_step": n_msg, "graph": not args.no_graph,
+                   "autotuned_gemm_shapes": n_tuned, "autotune_seconds": round(tune_s, 2)},
         "roofline": roof,
         "mfma": mfma,
-        "expect_latency_ms": {"p50": float(np.percentile(lat, 50)),
-                              "p99": float(np.percentile(lat, 99)),
+        "expect_latency_ms": {"p50": float(np.percentile(lat, 50)) if lat else None,
+                              "p99": float(np.percentile(lat, 99)) if lat else None,
                               "sweeps_before": sw, "distance_reached": err_c,
                               "tolerance_reached": bool(err_c <= 1e-5),
                               "energy_per_site": e, "bonds": len(ss)},
@@ -404,7 +577,7 @@ def main():
                   "contraction_gflop": cf / 1e9, "gemm_gflop": gf / 1e9, "kernels": breakdown},
     }
     if not args.no_precisions and args.precision == "fp64":
-        out["precisions"] = precision_runs(args, ts, msgs, e, err_next)
+        out["precisions"] = precision_runs(args, ts, msgs, e_next, err_next)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(ts, args)

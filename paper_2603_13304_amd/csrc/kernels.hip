@@ -1416,6 +1416,23 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol(const CholDesc* __restric
 // space holds the inverse's block products.
 constexpr int CHB_N = 80, CHB_LD = 80;
 
+// Complex 16 x 16 tile product on the matrix cores, acc += A B over
+// k in [kb, ke) (stepping by 4 from kb; loaders return 0 outside): four real
+// FP64 MFMAs per step.  MFMA operand layout: lane supplies A[lane % 16][k]
+// and B[k][lane % 16] with k = k0 + lane / 16; the accumulator holds rows
+// lane / 16 + 4 t, column lane % 16.  All 64 lanes must be active.
+template <class LA, class LB>
+__device__ __forceinline__ void cmma16(int kb, int ke, int lane, LA la, LB lb, d4& accr, d4& acci) {
+  for (int k0 = kb; k0 < ke; k0 += 4) {
+    const int k = k0 + (lane >> 4);
+    const cplx a = la(lane & 15, k), b = lb(k, lane & 15);
+    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.re, accr, 0, 0, 0);
+    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, b.im, accr, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, b.im, acci, 0, 0, 0);
+    acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, b.re, acci, 0, 0, 0);
+  }
+}
+
 __device__ __forceinline__ cplx shfl_c(cplx v, int src) {
   return cplx{__shfl(v.re, src), __shfl(v.im, src)};
 }
@@ -1559,39 +1576,75 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
         if (i < kw) A[(k0 + i) * CHB_LD + c] = x[i];
     }
     __syncthreads();
-    // (3) trailing triangle: G[i][c] -= sum_l conj(R[l][i]) R[l][c]
-    const int t = n - c1;
-    for (int e = tid; e < t * t; e += CHOL_THREADS) {
-      const int a = e / t, b = e - a * t;
-      if (a > b) continue;
-      const int i = c1 + a, c = c1 + b;
-      cplx s = A[i * CHB_LD + c];
-      for (int l = 0; l < kw; ++l) {
-        const cplx ri = A[(k0 + l) * CHB_LD + i], rc = A[(k0 + l) * CHB_LD + c];
-        s.re -= ri.re * rc.re + ri.im * rc.im;
-        s.im -= ri.re * rc.im - ri.im * rc.re;
+    // (3) trailing triangle: G[i][c] -= sum_l conj(R[l][i]) R[l][c], one
+    // wave per upper 16 x 16 tile on the matrix cores
+    const int t = n - c1, tt = (t + 15) / 16;
+    for (int p = wave; p < tt * tt; p += CHOL_THREADS / 64) {
+      const int ta = p / tt, tb = p - ta * tt;
+      if (ta > tb) continue;
+      const int i0 = c1 + 16 * ta, j0 = c1 + 16 * tb;
+      d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+      cmma16(0, 16, lane,
+             [&](int r, int l) {   // conj(R[k0 + l][i0 + r])
+               cplx v = {0.0, 0.0};
+               if (l < kw && i0 + r < n) {
+                 v = A[(k0 + l) * CHB_LD + i0 + r];
+                 v.im = -v.im;
+               }
+               return v;
+             },
+             [&](int l, int c) {   // R[k0 + l][j0 + c]
+               cplx v = {0.0, 0.0};
+               if (l < kw && j0 + c < n) v = A[(k0 + l) * CHB_LD + j0 + c];
+               return v;
+             },
+             accr, acci);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = i0 + (lane >> 4) + 4 * q, c = j0 + (lane & 15);
+        if (i < n && c < n && i <= c) {
+          cplx v = A[i * CHB_LD + c];
+          v.re -= accr[q];
+          v.im -= acci[q];
+          A[i * CHB_LD + c] = v;
+        }
       }
-      A[i * CHB_LD + c] = s;
     }
     __syncthreads();
   }
-  // running factor R <- R_new R_prev (R_prev staged packed in W)
-  if (want_r) {
+  // running factor R <- R_new R_prev (R_prev staged packed in W) on the
+  // matrix cores: one wave per 16 x 16 output tile; tiles below the
+  // diagonal are zero
+  if (acc_r) {
+    const int nt = (n + 15) / 16;
+    for (int p = wave; p < nt * nt; p += CHOL_THREADS / 64) {
+      const int ta = p / nt, tb = p - ta * nt;
+      d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+      if (ta <= tb) {
+        const int i0 = 16 * ta, j0 = 16 * tb;
+        cmma16(i0, j0 + 16 < n ? j0 + 16 : n, lane,
+               [&](int r, int k) {   // R_new[i0 + r][k], upper
+                 cplx v = {0.0, 0.0};
+                 if (i0 + r < n && i0 + r <= k && k < n) v = A[(i0 + r) * CHB_LD + k];
+                 return v;
+               },
+               [&](int k, int c) {   // R_prev[k][j0 + c], upper, packed
+                 cplx v = {0.0, 0.0};
+                 if (j0 + c < n && k <= j0 + c) v = W[chol_off(n, k, j0 + c)];
+                 return v;
+               },
+               accr, acci);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ta + (lane >> 4) + 4 * q, c = 16 * tb + (lane & 15);
+        if (r < n && c < n) Rg[r * n + c] = r <= c ? cplx{accr[q], acci[q]} : cplx{0.0, 0.0};
+      }
+    }
+  } else if (want_r) {
     for (int e = tid; e < nn; e += CHOL_THREADS) {
       const int i = e / n, k = e - i * n;
-      cplx s = {0.0, 0.0};
-      if (k >= i) {
-        if (acc_r) {
-          for (int l = i; l <= k; ++l) {
-            const cplx a = A[i * CHB_LD + l], b = W[chol_off(n, l, k)];
-            s.re += a.re * b.re - a.im * b.im;
-            s.im += a.re * b.im + a.im * b.re;
-          }
-        } else {
-          s = A[i * CHB_LD + k];
-        }
-      }
-      Rg[e] = s;
+      Rg[e] = k >= i ? A[i * CHB_LD + k] : cplx{0.0, 0.0};
     }
   }
   __syncthreads();   // W is reused below
@@ -1628,31 +1681,42 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
     }
   }
   __syncthreads();
-  // (I2) block columns: T = X[0:j0, 0:j0] R[0:j0, jb], then X[0:j0, jb] = -T X_jj
+  // (I2) block columns: T = X[0:j0, 0:j0] R[0:j0, jb], then X[0:j0, jb] =
+  // -T X_jj, one wave per 16-row tile on the matrix cores
   for (int jb = 1; jb < nb; ++jb) {
     const int j0 = 16 * jb, jw = n - j0 < 16 ? n - j0 : 16;
-    for (int e = tid; e < j0 * 16; e += CHOL_THREADS) {
-      const int i = e >> 4, c = e & 15;
-      cplx s = {0.0, 0.0};
-      if (c < jw)
-        for (int l = i; l < j0; ++l) {
-          const cplx x = A[i * CHB_LD + l], r = A[l * CHB_LD + j0 + c];
-          s.re += x.re * r.re - x.im * r.im;
-          s.im += x.re * r.im + x.im * r.re;
-        }
-      W[e] = s;
+    if (wave < jb) {
+      const int i0 = 16 * wave;
+      d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+      cmma16(i0, j0, lane,
+             [&](int r, int l) { return A[(i0 + r) * CHB_LD + l]; },   // X[i0 + r][l]
+             [&](int l, int c) {   // R[l][j0 + c]
+               cplx v = {0.0, 0.0};
+               if (c < jw) v = A[l * CHB_LD + j0 + c];
+               return v;
+             },
+             accr, acci);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        W[(i0 + (lane >> 4) + 4 * q) * 16 + (lane & 15)] = cplx{accr[q], acci[q]};
     }
     __syncthreads();
-    for (int e = tid; e < j0 * 16; e += CHOL_THREADS) {
-      const int i = e >> 4, c = e & 15;
-      if (c >= jw) continue;
-      cplx s = {0.0, 0.0};
-      for (int l = 0; l <= c; ++l) {
-        const cplx tt = W[i * 16 + l], x = A[(j0 + l) * CHB_LD + j0 + c];
-        s.re += tt.re * x.re - tt.im * x.im;
-        s.im += tt.re * x.im + tt.im * x.re;
+    if (wave < jb) {
+      const int i0 = 16 * wave;
+      d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
+      cmma16(0, 16, lane,
+             [&](int r, int l) { return W[(i0 + r) * 16 + l]; },   // T[i0 + r][l]
+             [&](int l, int c) {   // X_jj[l][c], zero below the diagonal
+               cplx v = {0.0, 0.0};
+               if (l < jw && c < jw) v = A[(j0 + l) * CHB_LD + j0 + c];
+               return v;
+             },
+             accr, acci);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = lane & 15;
+        if (c < jw) A[(i0 + (lane >> 4) + 4 * q) * CHB_LD + j0 + c] = cplx{-accr[q], -acci[q]};
       }
-      A[i * CHB_LD + j0 + c] = cplx{-s.re, -s.im};
     }
     __syncthreads();
   }
