@@ -214,8 +214,13 @@ struct Compiler::Lane {
   // R may be invalid when only Q is wanted (the Cholesky QR then skips it)
   void qr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh = false) {
     if (std::min(m, n) > 256) { err = "QR width above 256"; return; }
-    if (qr_kernel(m, n, Q.valid()) == QRK_CHOL) {
+    const int kq = qr_kernel(m, n, Q.valid());
+    if (kq == QRK_CHOL) {
       cholqr(A, m, n, lda, conjT, Q, R, qh);
+      return;
+    }
+    if (kq == QRK_TALL && m >= n && n <= 2 * CHOLQR_MAXN) {
+      cholqr_panels(A, m, n, lda, conjT, Q, R, qh);
       return;
     }
     if (!R.valid()) R = scratch(std::min(m, n) * n);
@@ -232,7 +237,9 @@ struct Compiler::Lane {
   // matrix Y^H Y as partial products over row chunks (one launch) and their
   // sum, k_chol (Cholesky, R^-1, running R), then Y R^-1 (a GEMM).  The last pass's
   // product is skipped when Q is not wanted, and writes Q^H with qh.
-  void cholqr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh) {
+  void cholqr(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh,
+              int64_t ldq = 0) {
+    if (ldq <= 0) ldq = n;
     int64_t rb = std::max<int64_t>(144, (m + 31) / 32);
     rb = (rb + 15) / 16 * 16;
     const int64_t S = (m + rb - 1) / rb;
@@ -272,11 +279,64 @@ struct Compiler::Lane {
       if (last && qh)   // Q^H = R^-H Y^H (n x m)
         gemm(Rinv, cur, out, n, m, n, n, cld, m, OP_C, cT ? OP_N : OP_C, PREC_FP64);
       else
-        gemm(cur, Rinv, out, m, n, n, cld, n, n, cT ? OP_C : OP_N, OP_N, PREC_FP64);
+        gemm(cur, Rinv, out, m, n, n, cld, n, last ? ldq : n, cT ? OP_C : OP_N, OP_N, PREC_FP64);
       cur = out;
       cld = n;
       cT = 0;
     }
+  }
+  // Strided copy: dst (contiguous, shape dims) <- src at element offsets
+  // sum_k idx_k * strides[k], conjugated with conj.
+  void gather(Ref src, Ref dst, const std::vector<int64_t>& dims,
+              const std::vector<int64_t>& strides, int conj) {
+    Op op;
+    op.type = OPK_PERM;
+    op.a = src; op.b = dst;
+    op.i[0] = int64_t(dims.size());
+    op.i[1] = conj;
+    for (size_t k = 0; k < dims.size(); ++k) { op.i[2 + k] = dims[k]; op.i[18 + k] = strides[k]; }
+    push(op);
+  }
+  // Tall QR with CHOLQR_MAXN < n <= 2 CHOLQR_MAXN: two column panels, each
+  // factorised by Cholesky QR; the second panel is projected off the first
+  // panel's Q twice (block classical Gram-Schmidt with reorthogonalisation)
+  // before its factorisation.  R = [[R11, R12], [0, R22]] with R12 the sum
+  // of the two projections' coefficients; diag(R) stays real non-negative.
+  void cholqr_panels(Ref A, int64_t m, int64_t n, int64_t lda, int conjT, Ref Q, Ref R, bool qh) {
+    const int64_t n1 = (n / 2 + 15) / 16 * 16, n2 = n - n1;
+    const Ref Qn = (Q.valid() && !qh) ? Q : scratch(m * n);
+    const bool want_r = R.valid();
+    Ref R11 = want_r ? scratch(n1 * n1) : Ref(), R22 = want_r ? scratch(n2 * n2) : Ref();
+    // panel 1: columns [0, n1) of op(A)
+    cholqr(A, m, n1, lda, conjT, Qn, R11, false, n);
+    // panel 2 as a dense m x n2 copy, then X -= Q1 (Q1^H X) twice
+    Ref X = scratch(m * n2);
+    if (!conjT)
+      gather(Ref{A.region, A.off + n1}, X, {m, n2}, {lda, 1}, 0);
+    else
+      gather(Ref{A.region, A.off + n1 * lda}, X, {m, n2}, {1, lda}, 1);
+    Ref Sc = scratch(2 * n1 * n2);
+    for (int pass = 0; pass < 2; ++pass) {
+      const Ref Sp{Sc.region, Sc.off + pass * n1 * n2};
+      gemm(Qn, X, Sp, n1, n2, m, n, n2, n2, OP_C, OP_N, PREC_FP64);
+      gemm(Qn, Sp, X, m, n2, n1, n, n2, n2, OP_N, OP_N, PREC_FP64, 0, -1.0, 0.0, 1.0, 0.0);
+    }
+    const Ref Q2{Qn.region, Qn.off + n1};
+    cholqr(X, m, n2, n2, 0, Q2, R22, false, n);
+    if (want_r) {
+      Ref R12 = scratch(n1 * n2);
+      Op sum;
+      sum.type = OPK_SUM;
+      sum.a = Sc; sum.c = R12;
+      sum.i[0] = 2; sum.i[1] = n1; sum.i[2] = n2; sum.i[3] = n2;
+      sum.x[0] = 1.0; sum.x[1] = 0.0;
+      push(sum);
+      pad(R11, R, int(n1), 1, int(n1), int(n), int(n), 0, 0, 0);
+      pad(R12, R, int(n1), 1, int(n2), int(n), int(n), 0, int(n1), 1);
+      pad(R22, R, int(n2), 1, int(n2), int(n), int(n), int(n1), int(n1), 1);
+    }
+    if (Q.valid() && qh)   // Q^H (n x m) from Qn (m x n)
+      gather(Qn, Q, {n, m}, {1, n}, 1);
   }
   // leading `keep` left singular vectors U (rows x keep) and values of the
   // rows x cols matrix A (element (i, c) at A[i*lda + c], conj(A[c*lda + i])
