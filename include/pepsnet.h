@@ -175,6 +175,21 @@ int32_t blockbp_expect(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids, in
                        const double* ops, double* out, double* rho_out, double* energy,
                        int32_t* n_bonds_out);
 
+/* Two-site measures of the density matrices the last blockbp_expect call
+ * computed: the negativity of rho_ij with the partial transpose on the second
+ * site (Eq. res:negativity) and, when sigma is given, the fidelity
+ * F(rho_ij, sigma_k) (Eq. metrics:fidelity).  Both matrices are normalised to
+ * unit trace and taken Hermitian; eigenvalues below zero (rounding) count as
+ * zero under the square roots, so F loses accuracy like sqrt(eps) when a
+ * matrix is rank-deficient.  bond_ids: n_bonds ids of the default bond table
+ * (NULL: all, n_bonds = their number); every listed bond's rho must come
+ * from a blockbp_expect call made since the last sweep or site/message
+ * replacement, else BBP_EINVAL.  sigma: NULL or n_bonds 4x4 complex matrices,
+ * row-major in the (p_i p_j) basis; negativity / fidelity: n_bonds doubles
+ * each (may be NULL; fidelity needs sigma).  Computed on the device. */
+int32_t blockbp_rho_measures(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids,
+                             const double* sigma, double* negativity, double* fidelity);
+
 /* Number of bonds in the bond table and their site pairs (2 ints per bond). */
 int32_t pepsnet_bonds(pepsnet_t h, int32_t* pairs, int32_t cap, int32_t* n);
 

@@ -112,6 +112,45 @@ def expect_op(rho, op):
     return complex(np.trace(rho @ op) / np.trace(rho))
 
 
+def _unit_hermitian(rho):
+    """rho / Tr rho, Hermitian part (a contracted rho carries rounding in
+    its anti-Hermitian part)."""
+    r = rho / np.trace(rho)
+    return 0.5 * (r + r.conj().T)
+
+
+def _psd_sqrt(X):
+    """Principal square root of a Hermitian positive semi-definite matrix
+    from its eigendecomposition; eigenvalues below zero (rounding) count as
+    zero."""
+    w, V = np.linalg.eigh(X)
+    return (V * np.sqrt(np.clip(w, 0.0, None))) @ V.conj().T
+
+
+def partial_transpose_b(rho, d=2):
+    """rho^{T_B} of a two-site matrix indexed [(p_i p_j), (p_i' p_j')]:
+    the second site's indices exchanged."""
+    return rho.reshape(d, d, d, d).transpose(0, 3, 2, 1).reshape(d * d, d * d)
+
+
+def negativity(rho, d=2):
+    """Eq. res:negativity: (||rho^{T_B}||_1 - 1) / 2 for rho normalised to
+    unit trace, the trace norm being the sum of the absolute eigenvalues of
+    the (Hermitian) partial transpose."""
+    w = np.linalg.eigvalsh(partial_transpose_b(_unit_hermitian(rho), d))
+    return float((np.sum(np.abs(w)) - 1.0) / 2.0)
+
+
+def fidelity(rho, sigma):
+    """Eq. metrics:fidelity: (Tr sqrt(sqrt(rho) sigma sqrt(rho)))^2 for rho
+    and sigma normalised to unit trace."""
+    r, s = _unit_hermitian(rho), _unit_hermitian(sigma)
+    sr = _psd_sqrt(r)
+    M = sr @ s @ sr
+    w = np.linalg.eigvalsh(0.5 * (M + M.conj().T))
+    return float(np.sum(np.sqrt(np.clip(w, 0.0, None))) ** 2)
+
+
 def rho_from_carry(R, order, i, j, d=2):
     """R over the carried pairs listed in ``order`` (fused p*d + p' each) ->
     rho[(p_i p_j), (p_i' p_j')]."""

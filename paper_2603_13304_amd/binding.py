@@ -61,6 +61,7 @@ def load_library():
         "blockbp_sweep_noalloc": (i32, [vp, i32, dbl, P(i32), P(dbl)]),
         "blockbp_expect": (i32, [vp, i32, P(i32), i32, P(dbl), P(dbl), P(dbl), P(dbl), P(i32)]),
         "pepsnet_bonds": (i32, [vp, P(i32), i32, P(i32)]),
+        "blockbp_rho_measures": (i32, [vp, i32, P(i32), P(dbl), P(dbl), P(dbl)]),
         "pepsnet_get_messages": (i32, [vp, P(dbl), i64, P(i64)]),
         "pepsnet_set_messages": (i32, [vp, P(dbl), i64]),
         "pepsnet_message_shape": (i32, [vp, i32, i32, P(i32), P(i32), P(i32), P(i32)]),
@@ -175,6 +176,23 @@ class PepsNet:
         rc = _check(self.lib.blockbp_sweep_noalloc(self.h, max_sweeps, tol, C.byref(done),
                                                    C.byref(err)))
         return done.value, err.value, rc
+
+    def rho_measures(self, bond_ids=None, sigma=None):
+        """(negativity, fidelity or None) per bond of the last expectation
+        (Eq. res:negativity, Eq. metrics:fidelity against ``sigma``)."""
+        n = C.c_int32(0)
+        _check(self.lib.pepsnet_bonds(self.h, None, 0, C.byref(n)))
+        ids = None if bond_ids is None else np.ascontiguousarray(bond_ids, np.int32)
+        nb = n.value if ids is None else ids.size
+        sg = None
+        if sigma is not None:
+            sg = np.ascontiguousarray(np.asarray(sigma, np.complex128).reshape(nb, 4, 4))
+        neg, fid = np.zeros(nb), np.zeros(nb)
+        _check(self.lib.blockbp_rho_measures(
+            self.h, nb, None if ids is None else ids.ctypes.data_as(C.POINTER(C.c_int32)),
+            None if sg is None else _dptr(sg.view(np.float64)), _dptr(neg),
+            None if sg is None else _dptr(fid)))
+        return neg, (fid if sg is not None else None)
 
     def blockbp_expect(self, bond_ids=None, ops=None):
         """(rho [n, 4, 4], values, energy).  values: <S.S> per bond (real)

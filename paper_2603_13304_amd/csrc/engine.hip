@@ -117,6 +117,12 @@ struct pepsnet_s {
   // their values per bond; the default bond selection (identity)
   cplx* ops_dev = nullptr;
   cplx* ops_out = nullptr;
+  // rho measures (blockbp_rho_measures): per bond, the (sweeps_total, edits)
+  // at which its rho was last computed; edits counts site and message
+  // replacements; device staging of bond ids, sigma and the results
+  std::vector<std::pair<int64_t, int64_t>> rho_stamp;
+  int64_t edits = 0;
+  char* meas_dev = nullptr;
   const int32_t* sel_default = nullptr;
   // plans of bond subsets: the default plan's lanes of the chosen bonds
   // (their regions and rho slots are those of the default plan)
@@ -773,6 +779,7 @@ int32_t upload_sites(pepsnet_s* h, const double* sites, int64_t len) {
                         hipMemcpyHostToDevice, h->stream));
   int32_t rc = run_compiled(h, &h->prep, false);
   if (rc) return rc;
+  h->edits += 1;
   PN_HIP(hipStreamSynchronize(h->stream));
   return BBP_OK;
 }
@@ -788,6 +795,7 @@ int32_t reset_messages(pepsnet_s* h) {
       (void)P;
     }
   h->parity = 0;
+  h->edits += 1;
   PN_HIP(hipMemcpyAsync(h->arena + h->region_base[RG_MSG0], buf.data(), buf.size() * sizeof(double),
                         hipMemcpyHostToDevice, h->stream));
   PN_HIP(hipStreamSynchronize(h->stream));
@@ -1389,7 +1397,9 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   if (hipMalloc(&h->rho_mat, size_t(std::max(nb, 1)) * 16 * sizeof(cplx)) != hipSuccess ||
       hipMalloc(&h->ss_dev, size_t(std::max(nb, 1)) * sizeof(double)) != hipSuccess ||
       hipMalloc(&h->ops_dev, size_t(kMaxOps) * 16 * sizeof(cplx)) != hipSuccess ||
-      hipMalloc(&h->ops_out, size_t(std::max(nb, 1)) * kMaxOps * sizeof(cplx)) != hipSuccess)
+      hipMalloc(&h->ops_out, size_t(std::max(nb, 1)) * kMaxOps * sizeof(cplx)) != hipSuccess ||
+      hipMalloc(&h->meas_dev, size_t(std::max(nb, 1)) * (16 * sizeof(cplx) + 2 * sizeof(double) +
+                                                         sizeof(int32_t)) + 512) != hipSuccess)
     return fail(BBP_ENOMEM, "expectation buffers");
   for (int par = 0; par < 2; ++par)
     for (int b = 0; b < nb; ++b)
@@ -1535,6 +1545,56 @@ int32_t blockbp_expect(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids, in
       std::memcpy(rho_out + 32 * int64_t(k), rho.data() + 16 * int64_t(ids[k]), 16 * sizeof(cplx));
   if (energy) *energy = h->P.kind == 1 ? e / 3.0 : e / std::max(nb, 1);
   if (n_bonds_out) *n_bonds_out = ns;
+  h->rho_stamp.resize(nb, {-1, -1});
+  for (int k = 0; k < ns; ++k) h->rho_stamp[ids[k]] = {h->sweeps_total, h->edits};
+  return BBP_OK;
+}
+
+int32_t blockbp_rho_measures(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids,
+                             const double* sigma, double* negativity, double* fidelity) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  const int nb = int(h->bonds.size());
+  std::vector<int32_t> ids;
+  if (bond_ids) {
+    if (n_bonds < 1 || n_bonds > nb) return fail(BBP_EINVAL, "bad number of bonds");
+    for (int b = 0; b < n_bonds; ++b) {
+      if (bond_ids[b] < 0 || bond_ids[b] >= nb) return fail(BBP_EINVAL, "bond id out of range");
+      ids.push_back(bond_ids[b]);
+    }
+  } else {
+    if (n_bonds != nb) return fail(BBP_EINVAL, "n_bonds must be the number of default bonds");
+    for (int b = 0; b < nb; ++b) ids.push_back(b);
+  }
+  if (fidelity && !sigma) return fail(BBP_EINVAL, "fidelity needs sigma");
+  h->rho_stamp.resize(nb, {-1, -1});
+  for (int32_t id : ids)
+    if (h->rho_stamp[id] != std::make_pair(h->sweeps_total, h->edits))
+      return fail(BBP_EINVAL, "no rho of the current state for bond " + std::to_string(id) +
+                                  " (call blockbp_expect first)");
+  const int ns = int(ids.size());
+  // staging: ids, then sigma (256-byte aligned), then the results
+  const size_t off_sg = (size_t(nb) * sizeof(int32_t) + 255) / 256 * 256;
+  int32_t* sel = reinterpret_cast<int32_t*>(h->meas_dev);
+  cplx* sg = reinterpret_cast<cplx*>(h->meas_dev + off_sg);
+  double* res = reinterpret_cast<double*>(h->meas_dev + off_sg + size_t(nb) * 16 * sizeof(cplx));
+  PN_HIP(hipMemcpyAsync(sel, ids.data(), size_t(ns) * sizeof(int32_t), hipMemcpyHostToDevice,
+                        h->stream));
+  if (sigma)
+    PN_HIP(hipMemcpyAsync(sg, sigma, size_t(ns) * 16 * sizeof(cplx), hipMemcpyHostToDevice,
+                          h->stream));
+  hipLaunchKernelGGL(k_rho_measures, dim3((ns + 63) / 64), dim3(64), 0, h->stream,
+                     (const cplx*)h->rho_mat, (const int32_t*)sel, ns,
+                     sigma ? (const cplx*)sg : nullptr, res);
+  PN_HIP(hipGetLastError());
+  std::vector<double> r(2 * size_t(ns));
+  PN_HIP(hipMemcpyAsync(r.data(), res, r.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  PN_HIP(hipStreamSynchronize(h->stream));
+  for (int k = 0; k < ns; ++k) {
+    if (!std::isfinite(r[2 * k]) || (sigma && !std::isfinite(r[2 * k + 1])))
+      return fail(BBP_ENUMERIC, "non-finite rho measure");
+    if (negativity) negativity[k] = r[2 * k];
+    if (fidelity) fidelity[k] = r[2 * k + 1];
+  }
   return BBP_OK;
 }
 
@@ -1606,6 +1666,7 @@ int32_t pepsnet_set_messages(pepsnet_t h, const double* buf, int64_t len) {
   PN_HIP(hipMemcpyAsync(h->arena + h->region_base[h->parity ? RG_MSG1 : RG_MSG0], all.data(),
                         M.size * sizeof(cplx), hipMemcpyHostToDevice, h->stream));
   PN_HIP(hipStreamSynchronize(h->stream));
+  h->edits += 1;
   return BBP_OK;
 }
 
@@ -2121,6 +2182,7 @@ void pepsnet_destroy(pepsnet_t h) {
   if (h->ss_dev) hipFree(h->ss_dev);
   if (h->ops_dev) hipFree(h->ops_dev);
   if (h->ops_out) hipFree(h->ops_out);
+  if (h->meas_dev) hipFree(h->meas_dev);
   if (h->pinned) hipHostFree(h->pinned);
   if (h->blob_fixed) hipHostFree(h->blob_fixed);
   if (h->ev0) hipEventDestroy(h->ev0);

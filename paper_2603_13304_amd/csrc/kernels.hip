@@ -3207,4 +3207,150 @@ __global__ void k_rho_ops(const cplx* __restrict__ rho_mat, const int32_t* __res
   const double den = tr * tr + ti * ti;
   out[t] = cplx{(sr * tr + si * ti) / den, (si * tr - sr * ti) / den};
 }
+
+// ------------------------------------------------- two-site rho measures
+// Eigenvalues (and with V, eigenvectors as columns) of a 4 x 4 Hermitian
+// matrix by cyclic complex Jacobi rotations: for the pair (p, q) with
+// A_pq = |a| e^{i phi}, the rotation G = diag(1, e^{-i phi}) [[c, s], [-s, c]]
+// (on rows/columns p, q) makes G^H A G real symmetric in that pair and zeroes
+// it; sweeps stop when the off-diagonal part is below 1e-30 of the
+// Frobenius norm squared.
+__device__ void herm_eig4(cplx A[4][4], double w[4], cplx V[4][4], bool vecs) {
+  if (vecs)
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) V[i][j] = cplx{i == j ? 1.0 : 0.0, 0.0};
+  double fro = 0.0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) fro += A[i][j].re * A[i][j].re + A[i][j].im * A[i][j].im;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        if (i != j) off += A[i][j].re * A[i][j].re + A[i][j].im * A[i][j].im;
+    if (!(off > 1e-30 * fro)) break;
+    for (int p = 0; p < 3; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        const double ab = sqrt(A[p][q].re * A[p][q].re + A[p][q].im * A[p][q].im);
+        if (!(ab > 0.0)) continue;
+        const cplx e = cplx{A[p][q].re / ab, A[p][q].im / ab};   // e^{i phi}
+        const double tau = (A[q][q].re - A[p][p].re) / (2.0 * ab);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+        // G = [[c, s], [-s conj(e), c conj(e)]] on (p, q): columns A <- A G
+        for (int k = 0; k < 4; ++k) {
+          const cplx ap = A[k][p], aq = A[k][q];
+          // aq * conj(e)
+          const cplx qe = cplx{aq.re * e.re + aq.im * e.im, aq.im * e.re - aq.re * e.im};
+          A[k][p] = cplx{c * ap.re - sn * qe.re, c * ap.im - sn * qe.im};
+          A[k][q] = cplx{sn * ap.re + c * qe.re, sn * ap.im + c * qe.im};
+          if (vecs) {
+            const cplx vp = V[k][p], vq = V[k][q];
+            const cplx ve = cplx{vq.re * e.re + vq.im * e.im, vq.im * e.re - vq.re * e.im};
+            V[k][p] = cplx{c * vp.re - sn * ve.re, c * vp.im - sn * ve.im};
+            V[k][q] = cplx{sn * vp.re + c * ve.re, sn * vp.im + c * ve.im};
+          }
+        }
+        // rows A <- G^H A: row p = c A_p - s e A_q, row q = s A_p + c e A_q
+        for (int k = 0; k < 4; ++k) {
+          const cplx ap = A[p][k], aq = A[q][k];
+          const cplx qe = cplx{aq.re * e.re - aq.im * e.im, aq.im * e.re + aq.re * e.im};
+          A[p][k] = cplx{c * ap.re - sn * qe.re, c * ap.im - sn * qe.im};
+          A[q][k] = cplx{sn * ap.re + c * qe.re, sn * ap.im + c * qe.im};
+        }
+        A[p][q] = cplx{0.0, 0.0};
+        A[q][p] = cplx{0.0, 0.0};
+        A[p][p].im = 0.0;
+        A[q][q].im = 0.0;
+      }
+  }
+  for (int i = 0; i < 4; ++i) w[i] = A[i][i].re;
+}
+
+// rho / Tr rho, Hermitian part, from 16 complex values [(p_i p_j), (p_i' p_j')]
+__device__ void unit_hermitian4(const cplx* r, cplx X[4][4]) {
+  double tr = 0.0, ti = 0.0;
+  for (int a = 0; a < 4; ++a) {
+    tr += r[a * 4 + a].re;
+    ti += r[a * 4 + a].im;
+  }
+  const double den = tr * tr + ti * ti;
+  cplx Y[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c) {
+      const cplx x = r[a * 4 + c];
+      Y[a][c] = cplx{(x.re * tr + x.im * ti) / den, (x.im * tr - x.re * ti) / den};
+    }
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c)
+      X[a][c] = cplx{0.5 * (Y[a][c].re + Y[c][a].re), 0.5 * (Y[a][c].im - Y[c][a].im)};
+}
+
+// Per selected bond b (one thread each): out[2 b] = negativity of
+// rho_mat[sel[b]] (Eq. res:negativity, partial transpose on the second
+// site), out[2 b + 1] = fidelity with sigma[b] (Eq. metrics:fidelity; NaN
+// without sigma).  Both matrices are normalised to unit trace and taken
+// Hermitian; negative eigenvalues (rounding) count as zero under the square
+// roots.
+__global__ void k_rho_measures(const cplx* __restrict__ rho_mat, const int32_t* __restrict__ sel,
+                               int nsel, const cplx* __restrict__ sigma, double* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nsel) return;
+  cplx X[4][4], P[4][4], V[4][4];
+  double w[4];
+  unit_hermitian4(rho_mat + 16 * sel[b], X);
+  // partial transpose on the second site: (a b),(c d) <- (a d),(c b)
+  for (int a = 0; a < 2; ++a)
+    for (int bb = 0; bb < 2; ++bb)
+      for (int c = 0; c < 2; ++c)
+        for (int d = 0; d < 2; ++d) P[a * 2 + bb][c * 2 + d] = X[a * 2 + d][c * 2 + bb];
+  herm_eig4(P, w, V, false);
+  out[2 * b] = 0.5 * (fabs(w[0]) + fabs(w[1]) + fabs(w[2]) + fabs(w[3]) - 1.0);
+  if (!sigma) {
+    out[2 * b + 1] = NAN;
+    return;
+  }
+  // sqrt(rho) = V diag(sqrt(max(w, 0))) V^H
+  herm_eig4(X, w, V, true);
+  cplx S[4][4], Sg[4][4], M[4][4], T[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        const double sq = sqrt(fmax(w[k], 0.0));
+        // V[i][k] sq conj(V[j][k])
+        re += sq * (V[i][k].re * V[j][k].re + V[i][k].im * V[j][k].im);
+        im += sq * (V[i][k].im * V[j][k].re - V[i][k].re * V[j][k].im);
+      }
+      S[i][j] = cplx{re, im};
+    }
+  unit_hermitian4(sigma + 16 * b, Sg);
+  for (int i = 0; i < 4; ++i)   // T = S Sg
+    for (int j = 0; j < 4; ++j) {
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        re += S[i][k].re * Sg[k][j].re - S[i][k].im * Sg[k][j].im;
+        im += S[i][k].re * Sg[k][j].im + S[i][k].im * Sg[k][j].re;
+      }
+      T[i][j] = cplx{re, im};
+    }
+  for (int i = 0; i < 4; ++i)   // M = T S
+    for (int j = 0; j < 4; ++j) {
+      double re = 0.0, im = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        re += T[i][k].re * S[k][j].re - T[i][k].im * S[k][j].im;
+        im += T[i][k].re * S[k][j].im + T[i][k].im * S[k][j].re;
+      }
+      M[i][j] = cplx{re, im};
+    }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j <= i; ++j) {
+      const cplx h = cplx{0.5 * (M[i][j].re + M[j][i].re), 0.5 * (M[i][j].im - M[j][i].im)};
+      M[i][j] = h;
+      M[j][i] = cplx{h.re, -h.im};
+    }
+  herm_eig4(M, w, V, false);
+  const double f = sqrt(fmax(w[0], 0.0)) + sqrt(fmax(w[1], 0.0)) + sqrt(fmax(w[2], 0.0)) +
+                   sqrt(fmax(w[3], 0.0));
+  out[2 * b + 1] = f * f;
+}
 }  // namespace pn
