@@ -51,12 +51,16 @@ PURPOSE_EXPECT = 2
 
 
 class BlockBP:
-    def __init__(self, prob, tensors, chi, chi_env=None, trunc="T1", q=2, p=8, seed=0):
+    def __init__(self, prob, tensors, chi, chi_env=None, trunc="T1", q=2, p=8, seed=0,
+                 damping=0.0, hermitize=False):
         self.prob = prob
         self.tensors = [np.asarray(t, complex) for t in tensors]
         self.chi = chi
         self.chi_env = chi if chi_env is None else chi_env
         self.trunc, self.q, self.p, self.seed = trunc, q, p, seed
+        # Sec. "Additions for numerical stability": learning step with
+        # alpha = 1 - damping, and Hermitised messages (both off by default)
+        self.damping, self.hermitize = float(damping), bool(hermitize)
         self.sweeps_done = 0
         self.sched = {}
         self.msgs = {}
@@ -184,6 +188,17 @@ class BlockBP:
         if max(x.shape[2] for x in A) > self.chi:
             A = bb.compress(A, self.chi)
         legs = self._recv_legs(self._store_key(key))
+        dims = [self._dim(s, l) for (s, l) in legs]
+        if self.hermitize or self.damping > 0.0:
+            # both act on the finished message: unit norm, trace real positive
+            A = bb.fix_phase(A, dims)
+        if self.hermitize:   # Sec. "'Hermitize' MPSs": (A + A^dagger) / 2
+            A = bb.compressed_sum(A, bb.hermitian_conjugate(A, dims), 0.5, 0.5, self.chi)
+        if self.damping > 0.0:
+            # Eq. blockBP:kagome:numerics:learning_step1 with alpha = 1 - damping:
+            # the replacing message is alpha new + (1 - alpha) old
+            old = self.msgs[self._store_key(key)]
+            A = bb.compressed_sum(A, old, 1.0 - self.damping, self.damping, self.chi)
         A = self._pad_to_caps(A, legs)
         # unit norm alone leaves the message's global phase free; round-off
         # in it is amplified by the sweep, so fix the trace real positive

@@ -368,6 +368,57 @@ def mps_dense(A):
     return X.reshape(X.shape[1:-1])
 
 
+def mps_sum(A, B, a=1.0, b=1.0):
+    """a A + b B for two open MPS on the same legs, as the MPS whose bond
+    spaces are the direct sums of theirs (first site [a A_0, b B_0] along its
+    right bond, inner sites block-diagonal, last site stacked along its left
+    bond; Schollwoeck 2011)."""
+    n = len(A)
+    if n == 1:
+        return [a * A[0] + b * B[0]]
+    out = []
+    for j in range(n):
+        x, y = A[j], B[j]
+        lx, P, rx = x.shape
+        ly, _, ry = y.shape
+        if j == 0:
+            z = np.zeros((1, P, rx + ry), complex)
+            z[:, :, :rx] = a * x
+            z[:, :, rx:] = b * y
+        elif j == n - 1:
+            z = np.zeros((lx + ly, P, 1), complex)
+            z[:lx] = x
+            z[lx:] = y
+        else:
+            z = np.zeros((lx + ly, P, rx + ry), complex)
+            z[:lx, :, :rx] = x
+            z[lx:, :, rx:] = y
+        out.append(z)
+    return out
+
+
+def compressed_sum(A, B, a, b, chi):
+    """a A + b B brought to right-canonical form with unit norm and
+    truncated to bond chi by exact SVDs (``compress``)."""
+    S = mps_sum(A, B, a, b)
+    ch = Chain(S, [None] * len(S), [[] for _ in S], center=0)
+    right_canonical(ch)
+    if max(x.shape[2] for x in ch.A) > chi:
+        return compress(ch.A, chi)
+    return ch.A
+
+
+def hermitian_conjugate(A, dims):
+    """A^dagger of a message read as an operator: every site's double leg
+    (ket, bra), of dimension D^2 with D = dims[j], has its two indices
+    exchanged, and every tensor is conjugated."""
+    out = []
+    for x, D in zip(A, dims):
+        l, P, r = x.shape
+        out.append(x.reshape(l, D, D, r).transpose(0, 2, 1, 3).conj().reshape(l, P, r))
+    return out
+
+
 def diff_norm(A, B):
     """||A - B||_F of two MPS on the same legs, from the direct-sum MPS and a
     left-to-right QR sweep (accurate to rounding of ||A||, ||B||)."""
