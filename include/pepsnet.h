@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define PEPSNET_ABI_VERSION 3
+#define PEPSNET_ABI_VERSION 4
 
 typedef struct pepsnet_s* pepsnet_t;
 
@@ -87,7 +87,19 @@ typedef struct {
                              * 0 the cheaper by the plan's cost model, 1 merge
                              * the in-leg run first, 2 absorb the ket tensor
                              * site by site along the run */
-  int32_t reserved;         /* 0 */
+  int32_t hermitize;        /* 1: every new message A is replaced by
+                             * (A + A^dagger) / 2, A^dagger exchanging the ket
+                             * and bra index of each double leg and
+                             * conjugating (Sec. "'Hermitize' MPSs"); 0: off */
+  double damping;           /* 1 - alpha of the learning step (Eq.
+                             * blockBP:kagome:numerics:learning_step1): the
+                             * stored message becomes (1 - damping) new +
+                             * damping old; in [0, 1), 0: the new message
+                             * alone.  With hermitize or damping on, each MPS
+                             * sum is brought to right-canonical form with
+                             * unit norm and compressed to chi by exact SVDs,
+                             * so chi must be at most 72 (bonds of the sum up
+                             * to 2 chi), else BBP_EINVAL */
 } pepsnet_desc;
 
 /* Build the problem the thesis states for BlockBP (the lattice, its blocks

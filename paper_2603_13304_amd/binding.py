@@ -17,7 +17,7 @@ BBP_EINVAL, BBP_ENOMEM, BBP_EDEVICE = -1, -2, -3
 NOALLOC_MAX_BYTES = 128 << 20   # PEPSNET_NOALLOC_MAX_BYTES
 BBP_FP64, BBP_FP32, BBP_BF16X3 = 0, 1, 2
 BBP_SVD_FULL, BBP_SVD_RAND = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
@@ -36,7 +36,8 @@ class Desc(C.Structure):
                 ("chi", C.c_int32), ("chi_env", C.c_int32), ("precision", C.c_int32),
                 ("trunc", C.c_int32), ("rsvd_q", C.c_int32), ("rsvd_p", C.c_int32),
                 ("seed", C.c_uint64), ("stream", C.c_void_p), ("hbm_budget_bytes", C.c_int64),
-                ("swallow_order", C.c_int32), ("reserved", C.c_int32)]
+                ("swallow_order", C.c_int32), ("hermitize", C.c_int32),
+                ("damping", C.c_double)]
 
 
 def library_path():
@@ -107,11 +108,11 @@ def _check(rc):
 
 def make_desc(lattice, D, chi, Lx=0, Ly=0, bLx=0, bLy=0, hex_N=0, chi_env=None,
               precision=BBP_FP64, trunc=BBP_SVD_FULL, q=2, p=8, seed=0, stream=None, d=2,
-              hbm_budget_bytes=0, swallow_order=0):
+              hbm_budget_bytes=0, swallow_order=0, hermitize=False, damping=0.0):
     return Desc(ABI_VERSION, lattice, Lx, Ly, bLx, bLy, hex_N, d, D, chi,
                 chi if chi_env is None else chi_env, precision, trunc, q, p, seed,
                 stream if stream is None else C.c_void_p(stream), int(hbm_budget_bytes),
-                int(swallow_order), 0)
+                int(swallow_order), int(bool(hermitize)), float(damping))
 
 
 def _dptr(a):

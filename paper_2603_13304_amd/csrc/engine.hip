@@ -762,6 +762,10 @@ int32_t check_desc(const pepsnet_desc* d) {
     return fail(BBP_EINVAL, "chi_env must equal chi, or be 0 (exact contraction of the block)");
   if (d->hbm_budget_bytes < 0) return fail(BBP_EINVAL, "negative HBM budget");
   if (d->swallow_order < 0 || d->swallow_order > 2) return fail(BBP_EINVAL, "bad swallow order");
+  if (d->hermitize != 0 && d->hermitize != 1) return fail(BBP_EINVAL, "hermitize must be 0 or 1");
+  if (!(d->damping >= 0.0 && d->damping < 1.0)) return fail(BBP_EINVAL, "damping must be in [0, 1)");
+  if ((d->hermitize || d->damping > 0.0) && d->chi > 72)
+    return fail(BBP_EINVAL, "hermitize and damping need chi <= 72 (exact SVDs of 2 chi columns)");
   if (d->precision < 0 || d->precision > 2) return fail(BBP_EINVAL, "bad precision");
   if (d->trunc < 0 || d->trunc > 1) return fail(BBP_EINVAL, "bad truncation mode");
   if (d->rsvd_q < 0 || d->rsvd_q > 8 || d->rsvd_p < 0 || d->rsvd_p > 64)
@@ -1320,6 +1324,8 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
   h->opt.d = desc->d;
   h->opt.D = desc->D;
   h->opt.order = desc->swallow_order;
+  h->opt.hermitize = desc->hermitize;
+  h->opt.damping = desc->damping;
   h->comp.reset(new Compiler(h->P, h->opt));
   if (!h->comp->error.empty()) return fail(BBP_EGEOM, h->comp->error);
   Plan sp[2], ep[2];

@@ -886,6 +886,38 @@ struct Compiler::Lane {
     center = n - 1;
     right_canonical(ch, center);
   }
+
+  // a A + b B for two open MPS on the same legs (Sec. "BlockBP Learning-step":
+  // MPS addition after Schollwoeck 2011): the bond spaces are the direct sums of
+  // the two, with the first site [a A, b B] along its right bond, inner
+  // sites block diagonal and the last site stacked along its left bond.
+  // The sum is brought to right-canonical form with unit norm and, where a
+  // bond exceeds chi, compressed to chi by exact truncated SVDs.
+  std::vector<CSite> compressed_sum(const std::vector<CSite>& A, const std::vector<CSite>& B,
+                                    double a, double b, int& center) {
+    const int n = int(A.size());
+    std::vector<CSite> S(n);
+    for (int j = 0; j < n; ++j) {
+      const CSite& x = A[j];
+      const CSite& y = B[j];
+      CSite z = x;
+      z.l = (j == 0) ? 1 : x.l + y.l;
+      z.r = (j == n - 1) ? 1 : x.r + y.r;
+      z.buf = chain_alloc(int64_t(z.l) * z.P * z.r);
+      const double sa = (j == 0) ? a : 1.0, sb = (j == 0) ? b : 1.0;
+      const int offl = (j == 0) ? 0 : x.l, offr = (j == n - 1) ? 0 : x.r;
+      pad(x.buf, z.buf, x.l, x.P, x.r, z.l, z.r, 0, 0, 0, sa);
+      // one site: both terms land on the same elements, so add
+      pad(y.buf, z.buf, y.l, y.P, y.r, z.l, z.r, offl, offr, n == 1 ? 2 : 1, sb);
+      S[j] = z;
+    }
+    center = 0;
+    right_canonical(S, center);
+    bool over = false;
+    for (const CSite& x : S) over = over || x.r > C->opt.chi;
+    if (over) compress(S, center);
+    return S;
+  }
 };
 
 // ------------------------------------------------------------- compiler
@@ -1246,6 +1278,36 @@ bool Compiler::build_sweep(int parity, Plan* out) {
       }
     }
     int slot = P.stored_slot_of_update(m);
+    if (opt.hermitize || opt.damping > 0.0) {
+      // both act on the finished message: unit norm, trace real and positive
+      L.at(1, 6, 0);
+      L.phase_fix(ch);
+      if (opt.hermitize) {
+        // Sec. "'Hermitize' MPSs": each double leg unfused to (ket, bra),
+        // the two exchanged and conjugated, then (A + A^dagger) / 2
+        L.at(1, 7, 0);
+        std::vector<CSite> hc = ch;
+        for (size_t j = 0; j < hc.size(); ++j) {
+          CSite& x = hc[j];
+          x.buf = L.chain_alloc(int64_t(x.l) * x.P * x.r);
+          L.perm(ch[j].buf, x.buf, {x.l, x.D, x.D, x.r}, {0, 2, 1, 3}, 1);
+        }
+        ch = L.compressed_sum(ch, hc, 0.5, 0.5, center);
+      }
+      if (opt.damping > 0.0) {
+        // Eq. blockBP:kagome:numerics:learning_step1 with alpha = 1 - damping:
+        // alpha new + (1 - alpha) old, the old message as stored (caps)
+        L.at(1, 8, 0);
+        std::vector<CSite> old = ch;
+        for (size_t j = 0; j < old.size(); ++j) {
+          old[j].buf = Ref{rin, msg.off[slot][j]};
+          old[j].l = msg.bl[slot][j];
+          old[j].r = msg.br[slot][j];
+        }
+        ch = L.compressed_sum(ch, old, 1.0 - opt.damping, opt.damping, center);
+      }
+      if (!L.err.empty()) { error = L.err; return false; }
+    }
     // pad into the stored message (caps), fix the phase, then the distance
     L.at(1, 2, 0);
     std::vector<CSite> stored;

@@ -78,6 +78,8 @@ struct PlanOptions {
   int d = 2;
   int D = 2;
   int order = 0;       // swallow order: 0 cost model, 1 merged run, 2 progressive
+  int hermitize = 0;   // replace each new message by (A + A^dagger) / 2
+  double damping = 0;  // 1 - alpha of the learning step (0: the new message alone)
 };
 
 // message storage layout (per slot: sites with cap shapes)

@@ -18,19 +18,24 @@ def problem(kind, **kw):
                                     Ly=kw["Ly"], bLx=kw["bLx"], bLy=kw["bLy"],
                                     precision=kw.get("prec", 0), trunc=kw.get("trunc", 0),
                                     q=kw.get("q", 2), p=kw.get("p", 8), seed=kw.get("seed", 0),
-                                    chi_env=kw.get("chi_env"), swallow_order=kw.get("order", 0))
+                                    chi_env=kw.get("chi_env"), swallow_order=kw.get("order", 0),
+                                    hermitize=kw.get("hermitize", False),
+                                    damping=kw.get("damping", 0.0))
     else:
         P = geo.HexProblem(kw["N"])
         desc = pn.binding.make_desc(pn.BBP_KAGOME_INF_HEX, D=kw["D"], chi=kw["chi"], hex_N=kw["N"],
                                     precision=kw.get("prec", 0), trunc=kw.get("trunc", 0),
                                     q=kw.get("q", 2), p=kw.get("p", 8), seed=kw.get("seed", 0),
-                                    chi_env=kw.get("chi_env"), swallow_order=kw.get("order", 0))
+                                    chi_env=kw.get("chi_env"), swallow_order=kw.get("order", 0),
+                                    hermitize=kw.get("hermitize", False),
+                                    damping=kw.get("damping", 0.0))
     return P, desc
 
 
-def oracle_for(P, ts, chi, trunc, q, p, seed, chi_env=None):
+def oracle_for(P, ts, chi, trunc, q, p, seed, chi_env=None, hermitize=False, damping=0.0):
     return BlockBP(P, ts, chi=chi, chi_env=chi if chi_env is None else chi_env,
-                   trunc="T2" if trunc else "T1", q=q, p=p, seed=seed)
+                   trunc="T2" if trunc else "T1", q=q, p=p, seed=seed,
+                   hermitize=hermitize, damping=damping)
 
 
 def slot_keys(P):

@@ -148,3 +148,36 @@ def test_hbm_budget_rejects_before_allocating():
         d2 = pn.make_desc(pn.BBP_KAGOME_INF_HEX, D=2, chi=4, hex_N=2, chi_env=bad)
         rc = lib.pepsnet_create(ctypes.byref(d2), None, 0, ctypes.byref(h))
         assert rc == -1
+
+
+def test_stability_options_checked_and_compiled():
+    """The learning-step damping must lie in [0, 1) and hermitize be 0 or 1,
+    and with either on chi is at most 72; valid options compile their plans
+    (the budget check after compilation then fails with BBP_ENOMEM before
+    any device call)."""
+    lib = _lib()
+    h = ctypes.c_void_p()
+    ts = syn.random_unit_cell(2, seed=1)
+    flat = np.concatenate([t.reshape(-1) for t in ts]).view(np.float64)
+    ptr = flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for bad in ({"damping": 1.0}, {"damping": -0.1}, {"damping": float("nan")},
+                {"hermitize": 2}, {"chi": 80, "damping": 0.2}, {"chi": 80, "hermitize": 1}):
+        kw = dict(D=2, chi=4, hex_N=2)
+        kw.update(bad)
+        d = pn.make_desc(pn.BBP_KAGOME_INF_HEX, **kw)
+        if "hermitize" in bad:
+            d.hermitize = bad["hermitize"]
+        rc = lib.pepsnet_create(ctypes.byref(d), ptr, flat.size, ctypes.byref(h))
+        assert rc == -1 and not h.value, bad
+    for kw in (dict(hermitize=True), dict(damping=0.3), dict(hermitize=True, damping=0.5)):
+        d = pn.make_desc(pn.BBP_KAGOME_INF_HEX, D=2, chi=8, hex_N=2, hbm_budget_bytes=1 << 12, **kw)
+        rc = lib.pepsnet_create(ctypes.byref(d), ptr, flat.size, ctypes.byref(h))
+        assert rc == -2 and not h.value, (kw, lib.pepsnet_last_error())
+        assert b"budget" in lib.pepsnet_last_error()
+    ts = syn.finite_patch_tensors(4, 4, 2, seed=1)
+    flat = np.concatenate([t.reshape(-1) for t in ts]).view(np.float64)
+    d = pn.make_desc(pn.BBP_KAGOME_OPEN, D=2, chi=4, Lx=4, Ly=4, bLx=2, bLy=2,
+                     hbm_budget_bytes=1 << 12, hermitize=True, damping=0.25)
+    rc = lib.pepsnet_create(ctypes.byref(d), flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            flat.size, ctypes.byref(h))
+    assert rc == -2 and not h.value, lib.pepsnet_last_error()
