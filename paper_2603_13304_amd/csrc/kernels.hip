@@ -1404,16 +1404,15 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol(const CholDesc* __restric
 
 // k_chol_b: the same step for n <= 80 by 16-wide blocks (far fewer barriers
 // than the column-by-column form).  Full storage in LDS (row stride 80).
-//   Cholesky, per diagonal block k: (1) one wave factors the diagonal block
-//   in registers, lane (r mod 4, c) holding rows r of column c, the pivot
-//   row broadcast by lane shuffles; (2) the block row right of it is solved
-//   with the block's conjugate transpose, one lane per column; (3) the
-//   trailing triangle gets the rank-16 update.
-//   R^-1 in place: every diagonal block inverted by one 16-lane group (back
-//   substitution, one lane per column), then block column j from the
-//   inverted leading block: X[0:j, j] = -(X[0:j, 0:j] R[0:j, j]) X[j, j].
-// The previous running factor is staged packed behind the matrix; the same
-// space holds the inverse's block products.
+// The Cholesky factorisation is carried out as row operations on [G | I]:
+// the operations that turn G into R turn I into R^-H (lower triangular), so
+// R^-1 = (R^-H)^H comes out of the same pass.  R fills the upper triangle,
+// R^-H the strictly lower one, its diagonal (1 / R_jj) a separate array.
+// Per 16-row block: (1) the block row is finished by its 16 pivot steps,
+// one column per lane, the pivot and the multipliers R[j][i] broadcast from
+// the lanes holding the diagonal block (readlane); (2) the rows below get
+// the rank-16 update on the matrix cores, in G's upper part and in R^-H.
+// The previous running factor is staged packed in W.
 constexpr int CHB_N = 80, CHB_LD = 80;
 
 // Complex 16 x 16 tile product on the matrix cores, acc += A B over
@@ -1433,17 +1432,13 @@ __device__ __forceinline__ void cmma16(int kb, int ke, int lane, LA la, LB lb, d
   }
 }
 
-__device__ __forceinline__ cplx shfl_c(cplx v, int src) {
-  return cplx{__shfl(v.re, src), __shfl(v.im, src)};
-}
-
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restrict__ descs) {
   const CholDesc d = descs[blockIdx.x];
   const int n = d.n, tid = threadIdx.x, nn = n * n;
   const int lane = tid & 63, wave = tid >> 6;
   __shared__ cplx A[CHB_N * CHB_LD];
   __shared__ cplx W[CHB_N * (CHB_N + 1) / 2];
-  __shared__ double rd[CHB_N], ird[CHB_N];
+  __shared__ double ird[CHB_N];
   __shared__ double sc[2];
   if (n > CHB_N) return;   // excluded by the executor
   const gptr<const cplx> G = to_global(d.G);
@@ -1503,86 +1498,76 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
   const int nb = (n + 15) / 16;
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = 16 * kb, kw = n - k0 < 16 ? n - k0 : 16, c1 = k0 + kw;
-    // (1) diagonal block, one wave
-    if (wave == 0) {
-      const int c = lane & 15, rg = lane >> 4;
-      cplx a[4];
-      double myr[4], myi[4];
+    // (1) rows k0 .. c1 - 1 of [G | I] by row operations.  Lanes 0-15 of
+    // every working wave hold the diagonal block's columns of G (the pivots
+    // and multipliers, the same in every wave); lanes 16-63 hold the other
+    // columns of the block row: the identity's diagonal block, R^-H left of
+    // it, then G right of it (n columns in all, 48 per wave).
+    const int nwork = (n + 47) / 48;
+    if (wave < nwork) {
+      const int c = lane & 15;
+      int kind = -1, col = 0;   // 0 G diagonal, 1 identity diagonal, 2 R^-H left, 3 G right
+      if (lane < 16) {
+        if (c < kw) { kind = 0; col = k0 + c; }
+      } else {
+        const int q = wave * 48 + lane - 16;
+        if (q < kw) { kind = 1; col = k0 + q; }
+        else if (q < c1) { kind = 2; col = q - kw; }
+        else if (q < n) { kind = 3; col = q; }
+      }
+      cplx a[16];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = rg + 4 * t;
-        a[t] = (r <= c && c < kw) ? A[(k0 + r) * CHB_LD + k0 + c] : cplx{0.0, 0.0};
-        myr[t] = 0.0;
-        myi[t] = 0.0;
+      for (int r = 0; r < 16; ++r) {
+        cplx v = {0.0, 0.0};
+        if (r < kw) {
+          if (kind == 0) {
+            if (r <= c) v = A[(k0 + r) * CHB_LD + col];
+          } else if (kind == 1) {
+            if (r == col - k0) v.re = 1.0;
+          } else if (kind > 1) {
+            v = A[(k0 + r) * CHB_LD + col];
+          }
+        }
+        a[r] = v;
       }
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         if (j < kw) {
-          const int src = (j & 3) * 16;   // lanes holding row j (register j / 4)
-          const cplx gjj = shfl_c(a[j >> 2], src + j);
-          const bool ok = !(gjj.re <= thr);
-          const double r = ok ? sqrt(gjj.re) : 0.0, ir = ok ? 1.0 / r : 0.0;
-          if (lane == 0) {
-            rd[k0 + j] = r;
-            ird[k0 + j] = ir;
-          }
+          const double g = readlane_d(a[j].re, j);   // pivot, diagonal lane j
+          const bool ok = !(g <= thr);
+          const double r = ok ? sqrt(g) : 0.0, ir = ok ? 1.0 / r : 0.0;
+          a[j].re *= ir;
+          a[j].im *= ir;
+          if (lane == j) a[j] = cplx{r, 0.0};   // R's diagonal is the root itself
+          if (tid == 0) ird[k0 + j] = ir;
+          // row i -= conj(R[j][i]) row j, R[j][i] from diagonal lane i
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (rg + 4 * t == j) { myr[t] = r; myi[t] = ir; }
-          const double inv = ok ? 1.0 / gjj.re : 0.0;
-          const cplx gc = shfl_c(a[j >> 2], src + c);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int rr = rg + 4 * t;
-            const cplx gr = shfl_c(a[j >> 2], src + rr);
-            if (ok && rr > j && rr <= c && c < kw) {
-              a[t].re -= (gr.re * gc.re + gr.im * gc.im) * inv;   // conj(g_jr) g_jc / g_jj
-              a[t].im -= (gr.re * gc.im - gr.im * gc.re) * inv;
-            }
+          for (int i = j + 1; i < 16; ++i) {
+            const double rr = readlane_d(a[j].re, i), ri = readlane_d(a[j].im, i);
+            a[i].re -= rr * a[j].re + ri * a[j].im;
+            a[i].im -= rr * a[j].im - ri * a[j].re;
           }
         }
       }
+      // R in the upper triangle, R^-H below it (its diagonal is ird)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int r = rg + 4 * t;
-        if (r <= c && c < kw)
-          A[(k0 + r) * CHB_LD + k0 + c] =
-              r == c ? cplx{myr[t], 0.0} : cplx{a[t].re * myi[t], a[t].im * myi[t]};
+      for (int r = 0; r < 16; ++r) {
+        const bool st = r < kw && ((kind == 0 && wave == 0 && r <= c) ||
+                                   (kind == 1 && r > col - k0) || kind > 1);
+        if (st) A[(k0 + r) * CHB_LD + col] = a[r];
       }
     }
     __syncthreads();
-    // (2) block row right of the diagonal block: R_kk^H X = G, one lane per column
-    for (int cc = tid; cc < n - c1; cc += CHOL_THREADS) {
-      const int c = c1 + cc;
-      cplx x[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        x[i] = cplx{0.0, 0.0};
-        if (i < kw) {
-          cplx s = A[(k0 + i) * CHB_LD + c];
-#pragma unroll
-          for (int l = 0; l < 16; ++l)
-            if (l < i) {
-              const cplx r = A[(k0 + l) * CHB_LD + k0 + i];   // conj(R[l][i]) x[l]
-              s.re -= r.re * x[l].re + r.im * x[l].im;
-              s.im -= r.re * x[l].im - r.im * x[l].re;
-            }
-          const double ir = ird[k0 + i];
-          x[i] = cplx{s.re * ir, s.im * ir};
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-        if (i < kw) A[(k0 + i) * CHB_LD + c] = x[i];
-    }
-    __syncthreads();
-    // (3) trailing triangle: G[i][c] -= sum_l conj(R[l][i]) R[l][c], one
-    // wave per upper 16 x 16 tile on the matrix cores
-    const int t = n - c1, tt = (t + 15) / 16;
-    for (int p = wave; p < tt * tt; p += CHOL_THREADS / 64) {
-      const int ta = p / tt, tb = p - ta * tt;
-      if (ta > tb) continue;
-      const int i0 = c1 + 16 * ta, j0 = c1 + 16 * tb;
+    // (2) rows c1 .. n - 1 of [G | I] -= (block row multipliers) x (block
+    // row): G's upper tiles right of c1 and R^-H's tiles left of c1, one
+    // wave per 16 x 16 tile on the matrix cores
+    const int t = n - c1, tt = (t + 15) / 16, tw = tt + kb + 1;
+    for (int p = wave; p < tt * tw; p += CHOL_THREADS / 64) {
+      const int ta = p / tw, tb = p - ta * tw;
+      const bool gpart = tb < tt;
+      if (gpart && ta > tb) continue;
+      const int i0 = c1 + 16 * ta, j0 = gpart ? c1 + 16 * tb : 16 * (tb - tt);
+      const int jend = gpart ? n : c1;
       d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
       cmma16(0, 16, lane,
              [&](int r, int l) {   // conj(R[k0 + l][i0 + r])
@@ -1593,20 +1578,24 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
                }
                return v;
              },
-             [&](int l, int c) {   // R[k0 + l][j0 + c]
+             [&](int l, int cc) {   // block row, column j0 + cc
+               const int col = j0 + cc;
                cplx v = {0.0, 0.0};
-               if (l < kw && j0 + c < n) v = A[(k0 + l) * CHB_LD + j0 + c];
+               if (l < kw && col < jend) {
+                 if (gpart || col < k0 + l) v = A[(k0 + l) * CHB_LD + col];
+                 else if (col == k0 + l) v.re = ird[k0 + l];
+               }
                return v;
              },
              accr, acci);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = i0 + (lane >> 4) + 4 * q, c = j0 + (lane & 15);
-        if (i < n && c < n && i <= c) {
-          cplx v = A[i * CHB_LD + c];
+        const int i = i0 + (lane >> 4) + 4 * q, col = j0 + (lane & 15);
+        if (i < n && col < jend && (!gpart || i <= col)) {
+          cplx v = A[i * CHB_LD + col];
           v.re -= accr[q];
           v.im -= acci[q];
-          A[i * CHB_LD + c] = v;
+          A[i * CHB_LD + col] = v;
         }
       }
     }
@@ -1647,83 +1636,18 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
       Rg[e] = k >= i ? A[i * CHB_LD + k] : cplx{0.0, 0.0};
     }
   }
-  __syncthreads();   // W is reused below
-  // (I1) diagonal blocks inverted in place, a 16-lane group per block
-  {
-    const int grp = tid >> 4, c = tid & 15;
-    if (grp < nb) {
-      const int k0 = 16 * grp, kw = n - k0 < 16 ? n - k0 : 16;
-      cplx x[16];
-#pragma unroll
-      for (int ii = 15; ii >= 0; --ii) {
-        x[ii] = cplx{0.0, 0.0};
-        if (ii < kw && c < kw && ii <= c) {
-          if (ii == c) {
-            x[ii] = cplx{ird[k0 + c], 0.0};
-          } else {
-            cplx s = {0.0, 0.0};
-#pragma unroll
-            for (int l = 0; l < 16; ++l)
-              if (l > ii && l <= c) {
-                const cplx r = A[(k0 + ii) * CHB_LD + k0 + l];
-                s.re += r.re * x[l].re - r.im * x[l].im;
-                s.im += r.re * x[l].im + r.im * x[l].re;
-              }
-            const double ir = ird[k0 + ii];
-            x[ii] = cplx{-s.re * ir, -s.im * ir};
-          }
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int ii = 0; ii < 16; ++ii)
-        if (ii < kw && c < kw && ii <= c) A[(k0 + ii) * CHB_LD + k0 + c] = x[ii];
-    }
-  }
-  __syncthreads();
-  // (I2) block columns: T = X[0:j0, 0:j0] R[0:j0, jb], then X[0:j0, jb] =
-  // -T X_jj, one wave per 16-row tile on the matrix cores
-  for (int jb = 1; jb < nb; ++jb) {
-    const int j0 = 16 * jb, jw = n - j0 < 16 ? n - j0 : 16;
-    if (wave < jb) {
-      const int i0 = 16 * wave;
-      d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
-      cmma16(i0, j0, lane,
-             [&](int r, int l) { return A[(i0 + r) * CHB_LD + l]; },   // X[i0 + r][l]
-             [&](int l, int c) {   // R[l][j0 + c]
-               cplx v = {0.0, 0.0};
-               if (c < jw) v = A[l * CHB_LD + j0 + c];
-               return v;
-             },
-             accr, acci);
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        W[(i0 + (lane >> 4) + 4 * q) * 16 + (lane & 15)] = cplx{accr[q], acci[q]};
-    }
-    __syncthreads();
-    if (wave < jb) {
-      const int i0 = 16 * wave;
-      d4 accr = {0.0, 0.0, 0.0, 0.0}, acci = {0.0, 0.0, 0.0, 0.0};
-      cmma16(0, 16, lane,
-             [&](int r, int l) { return W[(i0 + r) * 16 + l]; },   // T[i0 + r][l]
-             [&](int l, int c) {   // X_jj[l][c], zero below the diagonal
-               cplx v = {0.0, 0.0};
-               if (l < jw && c < jw) v = A[(j0 + l) * CHB_LD + j0 + c];
-               return v;
-             },
-             accr, acci);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int c = lane & 15;
-        if (c < jw) A[(i0 + (lane >> 4) + 4 * q) * CHB_LD + j0 + c] = cplx{-accr[q], -acci[q]};
-      }
-    }
-    __syncthreads();
-  }
+  // R^-1 = (R^-H)^H
   const gptr<cplx> Xg = to_global(d.Rinv);
   for (int e = tid; e < nn; e += CHOL_THREADS) {
-    const int i = e / n, k = e - i * n;
-    Xg[e] = k >= i ? A[i * CHB_LD + k] : cplx{0.0, 0.0};
+    const int i = e / n, kk = e - i * n;
+    cplx v = {0.0, 0.0};
+    if (kk == i) {
+      v.re = ird[i];
+    } else if (kk > i) {
+      v = A[kk * CHB_LD + i];
+      v.im = -v.im;
+    }
+    Xg[e] = v;
   }
 }
 
