@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--streams", type=int, default=4,
+                    help="streams for the independent message updates of a sweep (1-4)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the fixed GEMM tile rule")
     ap.add_argument("--tile-cache", default=None,
                     help="GEMM tile cache file (shapes found there are not timed again)")
@@ -104,6 +106,7 @@ def make_net(args, precision, ts):
                      q=args.q, p=args.p, seed=7)
     g = pn.PepsNet(desc, ts)
     g.use_graph(not args.no_graph)
+    g.use_streams(args.streams)
     return g
 
 
@@ -564,7 +567,7 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": workload_name(args, args.precision),
-                   "message_updates_per_step": n_msg, "graph": not args.no_graph,
+                   "message_updates_per_step": n_msg, "graph": not args.no_graph, "streams": args.streams,
                    "autotuned_gemm_shapes": n_tuned, "autotune_seconds": round(tune_s, 2)},
         "roofline": roof,
         "mfma": mfma,

@@ -226,6 +226,15 @@ int32_t pepsnet_timing(pepsnet_t h, int32_t reset, double* ms_per_sweep, int64_t
 /* Use a captured HIP graph for sweeps (1) or direct launches (0). */
 int32_t pepsnet_use_graph(pepsnet_t h, int32_t on);
 
+/* Streams a sweep may use, 1 to 4 (default 4).  The message updates of a
+ * sweep are independent (Sec. "The Block Belief-Propagation Algorithm":
+ * every update reads only the previous sweep's messages), so updates whose
+ * kernel sequences differ run on separate streams, forked from and joined
+ * back into the handle's stream; 1 issues every launch on the handle's
+ * stream.  Results are bit-identical either way.  BBP_EINVAL outside
+ * [1, 4]. */
+int32_t pepsnet_use_streams(pepsnet_t h, int32_t n);
+
 /* Algorithmic flop count of one sweep's contraction GEMMs (8 real flops per
  * complex multiply-add) and of all its GEMMs, and the number of launches. */
 int32_t pepsnet_sweep_stats(pepsnet_t h, double* contraction_flops, double* gemm_flops,

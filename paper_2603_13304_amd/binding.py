@@ -70,6 +70,7 @@ def load_library():
         "pepsnet_stream": (vp, [vp]),
         "pepsnet_timing": (i32, [vp, i32, P(dbl), P(i64)]),
         "pepsnet_use_graph": (i32, [vp, i32]),
+        "pepsnet_use_streams": (i32, [vp, i32]),
         "pepsnet_sweep_stats": (i32, [vp, P(dbl), P(dbl), P(i64)]),
         "pepsnet_profile_sweeps": (i32, [vp, i32, P(dbl), P(i64), P(dbl), P(dbl)]),
         "pepsnet_profile_launches": (i32, [vp, P(dbl), i64, P(i64)]),
@@ -274,6 +275,11 @@ class PepsNet:
 
     def use_graph(self, on=True):
         _check(self.lib.pepsnet_use_graph(self.h, int(on)))
+
+    def use_streams(self, n):
+        """Streams a sweep may use (1-4): independent message updates run
+        concurrently; 1 issues every launch on the handle's stream."""
+        _check(self.lib.pepsnet_use_streams(self.h, int(n)))
 
     def memory(self):
         """(resident bytes, workspace bytes)."""

@@ -64,6 +64,7 @@ struct LaunchRec {
   double flops = 0.0;    // algorithmic flops of the launch (8 per complex MAC)
   double bytes = 0.0;    // algorithmic bytes moved (operands read once, results written once)
   int64_t shape[3] = {0, 0, 0};   // GEMM: largest M, N, K of the launch; QR / SVD: rows, cols
+  int group = 0;         // stream group: launches of different groups share no data
 };
 
 struct Compiled {
@@ -74,7 +75,11 @@ struct Compiled {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   double gemm_flops = 0.0, contraction_flops = 0.0;
+  int ngroups = 1;
 };
+
+// Launch groups of a sweep plan run on up to this many streams.
+constexpr int kMaxStreams = 4;
 
 }  // namespace
 
@@ -108,6 +113,11 @@ struct pepsnet_s {
   int parity = 0;
   int64_t sweeps_total = 0;
   bool use_graph = false;
+  // the sweep's lane groups on the handle's stream and aux[0 .. nstreams - 2]
+  // (forked from and joined back into the handle's stream by events)
+  int nstreams = kMaxStreams;
+  hipStream_t aux[kMaxStreams - 1] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kMaxStreams - 1] = {};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double timed_ms = 0.0;
   int64_t timed_sweeps = 0;
@@ -308,13 +318,35 @@ typedef std::vector<std::vector<std::pair<WaveKey, Op>>> LaneList;
 struct OpSource {
   pepsnet_s* h;          // resolves the op's references
   const LaneList* lanes;
+  const std::vector<int>* groups = nullptr;   // stream group per lane (none: all 0)
 };
+
+// Stream groups of a plan whose lanes share no data (the message updates of
+// a sweep): lanes with the same sequence of (wave key, op kind) form a class
+// whose ops merge into shared launches; class c runs in group c mod
+// kMaxStreams.
+std::vector<int> lane_groups(const LaneList& lanes) {
+  std::map<std::vector<std::pair<std::vector<int>, int>>, int> cls;
+  std::vector<int> g(lanes.size(), 0);
+  for (size_t L = 0; L < lanes.size(); ++L) {
+    std::vector<std::pair<std::vector<int>, int>> sig;
+    sig.reserve(lanes[L].size());
+    for (const auto& ko : lanes[L]) sig.push_back({ko.first.k, int(ko.second.type)});
+    auto it = cls.find(sig);
+    if (it == cls.end()) it = cls.emplace(std::move(sig), int(cls.size())).first;
+    g[L] = it->second % kMaxStreams;
+  }
+  return g;
+}
 
 // Bucket the ops of every source by wave key, then by (kind, precision,
 // variant), and emit one launch per bucket with its descriptors in `blob`.
 void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Compiled* out) {
   // (wave key, source, lane, op index)
   std::vector<std::tuple<WaveKey, int, int, int>> all;
+  auto group_of = [&](int S, int L) {
+    return srcs[S].groups ? (*srcs[S].groups)[L] : 0;
+  };
   for (size_t S = 0; S < srcs.size(); ++S) {
     const LaneList& lanes = *srcs[S].lanes;
     for (size_t L = 0; L < lanes.size(); ++L)
@@ -330,18 +362,21 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
     while (j < all.size() && !(std::get<0>(all[i]) < std::get<0>(all[j])) &&
            !(std::get<0>(all[j]) < std::get<0>(all[i])))
       ++j;
-    std::map<std::tuple<int, int, int>, std::vector<std::pair<pepsnet_s*, const Op*>>> buckets;
+    std::map<std::tuple<int, int, int, int>, std::vector<std::pair<pepsnet_s*, const Op*>>> buckets;
     for (size_t t = i; t < j; ++t) {
       const OpSource& src = srcs[std::get<1>(all[t])];
       const Op& op = (*src.lanes)[std::get<2>(all[t])][std::get<3>(all[t])].second;
       int prec = op.type == OPK_GEMM ? int(op.i[8]) : 0;
-      buckets[{op.type, prec, op_variant(src.h, op)}].push_back({src.h, &op});
+      const int grp = group_of(std::get<1>(all[t]), std::get<2>(all[t]));
+      buckets[{grp, op.type, prec, op_variant(src.h, op)}].push_back({src.h, &op});
     }
     for (auto& bk : buckets) {
       LaunchRec rec;
-      rec.type = std::get<0>(bk.first);
-      rec.prec = std::get<1>(bk.first);
-      rec.variant = std::get<2>(bk.first);
+      rec.group = std::get<0>(bk.first);
+      rec.type = std::get<1>(bk.first);
+      rec.prec = std::get<2>(bk.first);
+      rec.variant = std::get<3>(bk.first);
+      out->ngroups = std::max(out->ngroups, rec.group + 1);
       rec.count = int(bk.second.size());
       const auto& ops = bk.second;
       switch (rec.type) {
@@ -706,14 +741,50 @@ hipError_t launch(const char* desc_dev, hipStream_t stream, const LaunchRec& r, 
   return hipGetLastError();
 }
 
-int32_t run_launches(hipStream_t stream, Compiled* c, bool graph) {
+// Streams for the launch groups of a plan: group 0 on `main`, group g > 0 on
+// aux[g - 1], forked from and joined back into `main` by events.
+struct GroupStreams {
+  int n = 1;
+  const hipStream_t* aux = nullptr;
+  hipEvent_t fork = nullptr;
+  const hipEvent_t* join = nullptr;
+};
+
+// Enqueue every launch of c in list order; with gs, group g goes to stream
+// g mod ns (ns = the streams in use, 0 = `main`), so each lane's ops keep
+// their order.
+hipError_t issue(const char* desc_dev, hipStream_t main, const Compiled* c,
+                 const GroupStreams* gs) {
+  const int ns = gs ? std::max(1, std::min(gs->n, c->ngroups)) : 1;
+  hipError_t e = hipSuccess;
+  if (ns > 1) {
+    if ((e = hipEventRecord(gs->fork, main)) != hipSuccess) return e;
+    for (int g = 1; g < ns; ++g)
+      if ((e = hipStreamWaitEvent(gs->aux[g - 1], gs->fork, 0)) != hipSuccess) return e;
+  }
+  for (const LaunchRec& r : c->launches) {
+    const int q = r.group % ns;
+    e = launch(desc_dev, q > 0 ? gs->aux[q - 1] : main, r);
+    if (e != hipSuccess) break;
+  }
+  // join even after a failed launch, so that a capture can end cleanly
+  for (int g = 1; g < ns; ++g) {
+    hipError_t e2 = hipEventRecord(gs->join[g - 1], gs->aux[g - 1]);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(main, gs->join[g - 1], 0);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
+}
+
+int32_t run_launches(hipStream_t stream, Compiled* c, bool graph,
+                     const GroupStreams* gs = nullptr) {
   const char* desc_dev = c->desc;
   if (!desc_dev) return fail(BBP_EDEVICE, "launch list without uploaded descriptors");
   if (graph) {
     if (!c->exec) {
       PN_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-      for (const LaunchRec& r : c->launches) {
-        hipError_t e = launch(desc_dev, stream, r);
+      {
+        hipError_t e = issue(desc_dev, stream, c, gs);
         if (e != hipSuccess) {
           // end the capture (the stream must leave capture mode) and drop
           // the partial graph it returns
@@ -735,15 +806,18 @@ int32_t run_launches(hipStream_t stream, Compiled* c, bool graph) {
     PN_HIP(hipGraphLaunch(c->exec, stream));
     return BBP_OK;
   }
-  for (const LaunchRec& r : c->launches) {
-    hipError_t e = launch(desc_dev, stream, r);
-    if (e != hipSuccess) return fail(BBP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
-  }
+  hipError_t e = issue(desc_dev, stream, c, gs);
+  if (e != hipSuccess) return fail(BBP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   return BBP_OK;
 }
 
 int32_t run_compiled(pepsnet_s* h, Compiled* c, bool allow_graph) {
-  return run_launches(h->stream, c, allow_graph && h->use_graph);
+  GroupStreams gs;
+  gs.n = h->nstreams;
+  gs.aux = h->aux;
+  gs.fork = h->fork_ev;
+  gs.join = h->join_ev;
+  return run_launches(h->stream, c, allow_graph && h->use_graph, h->fork_ev ? &gs : nullptr);
 }
 
 std::string build_problem(const pepsnet_desc* d, Problem* P) {
@@ -866,7 +940,11 @@ int32_t build_launches(pepsnet_s* h) {
   h->desc_host.clear();
   compile_ops({{h, &h->prep_lanes}}, &h->desc_host, &h->prep);
   for (int par = 0; par < 2; ++par) {
-    compile_ops({{h, &h->sweep_lanes[par]}}, &h->desc_host, &h->sweep[par]);
+    // the message updates of a sweep share no data: their lane groups may
+    // run on separate streams (the expectation's lanes pass carried
+    // messages between them, so its plan stays in one group)
+    const std::vector<int> groups = lane_groups(h->sweep_lanes[par]);
+    compile_ops({{h, &h->sweep_lanes[par], &groups}}, &h->desc_host, &h->sweep[par]);
     compile_ops({{h, &h->expect_lanes[par]}}, &h->desc_host, &h->expect[par]);
   }
   const int nb = int(h->bonds.size());
@@ -1372,6 +1450,11 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
     PN_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
     h->own_stream = true;
   }
+  for (int g = 0; g < kMaxStreams - 1; ++g) {
+    PN_HIP(hipStreamCreateWithFlags(&h->aux[g], hipStreamNonBlocking));
+    PN_HIP(hipEventCreateWithFlags(&h->join_ev[g], hipEventDisableTiming));
+  }
+  PN_HIP(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
   PN_HIP(hipGetDevice(&h->device));
   // the no-allocation sweep reports a failure here when it is called
   if (resolve_fixed(h->device) != BBP_OK) g_last_error.clear();
@@ -1689,6 +1772,22 @@ int32_t pepsnet_timing(pepsnet_t h, int32_t reset, double* ms, int64_t* sweeps) 
 int32_t pepsnet_use_graph(pepsnet_t h, int32_t on) {
   if (!h) return fail(BBP_EINVAL, "null handle");
   h->use_graph = on != 0;
+  return BBP_OK;
+}
+
+int32_t pepsnet_use_streams(pepsnet_t h, int32_t n) {
+  if (!h) return fail(BBP_EINVAL, "null handle");
+  if (n < 1 || n > kMaxStreams) return fail(BBP_EINVAL, "stream count must be in [1, 4]");
+  if (n != h->nstreams) {
+    // captured graphs hold the old stream layout
+    for (Compiled* c : {&h->sweep[0], &h->sweep[1]}) {
+      if (c->exec) hipGraphExecDestroy(c->exec);
+      if (c->graph) hipGraphDestroy(c->graph);
+      c->exec = nullptr;
+      c->graph = nullptr;
+    }
+  }
+  h->nstreams = n;
   return BBP_OK;
 }
 
@@ -2193,6 +2292,11 @@ void pepsnet_destroy(pepsnet_t h) {
   if (h->blob_fixed) hipHostFree(h->blob_fixed);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
+  for (int g = 0; g < kMaxStreams - 1; ++g) {
+    if (h->join_ev[g]) hipEventDestroy(h->join_ev[g]);
+    if (h->aux[g]) hipStreamDestroy(h->aux[g]);
+  }
+  if (h->fork_ev) hipEventDestroy(h->fork_ev);
   if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
   delete h;
 }
