@@ -113,11 +113,13 @@ struct pepsnet_s {
   int parity = 0;
   int64_t sweeps_total = 0;
   bool use_graph = false;
-  // the sweep's lane groups on the handle's stream and aux[0 .. nstreams - 2]
-  // (forked from and joined back into the handle's stream by events)
+  // the lane groups of sweeps and expectations on the handle's stream and
+  // the device's shared auxiliary streams (forked from and joined back into
+  // the handle's stream by these events); the *_serial plans merge every
+  // lane into shared launches for one stream
   int nstreams = kMaxStreams;
-  hipStream_t aux[kMaxStreams - 1] = {};
   hipEvent_t fork_ev = nullptr, join_ev[kMaxStreams - 1] = {};
+  Compiled sweep_serial[2], expect_serial[2];
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double timed_ms = 0.0;
   int64_t timed_sweeps = 0;
@@ -321,13 +323,34 @@ struct OpSource {
   const std::vector<int>* groups = nullptr;   // stream group per lane (none: all 0)
 };
 
-// Stream groups of a plan whose lanes share no data (the message updates of
-// a sweep): lanes with the same sequence of (wave key, op kind) form a class
+// Stream groups of a plan whose lanes share no data: the message updates of
+// a sweep (each reads the previous sweep's messages and writes its own
+// message slot) and the bonds of an expectation (each writes its own rho
+// block).  Lanes with the same sequence of (wave key, op kind) form a class
 // whose ops merge into shared launches; class c runs in group c mod
-// kMaxStreams.
+// kMaxStreams.  A plan in which a workspace region is referenced by more
+// than one lane, or a lane references more than one, stays in one group.
 std::vector<int> lane_groups(const LaneList& lanes) {
-  std::map<std::vector<std::pair<std::vector<int>, int>>, int> cls;
   std::vector<int> g(lanes.size(), 0);
+  std::map<int, size_t> owner;
+  for (size_t L = 0; L < lanes.size(); ++L) {
+    int mine = -1;
+    for (const auto& ko : lanes[L]) {
+      const Op& op = ko.second;
+      std::vector<Ref> rs = {op.a, op.b, op.c, op.d};
+      rs.insert(rs.end(), op.refs.begin(), op.refs.end());
+      for (const Ref& r : rs) {
+        if (r.region < RG_LANE0) continue;
+        if (mine >= 0 && r.region != mine) return g;
+        mine = r.region;
+      }
+    }
+    if (mine < 0) continue;
+    auto it = owner.find(mine);
+    if (it != owner.end() && it->second != L) return g;
+    owner[mine] = L;
+  }
+  std::map<std::vector<std::pair<std::vector<int>, int>>, int> cls;
   for (size_t L = 0; L < lanes.size(); ++L) {
     std::vector<std::pair<std::vector<int>, int>> sig;
     sig.reserve(lanes[L].size());
@@ -811,13 +834,43 @@ int32_t run_launches(hipStream_t stream, Compiled* c, bool graph,
   return BBP_OK;
 }
 
+// Auxiliary streams for the extra lane groups, shared by every handle on a
+// device (one stream per handle keeps the handles' own streams spread over
+// the hardware queues), made on first use and kept until the process ends.
+struct AuxStreams {
+  hipStream_t s[kMaxStreams - 1] = {};
+};
+std::mutex g_aux_mu;
+std::map<int, AuxStreams> g_aux;
+
+const hipStream_t* aux_streams(int dev) {
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  auto it = g_aux.find(dev);
+  if (it != g_aux.end()) return it->second.s;
+  AuxStreams a;
+  for (int g = 0; g < kMaxStreams - 1; ++g)
+    if (hipStreamCreateWithFlags(&a.s[g], hipStreamNonBlocking) != hipSuccess) {
+      for (int k = 0; k < g; ++k) (void)hipStreamDestroy(a.s[k]);
+      return nullptr;
+    }
+  return g_aux.emplace(dev, a).first->second.s;
+}
+
+// Run a plan on the handle's stream; a plan with several lane groups (and a
+// handle allowed more than one stream) spreads them over the auxiliary
+// streams too.
 int32_t run_compiled(pepsnet_s* h, Compiled* c, bool allow_graph) {
   GroupStreams gs;
-  gs.n = h->nstreams;
-  gs.aux = h->aux;
-  gs.fork = h->fork_ev;
-  gs.join = h->join_ev;
-  return run_launches(h->stream, c, allow_graph && h->use_graph, h->fork_ev ? &gs : nullptr);
+  const GroupStreams* use = nullptr;
+  if (h->nstreams > 1 && c->ngroups > 1 && h->fork_ev) {
+    gs.aux = aux_streams(h->device);
+    if (!gs.aux) return fail(BBP_EDEVICE, "stream creation failed");
+    gs.n = h->nstreams;
+    gs.fork = h->fork_ev;
+    gs.join = h->join_ev;
+    use = &gs;
+  }
+  return run_launches(h->stream, c, allow_graph && h->use_graph, use);
 }
 
 std::string build_problem(const pepsnet_desc* d, Problem* P) {
@@ -888,7 +941,7 @@ int32_t enqueue_sweep(pepsnet_s* h, hipEvent_t ev) {
   h->pinned[0] = double(h->sweeps_total);
   PN_HIP(hipMemcpyAsync(h->scal + Compiler::kSweepSlot, h->pinned, sizeof(double),
                         hipMemcpyHostToDevice, h->stream));
-  int32_t rc = run_compiled(h, &h->sweep[h->parity], true);
+  int32_t rc = run_compiled(h, &h->sweep_serial[h->parity], true);
   if (rc) return rc;
   PN_HIP(hipMemcpyAsync(h->pinned + 1, h->scal + h->comp->err_slot(0), nm * sizeof(double),
                         hipMemcpyDeviceToHost, h->stream));
@@ -905,7 +958,7 @@ int32_t finish_sweep(pepsnet_s* h, double* err) {
 
 int32_t enqueue_expect(pepsnet_s* h, hipEvent_t ev) {
   const int nm = int(h->P.msg_keys.size()), nb = int(h->bonds.size());
-  int32_t rc = run_compiled(h, &h->expect[h->parity], false);
+  int32_t rc = run_compiled(h, &h->expect_serial[h->parity], false);
   if (rc) return rc;
   hipLaunchKernelGGL(k_rho_ss, dim3((nb + 63) / 64), dim3(64), 0, h->stream,
                      h->rho_descs[h->parity], nb);
@@ -932,7 +985,9 @@ int32_t finish_expect(pepsnet_s* h, std::vector<double>* ss, double* energy) {
 // (Re)compile every launch list against the current arena and workspace
 // addresses and upload the descriptors; drops captured graphs.
 int32_t build_launches(pepsnet_s* h) {
-  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep}) {
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep,
+                      &h->sweep_serial[0], &h->sweep_serial[1], &h->expect_serial[0],
+                      &h->expect_serial[1]}) {
     if (c->exec) hipGraphExecDestroy(c->exec);
     if (c->graph) hipGraphDestroy(c->graph);
     *c = Compiled();
@@ -940,12 +995,14 @@ int32_t build_launches(pepsnet_s* h) {
   h->desc_host.clear();
   compile_ops({{h, &h->prep_lanes}}, &h->desc_host, &h->prep);
   for (int par = 0; par < 2; ++par) {
-    // the message updates of a sweep share no data: their lane groups may
-    // run on separate streams (the expectation's lanes pass carried
-    // messages between them, so its plan stays in one group)
-    const std::vector<int> groups = lane_groups(h->sweep_lanes[par]);
-    compile_ops({{h, &h->sweep_lanes[par], &groups}}, &h->desc_host, &h->sweep[par]);
-    compile_ops({{h, &h->expect_lanes[par]}}, &h->desc_host, &h->expect[par]);
+    // the message updates of a sweep, and the bonds of an expectation,
+    // share no data: their lane groups may run on separate streams
+    const std::vector<int> sg = lane_groups(h->sweep_lanes[par]);
+    compile_ops({{h, &h->sweep_lanes[par], &sg}}, &h->desc_host, &h->sweep[par]);
+    const std::vector<int> eg = lane_groups(h->expect_lanes[par]);
+    compile_ops({{h, &h->expect_lanes[par], &eg}}, &h->desc_host, &h->expect[par]);
+    compile_ops({{h, &h->sweep_lanes[par]}}, &h->desc_host, &h->sweep_serial[par]);
+    compile_ops({{h, &h->expect_lanes[par]}}, &h->desc_host, &h->expect_serial[par]);
   }
   const int nb = int(h->bonds.size());
   size_t rho_off[2];
@@ -976,7 +1033,9 @@ int32_t build_launches(pepsnet_s* h) {
   PN_HIP(hipMemcpyAsync(h->desc_dev, h->desc_host.data(), h->desc_host.size(),
                         hipMemcpyHostToDevice, h->stream));
   h->desc_work = h->work;
-  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep})
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep,
+                      &h->sweep_serial[0], &h->sweep_serial[1], &h->expect_serial[0],
+                      &h->expect_serial[1]})
     c->desc = h->desc_dev;
   for (int par = 0; par < 2; ++par)
     h->rho_descs[par] = reinterpret_cast<RhoDesc*>(h->desc_dev + rho_off[par]);
@@ -1014,7 +1073,8 @@ int32_t subset_plan(pepsnet_s* h, const std::vector<int>& ids, pepsnet_s::Subset
   for (int par = 0; par < 2; ++par) {
     LaneList lanes;
     for (int b : ids) lanes.push_back(h->expect_lanes[par][b]);
-    compile_ops({{h, &lanes}}, &S.blob, &S.plan[par]);
+    const std::vector<int> eg = lane_groups(lanes);
+    compile_ops({{h, &lanes, &eg}}, &S.blob, &S.plan[par]);
     std::vector<RhoDesc> rd;
     for (int b : ids) {
       RhoDesc r;
@@ -1450,10 +1510,8 @@ int32_t pepsnet_create(const pepsnet_desc* desc, const double* sites, int64_t si
     PN_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
     h->own_stream = true;
   }
-  for (int g = 0; g < kMaxStreams - 1; ++g) {
-    PN_HIP(hipStreamCreateWithFlags(&h->aux[g], hipStreamNonBlocking));
+  for (int g = 0; g < kMaxStreams - 1; ++g)
     PN_HIP(hipEventCreateWithFlags(&h->join_ev[g], hipEventDisableTiming));
-  }
   PN_HIP(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
   PN_HIP(hipGetDevice(&h->device));
   // the no-allocation sweep reports a failure here when it is called
@@ -1532,7 +1590,8 @@ int32_t blockbp_sweep(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* swee
                       double* max_err) {
   if (!h || max_sweeps < 0) return fail(BBP_EINVAL, "bad arguments");
   if (int32_t rc = need_work(h)) return rc;
-  return sweep_until(h, h->sweep, true, max_sweeps, tol, sweeps_done, max_err);
+  return sweep_until(h, h->nstreams > 1 ? h->sweep : h->sweep_serial, true, max_sweeps, tol,
+                     sweeps_done, max_err);
 }
 
 int32_t blockbp_sweep_noalloc(pepsnet_t h, int32_t max_sweeps, double tol, int32_t* sweeps_done,
@@ -1580,7 +1639,7 @@ int32_t blockbp_expect(pepsnet_t h, int32_t n_bonds, const int32_t* bond_ids, in
   }
   if (ops && (n_ops < 1 || n_ops > kMaxOps)) return fail(BBP_EINVAL, "n_ops must be in [1, 64]");
   const int ns = int(ids.size());
-  Compiled* plan = &h->expect[h->parity];
+  Compiled* plan = h->nstreams > 1 ? &h->expect[h->parity] : &h->expect_serial[h->parity];
   const RhoDesc* rdesc = h->rho_descs[h->parity];
   const int32_t* sel = h->sel_default;
   if (bond_ids) {
@@ -2020,7 +2079,8 @@ int32_t pepsnet_release_workspace(pepsnet_t h) {
   if (!h) return fail(BBP_EINVAL, "null handle");
   if (!h->work) return BBP_OK;
   PN_HIP(hipStreamSynchronize(h->stream));
-  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1]}) {
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1],
+                      &h->sweep_serial[0], &h->sweep_serial[1]}) {
     if (c->exec) hipGraphExecDestroy(c->exec);
     if (c->graph) hipGraphDestroy(c->graph);
     c->exec = nullptr;
@@ -2274,7 +2334,8 @@ void bbp_server_destroy(bbp_server_t S) {
 void pepsnet_destroy(pepsnet_t h) {
   if (!h) return;
   if (h->stream) hipStreamSynchronize(h->stream);
-  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep}) {
+  for (Compiled* c : {&h->sweep[0], &h->sweep[1], &h->expect[0], &h->expect[1], &h->prep,
+                      &h->sweep_serial[0], &h->sweep_serial[1]}) {
     if (c->exec) hipGraphExecDestroy(c->exec);
     if (c->graph) hipGraphDestroy(c->graph);
   }
@@ -2292,10 +2353,8 @@ void pepsnet_destroy(pepsnet_t h) {
   if (h->blob_fixed) hipHostFree(h->blob_fixed);
   if (h->ev0) hipEventDestroy(h->ev0);
   if (h->ev1) hipEventDestroy(h->ev1);
-  for (int g = 0; g < kMaxStreams - 1; ++g) {
+  for (int g = 0; g < kMaxStreams - 1; ++g)
     if (h->join_ev[g]) hipEventDestroy(h->join_ev[g]);
-    if (h->aux[g]) hipStreamDestroy(h->aux[g]);
-  }
   if (h->fork_ev) hipEventDestroy(h->fork_ev);
   if (h->own_stream && h->stream) hipStreamDestroy(h->stream);
   delete h;

@@ -1,6 +1,7 @@
 """Sweeps with the independent message updates on several streams (forked
 from and joined into the handle's stream, direct launches and captured
-graphs) give bit-identical messages and distances to every launch on one
+graphs), and expectations with the bonds on several streams, give
+bit-identical messages, distances and rho_ij to every launch on one
 stream."""
 import numpy as np
 import pytest
@@ -23,7 +24,8 @@ def _sweeps(kind, ts, streams, graph, sweeps=3, **kw):
                    kw.get("seed", 0))
     set_random_messages(g, O, P, 21)
     errs = [g.blockbp_sweep(1, 0.0)[1] for _ in range(sweeps)]
-    return errs, g.get_messages()
+    rho, ss, e = g.blockbp_expect()
+    return errs, g.get_messages(), (np.array(rho), np.array(ss), e)
 
 
 @pytest.mark.parametrize("case", [
@@ -33,11 +35,12 @@ def _sweeps(kind, ts, streams, graph, sweeps=3, **kw):
 def test_streams_bit_identical(case):
     kind, ts, kw = case
     print(f"case {kind} {kw}", flush=True)
-    e1, m1 = _sweeps(kind, ts, 1, False, **kw)
+    e1, m1, x1 = _sweeps(kind, ts, 1, False, **kw)
     for streams, graph in ((4, False), (2, True), (4, True)):
-        e, m = _sweeps(kind, ts, streams, graph, **kw)
-        print(f"  streams {streams} graph {graph}: {e}", flush=True)
+        e, m, x = _sweeps(kind, ts, streams, graph, **kw)
+        print(f"  streams {streams} graph {graph}: {e} E {x[2]}", flush=True)
         assert e == e1
+        assert np.array_equal(x[0], x1[0]) and np.array_equal(x[1], x1[1]) and x[2] == x1[2]
         for a, b in zip(m1, m):
             for x, y in zip(a, b):
                 assert np.array_equal(x, y)
