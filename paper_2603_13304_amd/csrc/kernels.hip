@@ -128,7 +128,17 @@ __global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc*
   typedef typename GemmCfg<P>::T T;
   constexpr int TK = GemmCfg<P>::TK;
   constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;
-  const GemmDesc* const gp0 = descs + blockIdx.z;
+  // XCD-aware order: the hardware hands consecutive workgroups round-robin
+  // to the chip's 8 XCDs, each with its own L2; renumber them so that every
+  // XCD works through one contiguous range of tiles, whose operand rows and
+  // output lines then meet in the same L2 (partial lines of a scattered
+  // store fill up there before they go to HBM)
+  const unsigned gx = gridDim.x, gy = gridDim.y, nwg = gx * gy * gridDim.z;
+  const unsigned wid = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const unsigned xcd = wid % 8u, per = nwg / 8u, extra = nwg % 8u;
+  const unsigned vid = xcd * per + (xcd < extra ? xcd : extra) + wid / 8u;
+  const unsigned bx = vid % gx, by = (vid / gx) % gy, bz = vid / (gx * gy);
+  const GemmDesc* const gp0 = descs + bz;
   GemmArgs g;
   g.A = gp0->A; g.B = gp0->B; g.C = gp0->C;
   g.M = gp0->M; g.N = gp0->N; g.K = gp0->K;
@@ -136,14 +146,14 @@ __global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc*
   g.opA = gp0->opA; g.opB = gp0->opB;
   g.sc_n = gp0->sc_n; g.sc_nr = gp0->sc_nr; g.sc_conj = gp0->sc_conj;
   g.alpha = gp0->alpha; g.beta = gp0->beta;
-  const int n0 = blockIdx.x * GT_N;
+  const int n0 = bx * GT_N;
   if (n0 >= g.N) return;
   const gptr<const cplx> Ag = to_global(g.A), Bg = to_global(g.B);
   const gptr<cplx> Cg = to_global(g.C);
   __shared__ T As_r[TK][GT_M + PAD], As_i[TK][GT_M + PAD];
   __shared__ T Bs_r[TK][GT_N + PAD], Bs_i[TK][GT_N + PAD];
   // M tiles are grid-strided (the grid's y extent is capped at 65535)
-  for (int m0 = blockIdx.y * GT_M; m0 < g.M; m0 += gridDim.y * GT_M) {
+  for (int m0 = by * GT_M; m0 < g.M; m0 += gy * GT_M) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = SH == 0 ? (wave >> 1) * 32 : (SH == 2 || SH == 3) ? wave * 16 : 0;
   const int wn = SH == 0 ? (wave & 1) * 32 : (SH == 1 || SH == 4) ? wave * 16 : 0;
@@ -314,7 +324,7 @@ __global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc*
     // transposed store: the tile's row and column offsets are formed once,
     // one per thread, and shared through LDS
     __shared__ int64_t sc_ro[GT_M], sc_co[GT_N];
-    const GemmDesc* const gp = descs + blockIdx.z;
+    const GemmDesc* const gp = descs + bz;
     if (tid < GT_M) {
       const int r = m0 + tid;
       sc_ro[tid] = r < g.M ? gemm_sc_offset(gp, 0, g.sc_nr, r) : 0;
