@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc*
   // by one slice per load), their K index, their row / column test and
   // their LDS slot, set once per output tile.
   constexpr int EA = GT_M * TK / 256, EB = GT_N * TK / 256;
-  constexpr bool PF = TK == 16;
+  constexpr bool PF = P != PREC_BF16X3;
   const bool conjA = g.opA == OP_C, conjB = g.opB == OP_C;
   const int64_t stA = g.opA == OP_N ? TK : (int64_t)TK * g.lda;
   const int64_t stB = g.opB == OP_N ? (int64_t)TK * g.ldb : TK;
@@ -245,6 +245,7 @@ __global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc*
     if constexpr (P == PREC_FP64 || P == PREC_FP32) {
 #pragma unroll 2
       for (int kk = 0; kk < TK; kk += 4) {
+        if (k0 + kk >= g.K) break;   // past K the slice holds zeros only
         const int kq = kk + (lane >> 4);
         T ar[IB], ai[IB], br[JB], bi[JB];
 #pragma unroll
