@@ -19,3 +19,22 @@ def test_close_sweep_advances_every_handle_then_reports(tmp_path):
     out = subprocess.run([str(exe)], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout + out.stderr
     assert out.stdout.strip() == "ok"
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="no host C++ compiler")
+def test_plan_compiler_under_address_and_undefined_sanitizers(tmp_path):
+    """The plan compiler and geometry (host C++ only) built with
+    AddressSanitizer and UndefinedBehaviorSanitizer: sweep and expectation
+    plans of the hexagonal blocks N=2, 3, 4 and the 4x4-cell patch, every
+    swallow order, T1 / T2, exact in-block contraction and the stability
+    options, both parities; every reference starts inside its region."""
+    exe = tmp_path / "plan_check"
+    srcs = [os.path.join(ROOT, "tests", "host", "plan_check.cpp"),
+            os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "geometry.cpp")]
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                    "-fno-omit-frame-pointer", "-I", CSRC, *srcs, "-o", str(exe)], check=True)
+    env = dict(os.environ, UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1",
+               ASAN_OPTIONS="detect_leaks=1")
+    out = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=600)
+    assert out.returncode == 0, out.stdout[-4000:] + out.stderr[-4000:]
+    assert out.stdout.strip().endswith("ok")
