@@ -200,23 +200,24 @@ __global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc*
     lB[q] = kk * (GT_N + PAD) + nn;
     pB[q] = Bg + (okB[q] ? (g.opB == OP_N ? (int64_t)kk * g.ldb + c : (int64_t)c * g.ldb + kk) : 0);
   }
+  // Every element is loaded unconditionally (from the operand's first
+  // element when it lies outside), so that all loads of a slice are in
+  // flight together; validity and conjugation are applied when the slice is
+  // written to LDS, after the loads have landed.
   cplx pa[EA], pb[EB];
+  bool va[EA], vb[EB];
   int kload = 0;   // K offset of the next slice to load
   auto fetch = [&]() {
 #pragma unroll
     for (int q = 0; q < EA; ++q) {
-      cplx x = {0.0, 0.0};
-      if (okA[q] && kload + kA[q] < g.K) x = pA[q][0];
-      if (conjA) x.im = -x.im;
-      pa[q] = x;
+      va[q] = okA[q] && kload + kA[q] < g.K;
+      pa[q] = *(va[q] ? pA[q] : Ag);
       pA[q] += stA;
     }
 #pragma unroll
     for (int q = 0; q < EB; ++q) {
-      cplx x = {0.0, 0.0};
-      if (okB[q] && kload + kB[q] < g.K) x = pB[q][0];
-      if (conjB) x.im = -x.im;
-      pb[q] = x;
+      vb[q] = okB[q] && kload + kB[q] < g.K;
+      pb[q] = *(vb[q] ? pB[q] : Bg);
       pB[q] += stB;
     }
     kload += TK;
@@ -230,13 +231,15 @@ __global__ __launch_bounds__(256, GemmOcc<P>::value) void k_gemm(const GemmDesc*
     if constexpr (!PF) fetch();
 #pragma unroll
     for (int q = 0; q < EA; ++q) {
-      Asr[lA[q]] = (T)pa[q].re;
-      Asi[lA[q]] = (T)pa[q].im;
+      const double re = pa[q].re, im = conjA ? -pa[q].im : pa[q].im;
+      Asr[lA[q]] = va[q] ? (T)re : (T)0;
+      Asi[lA[q]] = va[q] ? (T)im : (T)0;
     }
 #pragma unroll
     for (int q = 0; q < EB; ++q) {
-      Bsr[lB[q]] = (T)pb[q].re;
-      Bsi[lB[q]] = (T)pb[q].im;
+      const double re = pb[q].re, im = conjB ? -pb[q].im : pb[q].im;
+      Bsr[lB[q]] = vb[q] ? (T)re : (T)0;
+      Bsi[lB[q]] = vb[q] ? (T)im : (T)0;
     }
     if constexpr (PF) {
       if (k0 + TK < g.K) fetch();
