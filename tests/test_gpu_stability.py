@@ -70,3 +70,25 @@ def test_finite_both_fp64():
     _run("finite", ts, 3, 14, Lx=4, Ly=4, bLx=2, bLy=2, D=2, chi=4, hermitize=True,
          damping=0.25)
 
+
+
+def test_streams_and_graph_bit_identical_with_both_options():
+    """Lane groups on separate streams and graph replay leave the sweep with
+    the stability options bit-identical to one stream, direct launches."""
+    ts = syn.random_unit_cell(2, seed=5)
+    out = []
+    for streams, graph in ((1, False), (4, False), (4, True)):
+        P, desc = problem("infinite", N=2, D=2, chi=8, hermitize=True, damping=0.4)
+        g = pn.PepsNet(desc, ts)
+        g.use_streams(streams)
+        g.use_graph(graph)
+        O = oracle_for(P, ts, 8, 0, 2, 8, 0, None, True, 0.4)
+        set_random_messages(g, O, P, 17)
+        errs = [g.blockbp_sweep(1, 0.0)[1] for _ in range(3)]
+        out.append((errs, g.get_messages()))
+        g.close()
+    for errs, msgs in out[1:]:
+        assert errs == out[0][0]
+        for a, b in zip(out[0][1], msgs):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)

@@ -66,3 +66,19 @@ def test_noalloc_rejects_a_workspace_over_the_limit():
     assert e.value.code == pn.binding.BBP_ENOMEM
     g.blockbp_sweep(1, 0.0)                    # the handle is unaffected
     g.close()
+
+
+def test_noalloc_with_learning_step_and_hermitised_messages():
+    """The no-allocation sweep runs the same plan as blockbp_sweep when the
+    stability options add MPS sums to every update (hermitize, damping)."""
+    kw = dict(N=2, D=2, chi=8, trunc=0, hermitize=True, damping=0.3)
+    ref, na = _pair(kw, seed=31)
+    na.release_workspace()
+    r = ref.blockbp_sweep(3, 0.0)
+    n = na.blockbp_sweep_noalloc(3, 0.0)
+    print("distances", r[1], n[1], flush=True)
+    assert n[0] == r[0] == 3
+    assert abs(n[1] - r[1]) <= TOL
+    assert float(np.max(np.abs(_flat(ref.get_messages()) - _flat(na.get_messages())))) <= TOL
+    ref.close()
+    na.close()
