@@ -773,6 +773,12 @@ struct GroupStreams {
   const hipEvent_t* join = nullptr;
 };
 
+// held while a plan's lane groups are enqueued on the shared auxiliary
+// streams (directly or into a graph capture), so that the work of two host
+// threads never interleaves on them and no capture takes in another
+// thread's launches
+std::mutex g_aux_issue_mu;
+
 // Enqueue every launch of c in list order; with gs, group g goes to stream
 // g mod ns (ns = the streams in use, 0 = `main`), so each lane's ops keep
 // their order.
@@ -805,6 +811,8 @@ int32_t run_launches(hipStream_t stream, Compiled* c, bool graph,
   if (!desc_dev) return fail(BBP_EDEVICE, "launch list without uploaded descriptors");
   if (graph) {
     if (!c->exec) {
+      std::unique_lock<std::mutex> lk(g_aux_issue_mu, std::defer_lock);
+      if (gs && c->ngroups > 1 && gs->n > 1) lk.lock();
       PN_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
       {
         hipError_t e = issue(desc_dev, stream, c, gs);
@@ -829,6 +837,8 @@ int32_t run_launches(hipStream_t stream, Compiled* c, bool graph,
     PN_HIP(hipGraphLaunch(c->exec, stream));
     return BBP_OK;
   }
+  std::unique_lock<std::mutex> lk(g_aux_issue_mu, std::defer_lock);
+  if (gs && c->ngroups > 1 && gs->n > 1) lk.lock();
   hipError_t e = issue(desc_dev, stream, c, gs);
   if (e != hipSuccess) return fail(BBP_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
   return BBP_OK;

@@ -44,3 +44,43 @@ def test_streams_bit_identical(case):
         for a, b in zip(m1, m):
             for x, y in zip(a, b):
                 assert np.array_equal(x, y)
+
+
+def test_two_host_threads_share_the_extra_streams():
+    """Two handles swept at the same time from two host threads (each forking
+    its lane groups onto the device's shared extra streams, one capturing its
+    graph) give the same results as one after the other."""
+    import threading
+
+    ts = syn.simple_update_cell(3, seed=2, steps=5)
+    kw = dict(N=3, D=3, chi=16, trunc=1, seed=7)
+
+    def make(graph):
+        P, desc = problem("infinite", **kw)
+        g = pn.PepsNet(desc, ts)
+        g.use_graph(graph)
+        O = oracle_for(P, ts, kw["chi"], 1, 2, 8, 7)
+        set_random_messages(g, O, P, 23)
+        return g
+
+    def run(g, out, k):
+        out[k] = ([g.blockbp_sweep(1, 0.0)[1] for _ in range(3)], g.get_messages())
+
+    ref = {}
+    for k, graph in enumerate((True, False)):
+        g = make(graph)
+        run(g, ref, k)
+        g.close()
+    hs = [make(True), make(False)]
+    got = {}
+    th = [threading.Thread(target=run, args=(hs[k], got, k)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for k in range(2):
+        assert got[k][0] == ref[k][0]
+        for a, b in zip(ref[k][1], got[k][1]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        hs[k].close()
