@@ -42,12 +42,18 @@ def _fixture():
         return json.load(f)
 
 
-def _run(fx, precision):
+def _run(fx, precision, bench_config=False):
     ts = syn.simple_update_cell(fx["D"], seed=fx["su_seed"], steps=fx["su_steps"], dtau=fx["dtau"])
     desc = pn.binding.make_desc(pn.BBP_KAGOME_INF_HEX, D=fx["D"], chi=fx["chi"], hex_N=fx["N"],
                                 precision=precision, trunc=1, q=fx["q"], p=fx["p"],
                                 seed=fx["sketch_seed"])
     g = pn.PepsNet(desc, ts)
+    if bench_config:
+        # the launch configuration the benchmark times: tuned tiles, the
+        # sweep replayed as a graph, lane groups on four streams
+        g.autotune(None)
+        g.use_graph(True)
+        g.use_streams(4)
     shapes = [g.message_shapes(m) for m in range(g.num_messages())]
     assert [[tuple(s) for s in m] for m in fx["shapes"]] == shapes
     start = syn.random_messages(shapes, fx["message_seed"])
@@ -129,3 +135,18 @@ def test_cfg4_fp32_warm_messages_within_1e5():
     d_e, d_ss = abs(e32 - e64), np.abs(np.array(ss32) - np.array(ss64)).max()
     print(f"warm FP32: |dE/site| {d_e:.3e}, max |d<S.S>| {d_ss:.3e}")
     assert d_e < 1e-5 and d_ss < 1e-5
+
+
+def test_cfg4_bench_launch_configuration_matches_direct_sweep():
+    """The full-size sweep in the benchmark's launch configuration (tuned
+    tiles, graph replay, four streams) gives bit-identical messages,
+    distance, rho_ij and energy to the direct sweep checked against the
+    fixture above."""
+    fx = _fixture()
+    a = _run(fx, pn.BBP_FP64)
+    b = _run(fx, pn.BBP_FP64, bench_config=True)
+    assert a[2] == b[2]
+    for x, y in zip(a[1], b[1]):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v)
+    assert np.array_equal(np.asarray(a[3]), np.asarray(b[3])) and a[5] == b[5]
