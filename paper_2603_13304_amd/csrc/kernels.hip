@@ -486,6 +486,17 @@ __device__ __forceinline__ double svt_rcp(double q) {
   return r;
 }
 
+// 1/sqrt(g) for normal g > 0 from the hardware estimate and two
+// Newton-Raphson steps y <- y + y (1 - g y^2) / 2 (each squares the
+// estimate's relative error): full precision at a fraction of the cost of
+// sqrt followed by an IEEE division
+__device__ __forceinline__ double rsqrt_nr(double g) {
+  double y = __builtin_amdgcn_rsq(g);
+  y = fma(0.5 * y, fma(-g * y, y, 1.0), y);
+  y = fma(0.5 * y, fma(-g * y, y, 1.0), y);
+  return y;
+}
+
 // v of lane l (l uniform over the wave)
 __device__ __forceinline__ double readlane_d(double v, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
@@ -1737,12 +1748,16 @@ __device__ __forceinline__ void jac_pair(const JacStore<NT, NL>& S, int p, int q
   // columns at the rounding floor of the matrix are left alone (their
   // direction is noise, and their squares may be denormal)
   if (a <= floor2 || b <= floor2) return;
-  const double ag = sqrt(gr * gr + gi * gi);
-  if (ag == 0.0 || ag <= tol * sqrt(a * b)) return;
-  const double zeta = (b - a) / (2.0 * ag);
-  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + tt * tt), s = c * tt;
-  const double er = gr / ag, ei = -gi / ag;  // e^{-i phi}
+  // |g|^2 <= tol^2 a b: orthogonal to working precision (|g|^2, a and b are
+  // above the floor, so nothing here under- or overflows)
+  const double g2 = gr * gr + gi * gi;
+  if (g2 == 0.0 || g2 <= (tol * tol) * (a * b)) return;
+  const double rg = rsqrt_nr(g2);               // 1 / |g|
+  const double zeta = (b - a) * (0.5 * rg);
+  const double t1 = fma(zeta, zeta, 1.0);
+  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) * svt_rcp(fabs(zeta) + t1 * rsqrt_nr(t1));
+  const double c = rsqrt_nr(fma(tt, tt, 1.0)), s = c * tt;
+  const double er = gr * rg, ei = -gi * rg;     // e^{-i phi}
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const double yr = y[t].x * er - y[t].y * ei, yi = y[t].x * ei + y[t].y * er;
