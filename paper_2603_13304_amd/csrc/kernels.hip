@@ -1560,7 +1560,8 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
         if (j < kw) {
           const double g = readlane_d(a[j].re, j);   // pivot, diagonal lane j
           const bool ok = !(g <= thr);
-          const double r = ok ? sqrt(g) : 0.0, ir = ok ? 1.0 / r : 0.0;
+          const double y = rsqrt_nr(ok ? g : 1.0);
+          const double ir = ok ? y : 0.0, r = ok ? g * y : 0.0;
           a[j].re *= ir;
           a[j].im *= ir;
           if (lane == j) a[j] = cplx{r, 0.0};   // R's diagonal is the root itself
@@ -1569,8 +1570,8 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
 #pragma unroll
           for (int i = j + 1; i < 16; ++i) {
             const double rr = readlane_d(a[j].re, i), ri = readlane_d(a[j].im, i);
-            a[i].re -= rr * a[j].re + ri * a[j].im;
-            a[i].im -= rr * a[j].im - ri * a[j].re;
+            a[i].re = fma(-rr, a[j].re, fma(-ri, a[j].im, a[i].re));
+            a[i].im = fma(-rr, a[j].im, fma(ri, a[j].re, a[i].im));
           }
         }
       }
