@@ -455,6 +455,7 @@ void compile_ops(const std::vector<OpSource>& srcs, std::vector<char>* blob, Com
             for (int k = 0; k < p.rank; ++k) {
               p.dims[k] = int(op->i[2 + k]);
               p.stride[k] = op->i[18 + k];
+              p.inv[k] = 1.0 / p.dims[k];
               p.total *= p.dims[k];
             }
             mt = std::max(mt, p.total);

@@ -406,12 +406,16 @@ __global__ __launch_bounds__(256) void k_permute(const PermDesc* __restrict__ de
   const PermDesc& p = descs[blockIdx.y];
   const int64_t step = (int64_t)gridDim.x * blockDim.x;
   for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < p.total; o += step) {
+    // mixed-radix split of o by the double reciprocal (exact: o < 2^51, so
+    // (rem + 1/2) / dims[k] stays far enough from an integer for the two
+    // roundings), with no 64-bit integer division
     int64_t rem = o, off = 0;
-    for (int k = p.rank - 1; k >= 0; --k) {
-      int64_t idx = rem % p.dims[k];
-      rem /= p.dims[k];
-      off += idx * p.stride[k];
+    for (int k = p.rank - 1; k > 0; --k) {
+      const int64_t q = (int64_t)floor(((double)rem + 0.5) * p.inv[k]);
+      off += (rem - q * p.dims[k]) * p.stride[k];
+      rem = q;
     }
+    off += rem * p.stride[0];
     cplx v = p.src[off];
     if (p.conj) v.im = -v.im;
     p.dst[o] = v;

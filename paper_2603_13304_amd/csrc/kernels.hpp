@@ -48,6 +48,7 @@ struct PermDesc {
   int64_t total;
   int dims[16];
   int64_t stride[16];
+  double inv[16];   // 1 / dims[k]: the index split without integer division
 };
 
 // Householder QR of the m x n matrix A (row-major, lda) or, with conjT, of
