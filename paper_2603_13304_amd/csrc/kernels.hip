@@ -2994,7 +2994,11 @@ __global__ __launch_bounds__(256) void k_omega(const OmegaDesc* __restrict__ des
   }
 }
 
-// C = alpha * sum_s P_s (see SumDesc); grid (element blocks, items)
+// C = alpha * sum_s P_s (see SumDesc); grid (element blocks, items).  The
+// partials are loaded SUM_BATCH at a time, all in flight together, and added
+// in order s = 0, 1, ... (a loop of single loads would wait out one memory
+// round trip per partial).
+constexpr int SUM_BATCH = 8;
 __global__ __launch_bounds__(256) void k_sum_parts(const SumDesc* __restrict__ descs) {
   const SumDesc d = descs[blockIdx.y];
   const int64_t mn = (int64_t)d.M * d.N;
@@ -3002,10 +3006,18 @@ __global__ __launch_bounds__(256) void k_sum_parts(const SumDesc* __restrict__ d
   const gptr<cplx> C = to_global(d.C);
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < mn; e += (int64_t)gridDim.x * 256) {
     double r = 0.0, i = 0.0;
-    for (int s = 0; s < d.S; ++s) {
-      const cplx v = P[s * mn + e];
-      r += v.re;
-      i += v.im;
+    for (int s0 = 0; s0 < d.S; s0 += SUM_BATCH) {
+      cplx v[SUM_BATCH];
+#pragma unroll
+      for (int t = 0; t < SUM_BATCH; ++t)   // past S: partial 0 again, not added
+        v[t] = P[(s0 + t < d.S ? s0 + t : 0) * mn + e];
+      __builtin_amdgcn_sched_barrier(0);   // keep the batch's loads ahead of its adds
+#pragma unroll
+      for (int t = 0; t < SUM_BATCH; ++t)
+        if (s0 + t < d.S) {
+          r += v[t].re;
+          i += v[t].im;
+        }
     }
     const int64_t row = e / d.N, col = e - row * d.N;
     C[row * d.ldc + col] = cplx{d.alpha.re * r - d.alpha.im * i, d.alpha.re * i + d.alpha.im * r};
