@@ -87,6 +87,10 @@ def parse():
     ap.add_argument("--traffic-out", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"))
     ap.add_argument("--stats-summary", metavar="KERNEL_STATS_CSV",
                     help="only print a per-kernel table of a rocprofv3 --stats CSV and exit")
+    ap.add_argument("--timeline-summary", nargs=4,
+                    metavar=("KERNEL_TRACE_CSV", "LAUNCHES_PER_SWEEP", "TIMED", "TRAILING"),
+                    help="only print how the kernels of the timed sweeps of a traced run overlap "
+                         "(the trace ends with TIMED sweeps, then TRAILING others) and exit")
     return ap.parse_args()
 
 
@@ -497,8 +501,57 @@ def stats_summary(path):
         print(f"| {k} | {n} | {ns / 1e6:.2f} | {ns / n / 1e3:.2f} | {100 * ns / tot:.1f} % |")
 
 
+def timeline_summary(path, per, timed, trailing):
+    """Overlap of the kernels of the timed sweeps in a rocprofv3 kernel trace:
+    the share of the window with at least one and with two or more kernels
+    running, and per kernel the summed duration and the time it ran alone."""
+    import csv
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"].replace("void ", "").split("(")[0].split("<")[0].split("::")[-1]
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), name))
+    rows.sort()
+    sel = rows[len(rows) - per * (timed + trailing):][:per * timed]
+    t0, t1 = sel[0][0], max(e for _, e, _ in sel)
+    ev = sorted([(s, 1, k) for s, _, k in sel] + [(e, -1, k) for _, e, k in sel],
+                key=lambda x: (x[0], x[1]))
+    busy = two = 0
+    cur, last = 0, t0
+    active, alone, total = {}, {}, {}
+    for t, d, k in ev:
+        dt = t - last
+        if cur >= 1:
+            busy += dt
+        if cur >= 2:
+            two += dt
+        if cur == 1:
+            only = next(iter(active))
+            alone[only] = alone.get(only, 0) + dt
+        cur += d
+        active[k] = active.get(k, 0) + d
+        if active[k] == 0:
+            del active[k]
+        last = t
+    for s_, e_, k in sel:
+        total[k] = total.get(k, 0) + e_ - s_
+    w = t1 - t0
+    print(f"{len(sel)} launches in {timed} timed sweeps, window {w / 1e6:.1f} ms "
+          f"({w / 1e6 / timed:.1f} ms per sweep)\n")
+    print(f"- at least one kernel running: {100 * busy / w:.1f} % of the window")
+    print(f"- two or more kernels running: {100 * two / w:.1f} %\n")
+    print("| kernel | summed duration, ms per sweep | running alone, ms per sweep |")
+    print("|---|---|---|")
+    for k, v in sorted(total.items(), key=lambda kv: -kv[1])[:10]:
+        print(f"| {k} | {v / 1e6 / timed:.1f} | {alone.get(k, 0) / 1e6 / timed:.1f} |")
+
+
 def main():
     args = parse()
+    if args.timeline_summary:
+        path, per, timed, trailing = args.timeline_summary
+        timeline_summary(path, int(per), int(timed), int(trailing))
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
