@@ -1564,7 +1564,9 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_b(const CholDesc* __restr
         if (j < kw) {
           const double g = readlane_d(a[j].re, j);   // pivot, diagonal lane j
           const bool ok = !(g <= thr);
-          const double y = rsqrt_nr(ok ? g : 1.0);
+          // taken before the test, which only selects (a rejected pivot's
+          // non-finite 1/sqrt is discarded), to keep the test off the chain
+          const double y = rsqrt_nr(g);
           const double ir = ok ? y : 0.0, r = ok ? g * y : 0.0;
           a[j].re *= ir;
           a[j].im *= ir;
